@@ -1,0 +1,119 @@
+/*
+ * kdt.h -- C ABI of the MI355X (gfx950) left-balanced k-d tree builder.
+ *
+ * The library builds the left-balanced, complete k-d tree of Wald,
+ * "GPU-friendly, Parallel, and (Almost-)In-Place Construction of Left-Balanced
+ * k-d Trees" (arXiv 2211.00120) over N float32 points of dimension k:
+ *
+ *   - the tree is stored in level order, node s has children 2s+1 and 2s+2,
+ *     and only the array order carries the topology (Sec. 1, Sec. 2);
+ *   - it is built by O(log N) iterations over the whole point set, each a
+ *     sort by (subtree tag, coordinate in the split dimension) followed by a
+ *     per-point tag update that fixes every subtree's pivot with the O(1)
+ *     subtree-size and segment-begin formulas (Sec. 3, Sec. 4);
+ *   - the split dimension is either level(s) mod k (round robin, Sec. 2) or
+ *     the widest extent of the subtree's domain, i.e. the scene bounding box
+ *     clipped by all ancestors' planes (split-widest, Sec. 6).
+ *
+ * Equal coordinates are ordered by the points' original indices, which makes
+ * the tree unique (the paper's comparison has no tie-break, Sec. 3.1).
+ *
+ * Conventions for every entry point below:
+ *   - pointers named d_* are device memory of the current HIP device; h_* are
+ *     host memory;
+ *   - points are row-major float32, point i's coordinate d at [i*k + d];
+ *   - work is enqueued asynchronously on `stream` (0 = the null stream); the
+ *     call returns once it is enqueued, without synchronising;
+ *   - argument errors are detected on the host before anything is enqueued;
+ *     no call throws, and no call leaves partial work on the stream when it
+ *     returns an error;
+ *   - the caller owns every buffer it passes in.
+ */
+#ifndef KDT_H
+#define KDT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum kdt_status {
+    KDT_OK = 0,
+    KDT_EINVAL = 1,      /* bad argument (null pointer, k outside 1..4, N too large, workspace too small) */
+    KDT_ENOMEM = 2,      /* the library could not allocate device memory it owns */
+    KDT_EDEVICE = 3,     /* a HIP call failed; kdt_last_error() has its message */
+    KDT_ENONFINITE = 4,  /* device status word: an input coordinate is NaN or +-inf */
+    KDT_EBUSY = 5,       /* server: the request has not finished yet */
+    KDT_ENOTFOUND = 6    /* server: unknown ticket */
+} kdt_status;
+
+/* Split-dimension rule: level(s) mod k (Sec. 2) or widest domain extent
+ * (Sec. 6). */
+typedef enum kdt_dim_mode {
+    KDT_DIM_ROUND_ROBIN = 0,
+    KDT_DIM_WIDEST = 1
+} kdt_dim_mode;
+
+/* Largest supported point count (2^30 - 1): positions and lookback counts
+ * are kept in 30-bit fields. */
+#define KDT_MAX_POINTS 1073741823u
+
+/* Bytes of device workspace kdt_build_ws needs for (n, k, mode); 0 when the
+ * arguments are invalid.  The size depends only on the arguments. */
+size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode);
+
+/*
+ * Build the tree of d_points into caller-provided outputs.
+ *
+ *   d_points   n*k float32, read only; must not overlap any output.
+ *   n, k       point count (0..KDT_MAX_POINTS) and dimension (1..4).
+ *   dim_mode   KDT_DIM_ROUND_ROBIN or KDT_DIM_WIDEST.
+ *   d_tree     nullable; n*k float32: d_tree[s*k + d] = coordinate d of the
+ *              point stored at level-order node s.
+ *   d_perm     nullable; n uint32: original index of the point at node s.
+ *   d_dim      nullable; n uint8: split dimension of node s (round robin:
+ *              level(s) mod k; split-widest: widest extent of s's domain,
+ *              lowest dimension on ties; defined for leaves too).
+ *   d_status   nullable; one uint32 the device sets to KDT_OK or, if any
+ *              input coordinate is NaN or infinite, KDT_ENONFINITE (the
+ *              outputs are then unspecified).
+ *   d_ws       device workspace of at least kdt_workspace_bytes(n,k,mode)
+ *              bytes, 256-byte aligned; contents on entry are ignored.
+ *
+ * Never allocates and never synchronises.  Builds that use different
+ * workspaces may run concurrently on different streams.
+ */
+kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_mode,
+                        float* d_tree, uint32_t* d_perm, uint8_t* d_dim,
+                        uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/*
+ * Build in place: on return (once `stream` has run the work) d_points holds
+ * the tree in level order.  The library keeps one cached workspace per
+ * (device, stream) pair, allocated on first use and grown when needed, so
+ * this entry point may allocate.  Non-finite input is not reported (use
+ * kdt_build_ws with a status word for that).
+ */
+kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode,
+                     hipStream_t stream);
+
+/* Free every workspace cached by kdt_build (synchronises the streams that
+ * used them). */
+void kdt_release_cached(void);
+
+/* Static text for a status code. */
+const char* kdt_status_string(int status);
+
+/* Message of the last KDT_EDEVICE / KDT_EINVAL in the calling thread. */
+const char* kdt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDT_H */

@@ -1,0 +1,454 @@
+// kdt_api.hip -- host driver and C ABI (include/kdt.h) of the k-d tree build.
+//
+// The driver validates arguments, carves the caller's workspace, and
+// enqueues the kernel sequence of one build on the caller's stream:
+//
+//   init, prep, [root dim], k presorts x 4 passes, iteration 0,
+//   iterations 1.. with segmented onesweep passes while a subtree is larger
+//   than one workgroup's tile, then block-local iterations down to L-2.
+//
+// The loop bounds follow the paper's iteration count with the two savings of
+// Sec. 7.1: entries of fixed nodes are dropped from every iteration, and the
+// lowest level needs no iteration of its own (iteration L-2 places the
+// leaves directly, which replaces the final sort by tag of Sec. 5).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "../../include/kdt.h"
+#include "kdt_kernels.h"
+#include "kdt_layout.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+void set_err(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Everything about one build that depends only on (n, k, mode).
+struct Plan {
+    uint32_t n = 0, k = 0;
+    bool widest = false;
+    uint32_t L = 0;            // levels of the tree
+    uint32_t B = 0;            // bits of a rank
+    uint32_t P = 0;            // 8-bit digit passes per level sort
+    uint32_t first_local = 0;  // first iteration run block-locally
+    uint32_t max_tiles = 1;    // look-back words per buffer / 256
+    uint32_t max_hist_segs = 2;
+    // workspace offsets (bytes)
+    size_t o_ctl, o_counters, o_hist_rank, o_hist[2], o_lb[2], o_keys, o_perms, o_ranks, o_rec, o_nodeperm,
+        o_dimnode, total;
+    size_t rec_words;          // words per record buffer
+};
+
+bool level_is_global(const Plan& p, uint32_t l)
+{
+    return l >= 1 && l + 2 <= p.L && l < p.first_local;
+}
+
+Plan make_plan(uint32_t n, uint32_t k, bool widest)
+{
+    using namespace kdt;
+    Plan p;
+    p.n = n;
+    p.k = k;
+    p.widest = widest;
+    p.L = num_levels(n);
+    p.B = rank_bits(n);
+    p.P = (p.B + DIGIT_BITS_HOST - 1) / DIGIT_BITS_HOST;
+    // first iteration whose largest subtree (2W - 1 points) fits a local tile
+    p.first_local = 1;
+    while (p.first_local + 2 <= p.L) {
+        const uint32_t W = 1u << (p.L - p.first_local - 1u);
+        if (2u * W - 1u <= LOCAL_TILE) break;
+        ++p.first_local;
+    }
+    p.max_tiles = n ? ceil_div(n, PRESORT_TILE) : 1u;
+    for (uint32_t l = 1; l + 2 <= p.L; ++l) {
+        if (!level_is_global(p, l)) continue;
+        const Level v = make_level(n, l);
+        const SegTiles t = tiles_level(v, LEVEL_TILE);
+        if (t.tiles > p.max_tiles) p.max_tiles = t.tiles;
+        if (v.nseg * 2u > p.max_hist_segs) p.max_hist_segs = v.nseg * 2u;
+    }
+    const size_t N = n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    p.o_ctl = take(CTL_WORDS * 4);
+    p.o_counters = take(MAX_PASSES * 4);
+    p.o_hist_rank = take((size_t)k * 4 * RADIX_HOST * 4);
+    const size_t hist_bytes = (size_t)p.max_hist_segs * MAX_LEVEL_PASSES * RADIX_HOST * 4;
+    p.o_hist[0] = take(hist_bytes);
+    p.o_hist[1] = take(hist_bytes);
+    const size_t lb_bytes = (size_t)p.max_tiles * RADIX_HOST * 4;
+    p.o_lb[0] = take(lb_bytes);
+    p.o_lb[1] = take(lb_bytes);
+    p.o_keys = take(N * k * 4);
+    p.o_perms = take(N * k * 4);
+    p.o_ranks = take(N * k * 4);
+    p.rec_words = N * k > 2 * N ? N * k : 2 * N;     // also holds the presort's (key, value) ping-pong
+    p.o_rec = take(p.rec_words * 2 * 4);
+    p.o_nodeperm = take(N * 4);
+    p.o_dimnode = take(N);
+    p.total = off;
+    return p;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_err("%s failed: %s", #expr, hipGetErrorString(e_));                         \
+            return KDT_EDEVICE;                                                             \
+        }                                                                                   \
+    } while (0)
+
+kdt_status check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_err("%s launch failed: %s", what, hipGetErrorString(e));
+        return KDT_EDEVICE;
+    }
+    return KDT_OK;
+}
+
+kdt_status validate(const float* pts, uint32_t n, uint32_t k, int mode)
+{
+    if (k < 1 || k > 4) {
+        set_err("k must be in 1..4 (got %u)", k);
+        return KDT_EINVAL;
+    }
+    if (mode != KDT_DIM_ROUND_ROBIN && mode != KDT_DIM_WIDEST) {
+        set_err("dim_mode must be KDT_DIM_ROUND_ROBIN or KDT_DIM_WIDEST (got %d)", mode);
+        return KDT_EINVAL;
+    }
+    if (n > KDT_MAX_POINTS) {
+        set_err("n = %u exceeds KDT_MAX_POINTS", n);
+        return KDT_EINVAL;
+    }
+    if (n > 0 && !pts) {
+        set_err("points is null");
+        return KDT_EINVAL;
+    }
+    return KDT_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb)
+{
+    if (!a || !b || !na || !nb) return false;
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim,
+                         uint32_t* status, char* ws, hipStream_t st)
+{
+    using namespace kdt;
+    const uint32_t n = p.n, k = p.k;
+    const bool widest = p.widest;
+    uint32_t* ctl = (uint32_t*)(ws + p.o_ctl);
+    uint32_t* counters = (uint32_t*)(ws + p.o_counters);
+    uint32_t* hist_rank = (uint32_t*)(ws + p.o_hist_rank);
+    uint32_t* hist[2] = {(uint32_t*)(ws + p.o_hist[0]), (uint32_t*)(ws + p.o_hist[1])};
+    uint32_t* lb[2] = {(uint32_t*)(ws + p.o_lb[0]), (uint32_t*)(ws + p.o_lb[1])};
+    uint32_t* keys = (uint32_t*)(ws + p.o_keys);
+    uint32_t* perms = (uint32_t*)(ws + p.o_perms);
+    uint32_t* ranks = (uint32_t*)(ws + p.o_ranks);
+    uint32_t* recbase = (uint32_t*)(ws + p.o_rec);
+    uint32_t* rec[2] = {recbase, recbase + p.rec_words};
+    uint32_t* nodeperm = perm ? perm : (uint32_t*)(ws + p.o_nodeperm);
+    uint8_t* dimnode = (widest && dim) ? dim : (uint8_t*)(ws + p.o_dimnode);
+
+    if (n == 0) return KDT_OK;
+
+    // Onesweep passes of the build, in order, with their tile counts: the
+    // look-back buffer of pass q is lb[q & 1], cleared by pass q-1 (or init).
+    const uint32_t presort_tiles = ceil_div(n, PRESORT_TILE);
+    uint32_t pass_tiles[MAX_PASSES];
+    uint32_t npass = 0;
+    for (uint32_t d = 0; d < k; ++d)
+        for (int q = 0; q < 4; ++q) pass_tiles[npass++] = presort_tiles;
+    for (uint32_t l = 1; l + 2 <= p.L; ++l)
+        if (level_is_global(p, l)) {
+            const uint32_t t = tiles_level(make_level(n, l), LEVEL_TILE).tiles;
+            for (uint32_t q = 0; q < p.P; ++q) pass_tiles[npass++] = t;
+        }
+    auto next_tiles = [&](uint32_t q) { return q + 1 < npass ? pass_tiles[q + 1] : 0u; };
+
+    const bool level1_global = level_is_global(p, 1);
+    launch_init(ctl, counters, hist_rank, k * 4 * RADIX_HOST, lb[0], pass_tiles[0] * RADIX_HOST,
+                level1_global ? hist[1] : nullptr, 2u * p.P * RADIX_HOST, st);
+    if (kdt_status s = check_launch("init")) return s;
+    launch_prep((int)k, pts, n, keys, hist_rank, ctl, widest, st);
+    if (kdt_status s = check_launch("prep")) return s;
+    if (widest) {
+        launch_root_dim((int)k, ctl, dimnode, st);
+        if (kdt_status s = check_launch("root_dim")) return s;
+    }
+
+    // presort: per dimension, 4 stable digit passes of (key, index)
+    uint32_t q = 0;
+    // (key, index) ping-pong of the presort: four n-word arrays inside the
+    // record region (2 * rec_words >= 4n words), free until iteration 0
+    uint32_t* kv_k[2] = {recbase, recbase + n};
+    uint32_t* kv_v[2] = {recbase + 2 * (size_t)n, recbase + 3 * (size_t)n};
+    for (uint32_t d = 0; d < k; ++d) {
+        for (uint32_t ps = 0; ps < 4; ++ps, ++q) {
+            PresortArgs a{};
+            a.kin = ps == 0 ? keys + (size_t)d * n : kv_k[(ps - 1) & 1];
+            a.vin = ps == 0 ? nullptr : kv_v[(ps - 1) & 1];
+            a.kout = kv_k[ps & 1];
+            a.vout = kv_v[ps & 1];
+            a.hist = hist_rank + (d * 4 + ps) * RADIX_HOST;
+            a.lb = lb[q & 1];
+            a.lb_zero = lb[(q + 1) & 1];
+            a.lb_zero_n = next_tiles(q) * RADIX_HOST;
+            a.counter = counters + q;
+            a.n = n;
+            a.shift = 8 * ps;
+            a.perm_out = perms + (size_t)d * n;
+            a.rank_table = ranks;
+            a.k = k;
+            a.dim = d;
+            a.status = ctl + CTL_STATUS;
+            launch_presort_pass(a, ps == 0, ps == 3, presort_tiles, st);
+            if (kdt_status s = check_launch("presort")) return s;
+        }
+    }
+
+    Outs o{};
+    o.pts = pts;
+    o.tree = tree;
+    o.dim = widest ? nullptr : dim;
+    o.nodeperm = nodeperm;
+    o.dimnode = dimnode;
+    o.perm0 = perms;
+    o.ctl = ctl;
+    o.status = ctl + CTL_STATUS;
+    o.n = n;
+
+    // iteration 0
+    int cur = 0;    // record buffer holding the current iteration's input
+    {
+        Level0Args a{};
+        a.perms = perms;
+        a.rank_table = ranks;
+        a.rout = rec[cur];
+        a.hist_next = (level1_global && !widest) ? hist[1] : nullptr;
+        a.next_passes = p.P;
+        a.o = o;
+        launch_level0((int)k, a, widest, st);
+        if (kdt_status s = check_launch("level0")) return s;
+    }
+
+    // iterations 1 .. L-2
+    for (uint32_t l = 1; l + 2 <= p.L; ++l) {
+        const Level v = make_level(n, l);
+        if (level_is_global(p, l)) {
+            const SegTiles tl = tiles_level(v, LEVEL_TILE);
+            uint32_t* h = hist[l & 1];
+            if (widest) {
+                LevelHistArgs ha{};
+                ha.rin = rec[cur];
+                ha.dimnode = dimnode;
+                ha.hist = h;
+                ha.passes = p.P;
+                ha.v = v;
+                ha.tl = tiles_level(v, HIST_TILE);
+                ha.status = ctl + CTL_STATUS;
+                launch_level_hist((int)k, ha, st);
+                if (kdt_status s = check_launch("level_hist")) return s;
+            }
+            const bool next_global = level_is_global(p, l + 1);
+            const uint32_t next_hist_n = next_global ? 2u * v.nseg * p.P * RADIX_HOST : 0u;
+            for (uint32_t ps = 0; ps < p.P; ++ps, ++q) {
+                const bool last = ps + 1 == p.P;
+                LevelPassArgs a{};
+                a.rin = rec[cur];
+                a.rout = rec[cur ^ 1];
+                a.hist = h;
+                a.passes = p.P;
+                a.pass = ps;
+                a.shift = 8 * ps;
+                a.lb = lb[q & 1];
+                a.lb_zero = lb[(q + 1) & 1];
+                a.lb_zero_n = next_tiles(q) * RADIX_HOST;
+                a.zero2 = (ps == 0 && next_global) ? hist[(l + 1) & 1] : nullptr;
+                a.zero2_n = (ps == 0) ? next_hist_n : 0u;
+                a.counter = counters + q;
+                a.v = v;
+                a.tl = tl;
+                a.dim_rr = l % k;
+                a.hist_next = (last && next_global && !widest) ? hist[(l + 1) & 1] : nullptr;
+                a.next_passes = p.P;
+                a.dim_next_rr = (l + 1) % k;
+                a.o = o;
+                launch_level_pass((int)k, a, last, widest, st);
+                if (kdt_status s = check_launch("level_pass")) return s;
+                cur ^= 1;
+            }
+        } else {
+            LevelLocalArgs a{};
+            a.rin = rec[cur];
+            a.rout = rec[cur ^ 1];
+            a.v = v;
+            const uint32_t big = 2u * v.W - 1u;
+            a.G = LOCAL_TILE / big;
+            if (a.G > v.nseg) a.G = v.nseg;
+            a.group_bits = rank_bits(a.G);
+            a.rank_bits = p.B;
+            a.dim_rr = l % k;
+            a.o = o;
+            launch_level_local((int)k, a, widest, st);
+            if (kdt_status s = check_launch("level_local")) return s;
+            cur ^= 1;
+        }
+    }
+    if (status) {
+        launch_copy_word(status, ctl + CTL_STATUS, st);
+        if (kdt_status s = check_launch("status")) return s;
+    }
+    return KDT_OK;
+}
+
+// Workspaces cached by kdt_build, one per (device, stream).
+struct Cached {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_cache_mu;
+std::map<std::pair<int, hipStream_t>, Cached> g_cache;
+
+}  // namespace
+
+extern "C" {
+
+size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode)
+{
+    if (k < 1 || k > 4 || n > KDT_MAX_POINTS) return 0;
+    if (dim_mode != KDT_DIM_ROUND_ROBIN && dim_mode != KDT_DIM_WIDEST) return 0;
+    return make_plan(n, k, dim_mode == KDT_DIM_WIDEST).total;
+}
+
+kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
+                        uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                        hipStream_t stream)
+{
+    if (kdt_status s = validate(d_points, n, k, dim_mode)) return s;
+    const Plan p = make_plan(n, k, dim_mode == KDT_DIM_WIDEST);
+    if (!d_ws || ws_bytes < p.total) {
+        set_err("workspace of %zu bytes needed (got %zu)", p.total, d_ws ? ws_bytes : (size_t)0);
+        return KDT_EINVAL;
+    }
+    if (((uintptr_t)d_ws) % ALIGN) {
+        set_err("workspace must be %zu-byte aligned", ALIGN);
+        return KDT_EINVAL;
+    }
+    const size_t pb = (size_t)n * k * 4;
+    if (overlaps(d_points, pb, d_tree, pb) || overlaps(d_points, pb, d_perm, (size_t)n * 4) ||
+        overlaps(d_points, pb, d_dim, n) || overlaps(d_points, pb, d_ws, ws_bytes) ||
+        overlaps(d_tree, pb, d_ws, ws_bytes) || overlaps(d_perm, (size_t)n * 4, d_ws, ws_bytes) ||
+        overlaps(d_dim, n, d_ws, ws_bytes) || overlaps(d_status, 4, d_ws, ws_bytes)) {
+        set_err("points, outputs and workspace must not overlap");
+        return KDT_EINVAL;
+    }
+    if (n == 0) {
+        if (d_status) {
+            kdt::launch_set_word(d_status, 0u, stream);
+            return check_launch("status");
+        }
+        return KDT_OK;
+    }
+    return enqueue_build(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, stream);
+}
+
+kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipStream_t stream)
+{
+    if (kdt_status s = validate(d_points, n, k, dim_mode)) return s;
+    if (n == 0) return KDT_OK;
+    const Plan p = make_plan(n, k, dim_mode == KDT_DIM_WIDEST);
+    const size_t pb = align_up((size_t)n * k * 4);
+    const size_t need = p.total + pb;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        Cached& c = g_cache[{dev, stream}];
+        if (c.bytes < need) {
+            if (c.ptr) {
+                HIP_TRY(hipStreamSynchronize(stream));
+                HIP_TRY(hipFree(c.ptr));
+                c.ptr = nullptr;
+                c.bytes = 0;
+            }
+            if (hipMalloc(&c.ptr, need) != hipSuccess) {
+                (void)hipGetLastError();
+                c.ptr = nullptr;
+                set_err("hipMalloc of %zu bytes failed", need);
+                return KDT_ENOMEM;
+            }
+            c.bytes = need;
+        }
+        ws = c.ptr;
+    }
+    // the build reads the points until the last node is placed, so it works
+    // from a copy and writes the tree over the caller's array
+    float* copy = (float*)((char*)ws + p.total);
+    HIP_TRY(hipMemcpyAsync(copy, d_points, (size_t)n * k * 4, hipMemcpyDeviceToDevice, stream));
+    return enqueue_build(p, copy, d_points, nullptr, nullptr, nullptr, (char*)ws, stream);
+}
+
+void kdt_release_cached(void)
+{
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    for (auto& kv : g_cache) {
+        if (!kv.second.ptr) continue;
+        (void)hipSetDevice(kv.first.first);
+        (void)hipStreamSynchronize(kv.first.second);
+        (void)hipFree(kv.second.ptr);
+    }
+    g_cache.clear();
+    (void)hipSetDevice(prev);
+}
+
+const char* kdt_status_string(int status)
+{
+    switch (status) {
+    case KDT_OK: return "ok";
+    case KDT_EINVAL: return "invalid argument";
+    case KDT_ENOMEM: return "out of device memory";
+    case KDT_EDEVICE: return "HIP error";
+    case KDT_ENONFINITE: return "non-finite input coordinate";
+    case KDT_EBUSY: return "request not finished";
+    case KDT_ENOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char* kdt_last_error(void) { return g_err; }
+
+}  // extern "C"

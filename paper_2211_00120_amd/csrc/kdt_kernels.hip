@@ -1,0 +1,734 @@
+// kdt_kernels.hip -- gfx950 kernels of the left-balanced k-d tree build.
+//
+// Data flow of one build (all device-resident):
+//
+//  prep        one read of the points: order-preserving uint32 key per
+//              coordinate (SoA), non-finite flag, scene box (split-widest) and
+//              the digit histograms of every presort pass.
+//  presort     for each dimension d a stable LSD radix sort (4 onesweep passes
+//              over 8-bit digits) of (key_d, index); its output gives the
+//              dense rank of every point in the order (coordinate, index).
+//              Comparing ranks is comparing (coordinate, index), the total
+//              order the build sorts by (Sec. 3.1 plus the index tie-break).
+//  level 0     the presort of the root's dimension already is the iteration-0
+//              sort (all tags are 0), so iteration 0 is only the tag update:
+//              place the root at the pivot ss(1), write the rest compacted.
+//  level l     the live points are grouped by subtree (Obs. 3.2), so the sort
+//              by (tag, coordinate) only has to order each subtree's segment
+//              by the rank of its split dimension: segmented onesweep passes
+//              over the rank digits, with tiles that never straddle a segment
+//              and look-back that stops at the segment's first tile.  The last
+//              pass is fused with the tag update (Sec. 3.2): each point's
+//              sorted position decides pivot / left / right, pivots are placed
+//              at their node, the others are written compacted for the next
+//              iteration (position p - i - [p > pivot]).
+//  deep levels once a whole subtree segment fits in one workgroup, each
+//              workgroup sorts whole segments in LDS and applies the update in
+//              the same kernel (one read and one write per iteration).
+//
+// Records carried through the iterations are the k per-dimension ranks of a
+// point (k uint32, array of structs); the float points are only read by prep,
+// by the placement of fixed nodes and by the split-widest plane lookups.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kdt_device.h"
+#include "kdt_kernels.h"
+#include "kdt_layout.h"
+
+namespace kdt {
+
+// ------------------------------------------------------------------ helpers
+
+
+
+// Bounds guard of every scatter: a position outside its buffer flags an
+// internal error in the status word instead of writing.
+__device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t* status)
+{
+    if (pos < limit) return true;
+    atomicOr(status, KDT_STATUS_INTERNAL);
+    return false;
+}
+
+template <int K, bool WIDEST>
+__device__ __forceinline__ void place(const Outs& o, uint32_t node, uint32_t idx)
+{
+    if (!in_bounds(node, o.n, o.status) || !in_bounds(idx, o.n, o.status)) return;
+    if (o.tree) {
+#pragma unroll
+        for (int d = 0; d < K; ++d) o.tree[(size_t)node * K + d] = o.pts[(size_t)idx * K + d];
+    }
+    o.nodeperm[node] = idx;
+    if (!WIDEST && o.dim) o.dim[node] = (uint8_t)(level_of(node) % (uint32_t)K);
+}
+
+// Split-widest (Sec. 6): the domain of a child of s is the scene box clipped
+// by s's plane and by the plane of every ancestor of s (already fixed).  The
+// pivot of s is the point `pidx`; its split dimension is ds.  Writes the
+// dimension of each existing child into dst[child].
+template <int K>
+__device__ void widest_children(const Outs& o, uint32_t s, uint32_t pidx, uint32_t ds, uint8_t* dst)
+{
+    float lo[K], hi[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+        lo[d] = __uint_as_float(o.ctl[CTL_SCENE_LO + d]);
+        hi[d] = __uint_as_float(o.ctl[CTL_SCENE_HI + d]);
+    }
+    uint32_t c = s;
+    while (c > 0u) {
+        const uint32_t a = (c - 1u) >> 1;
+        const uint32_t da = o.dimnode[a];
+        const float plane = o.pts[(size_t)o.nodeperm[a] * K + da];
+#pragma unroll
+        for (int d = 0; d < K; ++d) {
+            if ((uint32_t)d == da) {
+                if (c == 2u * a + 1u) hi[d] = fminf(hi[d], plane);
+                else lo[d] = fmaxf(lo[d], plane);
+            }
+        }
+        c = a;
+    }
+    const float plane = o.pts[(size_t)pidx * K + ds];
+    const uint32_t cl = 2u * s + 1u, cr = 2u * s + 2u;
+    if (cl < o.n) {
+        float h2[K];
+#pragma unroll
+        for (int d = 0; d < K; ++d) h2[d] = ((uint32_t)d == ds) ? fminf(hi[d], plane) : hi[d];
+        dst[cl] = (uint8_t)widest_dim<K>(lo, h2);
+    }
+    if (cr < o.n) {
+        float l2[K];
+#pragma unroll
+        for (int d = 0; d < K; ++d) l2[d] = ((uint32_t)d == ds) ? fmaxf(lo[d], plane) : lo[d];
+        dst[cr] = (uint8_t)widest_dim<K>(l2, hi);
+    }
+}
+
+// r[d] for a runtime d without dynamic register indexing.
+template <int K>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&r)[K], uint32_t d)
+{
+    uint32_t v = r[0];
+#pragma unroll
+    for (int q = 1; q < K; ++q) v = ((uint32_t)q == d) ? r[q] : v;
+    return v;
+}
+
+template <int K>
+__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ p, size_t i, uint32_t (&r)[K])
+{
+    if constexpr (K == 4) {
+        const uint4 v = reinterpret_cast<const uint4*>(p)[i];
+        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    } else if constexpr (K == 2) {
+        const uint2 v = reinterpret_cast<const uint2*>(p)[i];
+        r[0] = v.x; r[1] = v.y;
+    } else {
+#pragma unroll
+        for (int w = 0; w < K; ++w) r[w] = p[i * K + w];
+    }
+}
+template <int K>
+__device__ __forceinline__ void store_rec(uint32_t* __restrict__ p, size_t i, const uint32_t (&r)[K])
+{
+    if constexpr (K == 4) {
+        reinterpret_cast<uint4*>(p)[i] = make_uint4(r[0], r[1], r[2], r[3]);
+    } else if constexpr (K == 2) {
+        reinterpret_cast<uint2*>(p)[i] = make_uint2(r[0], r[1]);
+    } else {
+#pragma unroll
+        for (int w = 0; w < K; ++w) p[i * K + w] = r[w];
+    }
+}
+
+__device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)
+{
+    if (!p) return;
+    for (uint32_t x = blockIdx.x * BLOCK + threadIdx.x; x < n; x += gridDim.x * BLOCK) p[x] = 0u;
+}
+
+// --------------------------------------------------------------------- init
+
+__global__ void __launch_bounds__(BLOCK) k_init(uint32_t* ctl, uint32_t* counters, uint32_t* z1, uint32_t n1,
+                                                uint32_t* z2, uint32_t n2, uint32_t* z3, uint32_t n3)
+{
+    const uint32_t gid = blockIdx.x * BLOCK + threadIdx.x;
+    if (gid < CTL_WORDS) {
+        uint32_t v = 0u;
+        if (gid >= CTL_BOX_LO && gid < CTL_BOX_LO + 4) v = 0xFFFFFFFFu;   // running minimum
+        ctl[gid] = v;
+    }
+    if (gid < MAX_PASSES) counters[gid] = 0u;
+    zero_range(z1, n1);
+    zero_range(z2, n2);
+    zero_range(z3, n3);
+}
+
+// --------------------------------------------------------------------- prep
+
+// One read of the points: uint32 keys (SoA, keys[d*n + i]), non-finite flag,
+// scene box (as orderable keys) and the 4 digit histograms of every
+// dimension's presort (hist[(d*4 + pass)*256 + digit]).
+template <int K, bool WIDEST>
+__global__ void __launch_bounds__(BLOCK) k_prep(const float* __restrict__ pts, uint32_t n, uint32_t* __restrict__ keys,
+                                                uint32_t* __restrict__ hist, uint32_t* __restrict__ ctl)
+{
+    __shared__ uint32_t sh[K * 4 * RADIX];
+    __shared__ uint32_t s_lo[K], s_hi[K];
+    for (uint32_t x = threadIdx.x; x < K * 4 * RADIX; x += BLOCK) sh[x] = 0u;
+    if (threadIdx.x < K) { s_lo[threadIdx.x] = 0xFFFFFFFFu; s_hi[threadIdx.x] = 0u; }
+    __syncthreads();
+    uint32_t lo[K], hi[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) { lo[d] = 0xFFFFFFFFu; hi[d] = 0u; }
+    bool bad = false;
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+#pragma unroll
+        for (int d = 0; d < K; ++d) {
+            const uint32_t b = __float_as_uint(pts[(size_t)i * K + d]);
+            bad |= nonfinite(b);
+            const uint32_t u = orderable(b);
+            keys[(size_t)d * n + i] = u;
+            if (WIDEST) { lo[d] = min(lo[d], u); hi[d] = max(hi[d], u); }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) atomicAdd(&sh[(d * 4 + p) * RADIX + ((u >> (8 * p)) & 0xFFu)], 1u);
+        }
+    }
+    if (__any(bad) && lane_id() == 0) atomicOr(&ctl[CTL_STATUS], (uint32_t)KDT_STATUS_NONFINITE);
+    if (WIDEST) {
+#pragma unroll
+        for (int d = 0; d < K; ++d) {
+            atomicMin(&s_lo[d], lo[d]);
+            atomicMax(&s_hi[d], hi[d]);
+        }
+    }
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < K * 4 * RADIX; x += BLOCK)
+        if (sh[x]) atomicAdd(&hist[x], sh[x]);
+    if (WIDEST && threadIdx.x < K) {
+        atomicMin(&ctl[CTL_BOX_LO + threadIdx.x], s_lo[threadIdx.x]);
+        atomicMax(&ctl[CTL_BOX_HI + threadIdx.x], s_hi[threadIdx.x]);
+    }
+}
+
+// Split-widest: scene box back to floats, root dimension (Sec. 6).
+template <int K>
+__global__ void k_root_dim(uint32_t* ctl, uint8_t* dimnode)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float lo[K], hi[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+        lo[d] = from_orderable(ctl[CTL_BOX_LO + d]);
+        hi[d] = from_orderable(ctl[CTL_BOX_HI + d]);
+        ctl[CTL_SCENE_LO + d] = __float_as_uint(lo[d]);
+        ctl[CTL_SCENE_HI + d] = __float_as_uint(hi[d]);
+    }
+    const uint32_t d0 = widest_dim<K>(lo, hi);
+    ctl[CTL_DIM0] = d0;
+    dimnode[0] = (uint8_t)d0;
+}
+
+// ------------------------------------------------------------ presort passes
+
+// One stable LSD digit pass of the (key, index) sort of one dimension.
+// FIRST reads the keys of prep and takes the index as value; LAST writes the
+// sorted indices (rank -> index) and scatters each index's rank into the
+// point-major rank table.
+template <bool FIRST, bool LAST>
+__global__ void __launch_bounds__(BLOCK) k_presort_pass(PresortArgs a)
+{
+    constexpr int ITEMS = PRESORT_ITEMS;
+    constexpr uint32_t T = BLOCK * ITEMS;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t wh[NWAVE * RADIX];
+    __shared__ uint32_t dstart[RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t sh[NWAVE];
+    __shared__ uint32_t stage_k[T];
+    __shared__ uint32_t stage_v[T];
+
+    if (threadIdx.x == 0) s_tile = atomicAdd(a.counter, 1u);
+    zero_range(a.lb_zero, a.lb_zero_n);
+    __syncthreads();
+    const uint32_t g = s_tile;
+    const uint32_t start = g * T;
+    const uint32_t cnt = min(T, a.n - start);
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+
+    uint32_t key[ITEMS], val[ITEMS], dig[ITEMS], rnk[ITEMS];
+    bool ok[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+        ok[i] = j < cnt;
+        key[i] = 0u;
+        val[i] = 0u;
+        if (ok[i]) {
+            key[i] = a.kin[start + j];
+            val[i] = FIRST ? start + j : a.vin[start + j];
+        }
+        dig[i] = (key[i] >> a.shift) & 0xFFu;
+    }
+    wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = tile_digit_counts(wh, dstart, sh);
+    const uint32_t dex = block_excl_scan(a.hist[t], sh);
+    const uint32_t ex = lookback(a.lb, g, 0u, t, c, a.status);
+    gbase[t] = dex + ex - dstart[t];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (ok[i]) {
+            const uint32_t dst = dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i];
+            stage_k[dst] = key[i];
+            stage_v[dst] = val[i];
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
+        const uint32_t kk = stage_k[j], vv = stage_v[j];
+        const uint32_t pos = gbase[(kk >> a.shift) & 0xFFu] + j;
+        if (!in_bounds(pos, a.n, a.status) || !in_bounds(vv, a.n, a.status)) continue;
+        if (LAST) {
+            a.perm_out[pos] = vv;
+            a.rank_table[(size_t)vv * a.k + a.dim] = pos;
+        } else {
+            a.kout[pos] = kk;
+            a.vout[pos] = vv;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ level 0
+
+// Iteration 0: every tag is 0 and the presort of the root's dimension is the
+// sorted order, so array position r holds the point of rank r.  The pivot is
+// ss(1) (Sec. 3.2, Sec. 5); the root is placed, the others keep their order
+// and are written compacted (left subtree then right subtree).  With N <= 3
+// the children are leaves and are placed directly.  Optionally accumulates
+// the digit histograms of iteration 1 (round robin).
+template <int K, bool WIDEST>
+__global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
+{
+    __shared__ uint32_t nh[2 * MAX_LEVEL_PASSES * RADIX];
+    const uint32_t P = a.next_passes;
+    const bool acc = a.hist_next != nullptr;
+    if (acc)
+        for (uint32_t x = threadIdx.x; x < 2u * P * RADIX; x += BLOCK) nh[x] = 0u;
+    __syncthreads();
+    const uint32_t n = a.o.n;
+    const uint32_t L = num_levels(n);
+    const uint32_t d0 = WIDEST ? a.o.ctl[CTL_DIM0] : 0u;
+    const uint32_t* perm_d0 = a.perms + (size_t)d0 * n;
+    const uint32_t piv = (L >= 2) ? seg_pivot(make_level(n, 0), 0) : 0u;
+    const uint32_t dn = (K == 1) ? 0u : 1u % (uint32_t)K;
+    for (uint32_t r = blockIdx.x * BLOCK + threadIdx.x; r < n; r += gridDim.x * BLOCK) {
+        const uint32_t idx = perm_d0[r];
+        if (r == piv) {
+            place<K, WIDEST>(a.o, 0u, idx);
+            if (WIDEST && L >= 2) widest_children<K>(a.o, 0u, idx, d0, a.o.dimnode);
+            continue;
+        }
+        if (L == 2) {                       // N = 2 or 3: children are leaves
+            place<K, WIDEST>(a.o, r < piv ? 1u : 2u, idx);
+            continue;
+        }
+        uint32_t rec[K];
+        load_rec<K>(a.rank_table, idx, rec);
+        const uint32_t side = r > piv ? 1u : 0u;
+        store_rec<K>(a.rout, r - side, rec);
+        if (acc) {
+            const uint32_t u = pick<K>(rec, dn);
+            for (uint32_t p = 0; p < P; ++p)
+                atomicAdd(&nh[(side * P + p) * RADIX + ((u >> (8u * p)) & 0xFFu)], 1u);
+        }
+    }
+    if (acc) {
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < 2u * P * RADIX; x += BLOCK)
+            if (nh[x]) atomicAdd(&a.hist_next[x], nh[x]);
+    }
+}
+
+// ------------------------------------------------------ segmented level pass
+
+// Digit histograms of iteration l for split-widest (the split dimension of a
+// subtree is only known once its parent's pivot is fixed).  Blocks cover
+// segment-aligned chunks of the live array.
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_level_hist(LevelHistArgs a)
+{
+    __shared__ uint32_t h[MAX_LEVEL_PASSES * RADIX];
+    const uint32_t P = a.passes;
+    for (uint32_t x = threadIdx.x; x < P * RADIX; x += BLOCK) h[x] = 0u;
+    __syncthreads();
+    uint32_t seg, u;
+    tile_locate(a.tl, blockIdx.x, seg, u);
+    const uint32_t off = tiles_seg_offset(a.tl, seg);
+    const uint32_t sz = tiles_seg_size(a.tl, seg);
+    const uint32_t start = u * a.tl.tile;
+    const uint32_t cnt = min(a.tl.tile, sz - start);
+    const uint32_t d = a.dimnode[a.v.Fl + seg];
+    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
+        const uint32_t r = a.rin[(size_t)(off + start + j) * K + d];
+        for (uint32_t p = 0; p < P; ++p) atomicAdd(&h[p * RADIX + ((r >> (8u * p)) & 0xFFu)], 1u);
+    }
+    __syncthreads();
+    uint32_t* dst = a.hist + (size_t)seg * P * RADIX;
+    for (uint32_t x = threadIdx.x; x < P * RADIX; x += BLOCK)
+        if (h[x]) atomicAdd(&dst[x], h[x]);
+}
+
+// One stable digit pass of the per-segment sort of iteration l, ordering each
+// subtree's points by the rank of its split dimension.  Tiles never straddle
+// a segment; global offsets are segment offset + digit prefix inside the
+// segment (from the histogram) + look-back over the segment's earlier tiles.
+// LAST fuses the tag update of Sec. 3.2 into the scatter.
+template <int K, bool LAST, bool WIDEST>
+__global__ void __launch_bounds__(BLOCK) k_level_pass(LevelPassArgs a)
+{
+    constexpr int ITEMS = LEVEL_ITEMS;
+    constexpr uint32_t T = BLOCK * ITEMS;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t wh[NWAVE * RADIX];
+    __shared__ uint32_t dstart[RADIX];
+    __shared__ uint32_t gbase[RADIX];
+    __shared__ uint32_t sh[NWAVE];
+    __shared__ uint32_t stage[K][T];
+    __shared__ uint32_t nh[LAST ? 2 * MAX_LEVEL_PASSES * RADIX : 1];
+
+    if (threadIdx.x == 0) s_tile = atomicAdd(a.counter, 1u);
+    zero_range(a.lb_zero, a.lb_zero_n);
+    zero_range(a.zero2, a.zero2_n);
+    const uint32_t NP = a.next_passes;
+    const bool acc = LAST && a.hist_next != nullptr;
+    if (acc)
+        for (uint32_t x = threadIdx.x; x < 2u * NP * RADIX; x += BLOCK) nh[x] = 0u;
+    __syncthreads();
+    const uint32_t g = s_tile;
+    uint32_t seg, u;
+    tile_locate(a.tl, g, seg, u);
+    const uint32_t soff = tiles_seg_offset(a.tl, seg);
+    const uint32_t ssz = tiles_seg_size(a.tl, seg);
+    const uint32_t start = u * T;
+    const uint32_t cnt = min(T, ssz - start);
+    const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[a.v.Fl + seg] : a.dim_rr;
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t live = a.v.n - a.v.Fl;
+
+    uint32_t rec[ITEMS][K], dig[ITEMS], rnk[ITEMS];
+    bool ok[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+        ok[i] = j < cnt;
+#pragma unroll
+        for (int q = 0; q < K; ++q) rec[i][q] = 0u;
+        if (ok[i]) load_rec<K>(a.rin, (size_t)soff + start + j, rec[i]);
+        dig[i] = (pick<K>(rec[i], d) >> a.shift) & 0xFFu;
+    }
+    wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = tile_digit_counts(wh, dstart, sh);
+    const uint32_t dex = block_excl_scan(a.hist[((size_t)seg * a.passes + a.pass) * RADIX + t], sh);
+    const uint32_t ex = lookback(a.lb, g, g - u, t, c, a.o.status);
+    gbase[t] = soff + dex + ex - dstart[t];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (ok[i]) {
+            const uint32_t dst = dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i];
+#pragma unroll
+            for (int q = 0; q < K; ++q) stage[q][dst] = rec[i][q];
+        }
+    }
+    __syncthreads();
+    if (!LAST) {
+        for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
+            uint32_t r[K];
+#pragma unroll
+            for (int q = 0; q < K; ++q) r[q] = stage[q][j];
+            const uint32_t pos = gbase[(pick<K>(r, d) >> a.shift) & 0xFFu] + j;
+            if (in_bounds(pos, live, a.o.status)) store_rec<K>(a.rout, pos, r);
+        }
+        return;
+    }
+    // tag update (Sec. 3.2) for subtree s = F(l) + seg: the sorted segment is
+    // [soff, soff + ssz); the pivot is the entry at soff + ss(2s+1).
+    const uint32_t piv = seg_pivot(a.v, seg);
+    const uint32_t s = a.v.Fl + seg;
+    const uint32_t dn = a.dim_next_rr;
+    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
+        uint32_t r[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) r[q] = stage[q][j];
+        const uint32_t pos = gbase[(pick<K>(r, d) >> a.shift) & 0xFFu] + j;
+        if (pos == piv) {
+            if (!in_bounds(r[0], a.o.n, a.o.status)) continue;
+            const uint32_t idx = a.o.perm0[r[0]];
+            place<K, WIDEST>(a.o, s, idx);
+            if (WIDEST) widest_children<K>(a.o, s, idx, d, a.o.dimnode);
+            continue;
+        }
+        const uint32_t side = pos > piv ? 1u : 0u;
+        const uint32_t nxt = pos - seg - side;
+        if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - a.v.nseg, a.o.status)) continue;
+        store_rec<K>(a.rout, nxt, r);
+        if (acc) {
+            const uint32_t v = pick<K>(r, dn);
+            for (uint32_t p = 0; p < NP; ++p)
+                atomicAdd(&nh[(side * NP + p) * RADIX + ((v >> (8u * p)) & 0xFFu)], 1u);
+        }
+    }
+    if (acc) {
+        __syncthreads();
+        uint32_t* dst = a.hist_next + (size_t)(2u * seg) * NP * RADIX;   // children 2seg, 2seg+1 are adjacent
+        for (uint32_t x = threadIdx.x; x < 2u * NP * RADIX; x += BLOCK)
+            if (nh[x]) atomicAdd(&dst[x], nh[x]);
+    }
+}
+
+// --------------------------------------------------------- block-local level
+
+// Iteration l when every subtree segment fits in one workgroup: each
+// workgroup takes G consecutive whole segments, sorts them in LDS by
+// (segment, rank of the segment's split dimension) with a stable LSD radix
+// sort over (key << 12 | slot) items, then applies the tag update and writes
+// the next iteration's records (or, at l = L-2, places pivots and leaves).
+template <int K, bool WIDEST>
+__global__ void __launch_bounds__(BLOCK) k_level_local(LevelLocalArgs a)
+{
+    constexpr int ITEMS = LOCAL_ITEMS;
+    constexpr uint32_t T = BLOCK * ITEMS;
+    __shared__ uint32_t srec[K][T];
+    __shared__ uint64_t sitem[T];
+    __shared__ uint32_t wh[NWAVE * RADIX];
+    __shared__ uint32_t dstart[RADIX];
+    __shared__ uint32_t sh[NWAVE];
+
+    const Level& v = a.v;
+    const uint32_t live = v.n - v.Fl;
+    const uint32_t i0 = blockIdx.x * a.G;
+    const uint32_t i1 = min(i0 + a.G, v.nseg);
+    const uint32_t off0 = seg_offset(v, i0);
+    const uint32_t off1 = (i1 == v.nseg) ? live : seg_offset(v, i1);
+    const uint32_t m = off1 - off0;
+    for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
+        uint32_t r[K];
+        load_rec<K>(a.rin, (size_t)off0 + j, r);
+#pragma unroll
+        for (int q = 0; q < K; ++q) srec[q][j] = r[q];
+    }
+    __syncthreads();
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t B = a.rank_bits;
+    uint64_t it[ITEMS];
+    bool ok[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+        ok[i] = j < m;
+        it[i] = 0u;
+        if (ok[i]) {
+            const uint32_t sl = seg_of_pos(v, off0 + j) - i0;
+            const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[v.Fl + i0 + sl] : a.dim_rr;
+            uint32_t key = srec[0][j];
+#pragma unroll
+            for (int q = 1; q < K; ++q) key = ((uint32_t)q == d) ? srec[q][j] : key;
+            it[i] = ((((uint64_t)sl << B) | key) << 12) | j;
+        }
+    }
+    const uint32_t keybits = B + a.group_bits;
+    for (uint32_t sft = 12; sft < 12 + keybits; sft += DIGIT_BITS) {
+        uint32_t dig[ITEMS], rnk[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(it[i] >> sft) & 0xFFu;
+        wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
+        tile_digit_counts(wh, dstart, sh);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (ok[i]) sitem[dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i]] = it[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+            if (ok[i]) it[i] = sitem[j];
+        }
+        __syncthreads();
+    }
+    const bool last = (v.l + 2u == v.L);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (!ok[i]) continue;
+        const uint32_t q = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+        const uint32_t slot = (uint32_t)(it[i] & 0xFFFu);
+        const uint32_t seg = i0 + (uint32_t)(it[i] >> (12 + B));
+        const uint32_t pos = off0 + q;
+        const uint32_t piv = seg_pivot(v, seg);
+        const uint32_t s = v.Fl + seg;
+        uint32_t r[K];
+#pragma unroll
+        for (int qq = 0; qq < K; ++qq) r[qq] = srec[qq][slot];
+        if (!in_bounds(r[0], a.o.n, a.o.status)) continue;
+        if (pos == piv) {
+            const uint32_t idx = a.o.perm0[r[0]];
+            place<K, WIDEST>(a.o, s, idx);
+            if (WIDEST) {
+                uint32_t ds = a.o.dimnode[s];
+                widest_children<K>(a.o, s, idx, ds, a.o.dimnode);
+            }
+            continue;
+        }
+        const uint32_t side = pos > piv ? 1u : 0u;
+        if (last) {
+            place<K, WIDEST>(a.o, 2u * s + 1u + side, a.o.perm0[r[0]]);
+        } else {
+            const uint32_t nxt = pos - seg - side;
+            if (in_bounds(nxt, live - v.nseg, a.o.status)) store_rec<K>(a.rout, nxt, r);
+        }
+    }
+}
+
+__global__ void k_set_word(uint32_t* dst, uint32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+__global__ void k_copy_word(uint32_t* dst, const uint32_t* src)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+// ------------------------------------------------------------- launchers
+
+void launch_set_word(uint32_t* dst, uint32_t value, hipStream_t st) { k_set_word<<<1, 64, 0, st>>>(dst, value); }
+void launch_copy_word(uint32_t* dst, const uint32_t* src, hipStream_t st) { k_copy_word<<<1, 64, 0, st>>>(dst, src); }
+
+template <int K>
+static void launch_prep_k(const float* pts, uint32_t n, uint32_t* keys, uint32_t* hist, uint32_t* ctl, bool widest,
+                          uint32_t grid, hipStream_t st)
+{
+    if (widest) k_prep<K, true><<<grid, BLOCK, 0, st>>>(pts, n, keys, hist, ctl);
+    else k_prep<K, false><<<grid, BLOCK, 0, st>>>(pts, n, keys, hist, ctl);
+}
+
+void launch_init(uint32_t* ctl, uint32_t* counters, uint32_t* z1, uint32_t n1, uint32_t* z2, uint32_t n2,
+                 uint32_t* z3, uint32_t n3, hipStream_t st)
+{
+    uint32_t m = CTL_WORDS > MAX_PASSES ? CTL_WORDS : MAX_PASSES;
+    uint32_t big = n1 > n2 ? n1 : n2;
+    big = big > n3 ? big : n3;
+    uint32_t grid = ceil_div(m > big ? m : big, BLOCK);
+    if (grid > 2048) grid = 2048;
+    if (grid == 0) grid = 1;
+    k_init<<<grid, BLOCK, 0, st>>>(ctl, counters, z1, n1, z2, n2, z3, n3);
+}
+
+void launch_prep(int k, const float* pts, uint32_t n, uint32_t* keys, uint32_t* hist, uint32_t* ctl, bool widest,
+                 hipStream_t st)
+{
+    uint32_t grid = ceil_div(n, BLOCK * 16u);
+    if (grid > 4096) grid = 4096;
+    if (grid == 0) grid = 1;
+    switch (k) {
+    case 1: launch_prep_k<1>(pts, n, keys, hist, ctl, widest, grid, st); break;
+    case 2: launch_prep_k<2>(pts, n, keys, hist, ctl, widest, grid, st); break;
+    case 3: launch_prep_k<3>(pts, n, keys, hist, ctl, widest, grid, st); break;
+    default: launch_prep_k<4>(pts, n, keys, hist, ctl, widest, grid, st); break;
+    }
+}
+
+void launch_root_dim(int k, uint32_t* ctl, uint8_t* dimnode, hipStream_t st)
+{
+    switch (k) {
+    case 1: k_root_dim<1><<<1, 64, 0, st>>>(ctl, dimnode); break;
+    case 2: k_root_dim<2><<<1, 64, 0, st>>>(ctl, dimnode); break;
+    case 3: k_root_dim<3><<<1, 64, 0, st>>>(ctl, dimnode); break;
+    default: k_root_dim<4><<<1, 64, 0, st>>>(ctl, dimnode); break;
+    }
+}
+
+void launch_presort_pass(const PresortArgs& a, bool first, bool last, uint32_t tiles, hipStream_t st)
+{
+    if (first && last) k_presort_pass<true, true><<<tiles, BLOCK, 0, st>>>(a);
+    else if (first) k_presort_pass<true, false><<<tiles, BLOCK, 0, st>>>(a);
+    else if (last) k_presort_pass<false, true><<<tiles, BLOCK, 0, st>>>(a);
+    else k_presort_pass<false, false><<<tiles, BLOCK, 0, st>>>(a);
+}
+
+template <int K>
+static void level0_k(const Level0Args& a, bool widest, uint32_t grid, hipStream_t st)
+{
+    if (widest) k_level0<K, true><<<grid, BLOCK, 0, st>>>(a);
+    else k_level0<K, false><<<grid, BLOCK, 0, st>>>(a);
+}
+
+void launch_level0(int k, const Level0Args& a, bool widest, hipStream_t st)
+{
+    uint32_t grid = ceil_div(a.o.n, BLOCK * 8u);
+    if (grid > 2048) grid = 2048;
+    if (grid == 0) grid = 1;
+    switch (k) {
+    case 1: level0_k<1>(a, widest, grid, st); break;
+    case 2: level0_k<2>(a, widest, grid, st); break;
+    case 3: level0_k<3>(a, widest, grid, st); break;
+    default: level0_k<4>(a, widest, grid, st); break;
+    }
+}
+
+void launch_level_hist(int k, const LevelHistArgs& a, hipStream_t st)
+{
+    const uint32_t grid = a.tl.tiles;
+    switch (k) {
+    case 1: k_level_hist<1><<<grid, BLOCK, 0, st>>>(a); break;
+    case 2: k_level_hist<2><<<grid, BLOCK, 0, st>>>(a); break;
+    case 3: k_level_hist<3><<<grid, BLOCK, 0, st>>>(a); break;
+    default: k_level_hist<4><<<grid, BLOCK, 0, st>>>(a); break;
+    }
+}
+
+template <int K>
+static void level_pass_k(const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
+{
+    const uint32_t grid = a.tl.tiles;
+    if (last) {
+        if (widest) k_level_pass<K, true, true><<<grid, BLOCK, 0, st>>>(a);
+        else k_level_pass<K, true, false><<<grid, BLOCK, 0, st>>>(a);
+    } else {
+        if (widest) k_level_pass<K, false, true><<<grid, BLOCK, 0, st>>>(a);
+        else k_level_pass<K, false, false><<<grid, BLOCK, 0, st>>>(a);
+    }
+}
+
+void launch_level_pass(int k, const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
+{
+    switch (k) {
+    case 1: level_pass_k<1>(a, last, widest, st); break;
+    case 2: level_pass_k<2>(a, last, widest, st); break;
+    case 3: level_pass_k<3>(a, last, widest, st); break;
+    default: level_pass_k<4>(a, last, widest, st); break;
+    }
+}
+
+template <int K>
+static void level_local_k(const LevelLocalArgs& a, bool widest, uint32_t grid, hipStream_t st)
+{
+    if (widest) k_level_local<K, true><<<grid, BLOCK, 0, st>>>(a);
+    else k_level_local<K, false><<<grid, BLOCK, 0, st>>>(a);
+}
+
+void launch_level_local(int k, const LevelLocalArgs& a, bool widest, hipStream_t st)
+{
+    const uint32_t grid = ceil_div(a.v.nseg, a.G);
+    switch (k) {
+    case 1: level_local_k<1>(a, widest, grid, st); break;
+    case 2: level_local_k<2>(a, widest, grid, st); break;
+    case 3: level_local_k<3>(a, widest, grid, st); break;
+    default: level_local_k<4>(a, widest, grid, st); break;
+    }
+}
+
+}  // namespace kdt

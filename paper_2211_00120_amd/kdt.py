@@ -1,0 +1,133 @@
+"""ctypes binding of the C ABI in include/kdt.h.
+
+Argument marshalling only: every step of the build runs in the gfx950
+kernels of ``libkdt.so``.  PyTorch supplies device memory and the current
+stream.  If the library has not been built, every call raises; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkdt.so")
+
+OK = 0
+EINVAL = 1
+ENOMEM = 2
+EDEVICE = 3
+ENONFINITE = 4
+EBUSY = 5
+ENOTFOUND = 6
+
+ROUND_ROBIN = 0
+WIDEST = 1
+MAX_POINTS = (1 << 30) - 1
+
+_lib = None
+
+_SIGS = {
+    "kdt_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
+    "kdt_build_ws": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "kdt_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                 ctypes.c_void_p]),
+    "kdt_release_cached": (None, []),
+    "kdt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "kdt_last_error": (ctypes.c_char_p, []),
+}
+
+
+class KdtError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({last_error()})")
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().kdt_status_string(int(status)).decode()
+
+
+def last_error() -> str:
+    return lib().kdt_last_error().decode()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def workspace_bytes(n: int, k: int, mode: int = ROUND_ROBIN) -> int:
+    return int(lib().kdt_workspace_bytes(n, k, mode))
+
+
+def _check_points(points):
+    import torch
+    if points.dtype != torch.float32 or points.dim() != 2 or not points.is_contiguous():
+        raise ValueError("points must be a contiguous (N, k) float32 tensor")
+    if not points.is_cuda:
+        raise ValueError("points must live on the GPU")
+
+
+def build_ws(points, mode: int = ROUND_ROBIN, *, tree=None, perm=None, dim=None, status=None,
+             workspace=None, stream=None, want_tree=True, want_perm=True, want_dim=True):
+    """kdt_build_ws over torch tensors.  Missing outputs are allocated (unless
+    want_* is False); returns (tree, perm, dim, status) with status a 1-element
+    int32 device tensor holding KDT_OK or KDT_ENONFINITE."""
+    import torch
+    _check_points(points)
+    n, k = points.shape
+    dev = points.device
+    if tree is None and want_tree:
+        tree = torch.empty((n, k), dtype=torch.float32, device=dev)
+    if perm is None and want_perm:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    if dim is None and want_dim:
+        dim = torch.empty(n, dtype=torch.uint8, device=dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(n, k, mode)
+    if workspace is None:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    rc = lib().kdt_build_ws(_ptr(points), n, k, mode, _ptr(tree), _ptr(perm), _ptr(dim), _ptr(status),
+                            _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream))
+    if rc != OK:
+        raise KdtError(rc, "kdt_build_ws")
+    return tree, perm, dim, status
+
+
+def build(points, mode: int = ROUND_ROBIN, stream=None):
+    """kdt_build: replace `points` by its tree in level order (in place)."""
+    _check_points(points)
+    n, k = points.shape
+    rc = lib().kdt_build(_ptr(points), n, k, mode, _stream(stream))
+    if rc != OK:
+        raise KdtError(rc, "kdt_build")
+    return points
+
+
+def release_cached():
+    lib().kdt_release_cached()

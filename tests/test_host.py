@@ -1,0 +1,96 @@
+"""Host-side tests that need no GPU: the C ABI library loads and exports every
+symbol include/kdt.h declares, argument validation happens on the host
+before anything is enqueued, and the implicit-tree arithmetic the kernels use
+matches direct enumeration of the tree."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2211_00120_amd import kdt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kdt.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(kdt_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = kdt.lib()
+    names = _declared_functions()
+    assert "kdt_build" in names and "kdt_build_ws" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", kdt.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r" T (kdt_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_workspace_bytes():
+    lib = kdt.lib()
+    assert lib.kdt_workspace_bytes(100, 0, 0) == 0
+    assert lib.kdt_workspace_bytes(100, 5, 0) == 0
+    assert lib.kdt_workspace_bytes(100, 3, 7) == 0
+    assert lib.kdt_workspace_bytes(kdt.MAX_POINTS + 1, 3, 0) == 0
+    prev = 0
+    for n in [0, 1, 10, 1000, 10**5, 10**7]:
+        b = lib.kdt_workspace_bytes(n, 3, 0)
+        assert b > 0 and b % 256 == 0 and b >= prev
+        prev = b
+    assert lib.kdt_workspace_bytes(10**6, 4, 1) >= lib.kdt_workspace_bytes(10**6, 4, 0)
+
+
+def test_argument_errors_are_synchronous():
+    lib = kdt.lib()
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x100000)
+    # k out of range, bad mode, too many points, null points, no workspace
+    assert lib.kdt_build_ws(fake, 10, 0, 0, None, None, None, None, ws, 1 << 30, None) == kdt.EINVAL
+    assert lib.kdt_build_ws(fake, 10, 5, 0, None, None, None, None, ws, 1 << 30, None) == kdt.EINVAL
+    assert lib.kdt_build_ws(fake, 10, 3, 2, None, None, None, None, ws, 1 << 30, None) == kdt.EINVAL
+    assert lib.kdt_build_ws(fake, kdt.MAX_POINTS + 1, 3, 0, None, None, None, None, ws, 1 << 30, None) \
+        == kdt.EINVAL
+    assert lib.kdt_build_ws(None, 10, 3, 0, None, None, None, None, ws, 1 << 30, None) == kdt.EINVAL
+    assert lib.kdt_build_ws(fake, 10, 3, 0, None, None, None, None, None, 0, None) == kdt.EINVAL
+    assert "workspace" in kdt.last_error()
+    need = lib.kdt_workspace_bytes(10, 3, 0)
+    assert lib.kdt_build_ws(fake, 10, 3, 0, None, None, None, None, ws, need - 1, None) == kdt.EINVAL
+    # misaligned workspace
+    assert lib.kdt_build_ws(fake, 10, 3, 0, None, None, None, None, ctypes.c_void_p(0x100004), need + 512,
+                            None) == kdt.EINVAL
+    # outputs overlapping the points
+    assert lib.kdt_build_ws(fake, 10, 3, 0, ctypes.c_void_p(0x1000 + 4), None, None, None, ws, need, None) \
+        == kdt.EINVAL
+    assert lib.kdt_build(None, 10, 3, 0, None) == kdt.EINVAL
+    assert lib.kdt_build(fake, 10, 9, 0, None) == kdt.EINVAL
+
+
+def test_status_strings():
+    for code in range(7):
+        assert kdt.status_string(code)
+    assert kdt.status_string(99) == "unknown status"
+
+
+def test_layout_arithmetic_matches_enumeration(tmp_path):
+    src = os.path.join(ROOT, "tests", "host", "layout_check.cpp")
+    inc = os.path.join(ROOT, "paper_2211_00120_amd", "csrc")
+    exe = str(tmp_path / "layout_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", inc, src, "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("ok")
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(kdt, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(kdt, "_lib", None)
+    with pytest.raises(RuntimeError):
+        kdt.lib()

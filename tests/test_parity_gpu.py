@@ -1,0 +1,186 @@
+"""GPU parity: the HIP build through the C ABI against the CPU oracle.
+
+The build is integer/permutation work on float32 inputs, so the bar is bit
+equality of perm, dim and the tree's coordinates with the oracle.  At sizes
+the oracle builds in seconds the comparison is element by element; at the
+full benchmark sizes the oracle's checker verifies the GPU tree at every node
+(k-d order against every ancestor, split rule, permutation), which by the
+uniqueness of the tree under the (coordinate, index) order is the same as
+equality with the oracle's tree.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2211_00120_amd import kdt, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_build(pts, mode):
+    t = torch.from_numpy(np.ascontiguousarray(pts)).to(DEV)
+    tree, perm, dim, status = kdt.build_ws(t, mode)
+    torch.cuda.synchronize()
+    return (tree.cpu().numpy(), perm.cpu().numpy().astype(np.uint32), dim.cpu().numpy(),
+            int(status.item()))
+
+
+def _omode(mode):
+    return oracle.WIDEST if mode == kdt.WIDEST else oracle.RR
+
+
+def _assert_same(pts, mode, label):
+    _say(f"case {label}: n={pts.shape[0]} k={pts.shape[1]} mode={mode}")
+    tree, perm, dim, status = _gpu_build(pts, mode)
+    assert status == kdt.OK, f"{label}: device status {status:#x}"
+    perm_o, dim_o = oracle.build(pts, _omode(mode))
+    bad = np.flatnonzero(perm != perm_o)
+    assert bad.size == 0, f"{label}: perm differs at {bad.size} nodes, first {bad[:5]}"
+    assert np.array_equal(dim, dim_o), f"{label}: dim differs"
+    assert tree.tobytes() == np.ascontiguousarray(pts[perm_o]).tobytes(), f"{label}: tree bytes differ"
+
+
+GENS = {
+    "uniform": lambda n, k, s: workloads.uniform(n, k, s),
+    "grid": lambda n, k, s: workloads.grid(n, k, s, levels=7),
+    "signed": lambda n, k, s: workloads.signed_mix(n, k, s),
+}
+
+SMALL_N = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 15, 16, 17, 31, 32, 33, 63, 64, 100, 127, 128, 129, 255, 256, 257,
+           1000, 1023, 1024, 1025]
+MID_N = [2047, 2048, 2049, 4095, 4096, 4097, 6000, 8191, 8192, 12345, 65535, 65536, 65537, 100003]
+BIG_N = [300000, 1048575, 1048576, 2000001]
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", SMALL_N)
+def test_small_sweep(n, k, mode):
+    gen = ["uniform", "grid", "signed"][(n + k) % 3]
+    _assert_same(GENS[gen](n, k, 1000 + n * 7 + k), mode, f"small-{gen}")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("n", MID_N)
+def test_mid_sweep(n, k, mode):
+    gen = ["uniform", "grid", "signed"][(n + k) % 3]
+    _assert_same(GENS[gen](n, k, 2000 + n + k), mode, f"mid-{gen}")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+@pytest.mark.parametrize("n", BIG_N)
+def test_big_sweep(n, mode):
+    k = 3 if mode == kdt.ROUND_ROBIN else 4
+    gen = "grid" if n % 2 else "uniform"
+    _assert_same(GENS[gen](n, k, 3000 + n), mode, f"big-{gen}")
+
+
+def test_config_small_1024():
+    _assert_same(workloads.cfg_small(1), kdt.ROUND_ROBIN, "cfg-1024")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_identical_points(mode):
+    pts = np.full((5000, 3), 0.25, np.float32)
+    _assert_same(pts, mode, "identical")
+
+
+def test_k1_widest_and_rr_equal():
+    pts = workloads.grid(7777, 1, 5, levels=50)
+    _assert_same(pts, kdt.ROUND_ROBIN, "k1-rr")
+    _assert_same(pts, kdt.WIDEST, "k1-widest")
+
+
+def test_nonfinite_sets_status():
+    pts = workloads.uniform(5000, 3, 8)
+    pts[1234, 1] = np.nan
+    _say("case nonfinite")
+    *_, status = _gpu_build(pts, kdt.ROUND_ROBIN)
+    assert status & kdt.ENONFINITE
+    pts[1234, 1] = np.inf
+    *_, status = _gpu_build(pts, kdt.WIDEST)
+    assert status & kdt.ENONFINITE
+
+
+def test_empty_input():
+    _say("case empty")
+    t = torch.zeros((0, 3), dtype=torch.float32, device=DEV)
+    tree, perm, dim, status = kdt.build_ws(t, kdt.ROUND_ROBIN)
+    torch.cuda.synchronize()
+    assert tree.numel() == 0 and perm.numel() == 0 and int(status.item()) == 0
+
+
+def test_deterministic_repeats():
+    pts = workloads.cfg_mixture(n=400000, seed=2)
+    _say("case repeats")
+    t = torch.from_numpy(pts).to(DEV)
+    ws = torch.empty(kdt.workspace_bytes(*pts.shape, kdt.ROUND_ROBIN), dtype=torch.uint8, device=DEV)
+    ref = None
+    for _ in range(10):
+        tree, perm, dim, status = kdt.build_ws(t, kdt.ROUND_ROBIN, workspace=ws)
+        torch.cuda.synchronize()
+        assert int(status.item()) == 0
+        cur = perm.cpu().numpy()
+        if ref is None:
+            ref = cur
+        assert np.array_equal(cur, ref)
+    perm_o, _ = oracle.build(pts, oracle.RR)
+    assert np.array_equal(ref.astype(np.uint32), perm_o)
+
+
+def test_in_place_build_matches():
+    pts = workloads.uniform(123457, 4, 12)
+    _say("case in-place")
+    t = torch.from_numpy(pts).to(DEV)
+    kdt.build(t, kdt.WIDEST)
+    torch.cuda.synchronize()
+    perm_o, _ = oracle.build(pts, oracle.WIDEST)
+    assert t.cpu().numpy().tobytes() == pts[perm_o].tobytes()
+
+
+def test_optional_outputs():
+    pts = workloads.uniform(50000, 3, 13)
+    _say("case optional outputs")
+    t = torch.from_numpy(pts).to(DEV)
+    perm_o, dim_o = oracle.build(pts, oracle.WIDEST)
+    tree, perm, dim, status = kdt.build_ws(t, kdt.WIDEST, want_tree=False, want_dim=False)
+    torch.cuda.synchronize()
+    assert tree is None and dim is None
+    assert np.array_equal(perm.cpu().numpy().astype(np.uint32), perm_o)
+    tree, perm, dim, status = kdt.build_ws(t, kdt.WIDEST, want_perm=False)
+    torch.cuda.synchronize()
+    assert tree.cpu().numpy().tobytes() == pts[perm_o].tobytes()
+    assert np.array_equal(dim.cpu().numpy(), dim_o)
+
+
+def _check_full(pts, mode, label):
+    _say(f"case {label}: n={pts.shape[0]} k={pts.shape[1]} mode={mode} (checker)")
+    tree, perm, dim, status = _gpu_build(pts, mode)
+    assert status == kdt.OK, f"device status {status:#x}"
+    code, node = oracle.check(pts, perm, dim, _omode(mode))
+    assert code == 0, f"{label}: checker code {code} at node {node}"
+    # the tree's coordinates are the points in perm order
+    samp = np.random.default_rng(0).integers(0, pts.shape[0], 100000)
+    assert np.array_equal(tree[samp], pts[perm[samp]])
+
+
+def test_config_mixture_10m():
+    _check_full(workloads.cfg_mixture(), kdt.ROUND_ROBIN, "cfg-10M-mixture")
+
+
+@pytest.mark.skipif(os.environ.get("KDT_SKIP_100M") == "1", reason="100M case disabled by KDT_SKIP_100M")
+def test_config_cluster_100m_widest():
+    _check_full(workloads.cfg_cluster4d(), kdt.WIDEST, "cfg-100M-widest")
