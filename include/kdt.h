@@ -106,6 +106,27 @@ kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode,
  * used them). */
 void kdt_release_cached(void);
 
+/*
+ * Measurement hook for benchmarks.  While enabled, every kernel a build
+ * enqueues is bracketed by a pair of hipEvents recorded on the build's own
+ * stream, tagged with the kernel's name and its algorithmic byte count (the
+ * bytes the step moves by definition: e.g. a level pass reads and writes
+ * 4k bytes per live point).  Enabling adds two event records per launch.
+ */
+typedef struct kdt_kernel_stat {
+    char name[32];        /* kernel name, e.g. "k_level_pass" */
+    uint64_t launches;    /* launches recorded since the last collect */
+    double total_ms;      /* sum of event-measured durations */
+    double alg_bytes;     /* sum of algorithmic bytes */
+} kdt_kernel_stat;
+
+kdt_status kdt_profile_enable(int on);
+
+/* Wait for the recorded events, write one entry per kernel name (at most
+ * max_entries) into out, clear the records and return the number of entries;
+ * -1 if an event could not be read. */
+int kdt_profile_collect(kdt_kernel_stat* out, int max_entries);
+
 /* Static text for a status code. */
 const char* kdt_status_string(int status);
 

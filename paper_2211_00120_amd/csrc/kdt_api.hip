@@ -18,6 +18,7 @@
 #include <string.h>
 
 #include <map>
+#include <vector>
 #include <mutex>
 #include <utility>
 
@@ -132,6 +133,60 @@ kdt_status check_launch(const char* what)
     return KDT_OK;
 }
 
+// ------------------------------------------------------------ profiling
+// While enabled, every kernel enqueued by a build is bracketed by two
+// hipEvents on the build's stream and tagged with its kind and algorithmic
+// bytes (the bytes the step must move by definition).
+enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_HIST, KIND_PASS, KIND_LOCAL,
+            KIND_STATUS, KIND_COUNT };
+const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass", "k_level0",
+                                            "k_level_hist", "k_level_pass", "k_level_local", "k_word"};
+
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<ProfRec> recs;
+    hipEvent_t take()
+    {
+        if (used == pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+Profiler g_prof;
+
+// Enqueue one kernel through `fn`, with profiling events when enabled.
+template <class F>
+kdt_status run_kernel(hipStream_t st, int kind, double bytes, F&& fn)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool on = g_prof.on;
+    if (on) {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = g_prof.take();
+        b = g_prof.take();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    fn();
+    if (kdt_status s = check_launch(kind_names[kind])) return s;
+    if (on && a && b) {
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        (void)hipEventRecord(b, st);
+        g_prof.recs.push_back({kind, a, b, bytes});
+    }
+    return KDT_OK;
+}
+
 kdt_status validate(const float* pts, uint32_t n, uint32_t k, int mode)
 {
     if (k < 1 || k > 4) {
@@ -197,15 +252,18 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
     auto next_tiles = [&](uint32_t q) { return q + 1 < npass ? pass_tiles[q + 1] : 0u; };
 
     const bool level1_global = level_is_global(p, 1);
-    launch_init(ctl, counters, hist_rank, k * 4 * RADIX_HOST, lb[0], pass_tiles[0] * RADIX_HOST,
-                level1_global ? hist[1] : nullptr, 2u * p.P * RADIX_HOST, st);
-    if (kdt_status s = check_launch("init")) return s;
-    launch_prep((int)k, pts, n, keys, hist_rank, ctl, widest, st);
-    if (kdt_status s = check_launch("prep")) return s;
-    if (widest) {
-        launch_root_dim((int)k, ctl, dimnode, st);
-        if (kdt_status s = check_launch("root_dim")) return s;
-    }
+    const double N = n, K = k;
+    if (kdt_status s = run_kernel(st, KIND_INIT, 4.0 * (pass_tiles[0] + k * 4 + 2 * p.P) * RADIX_HOST, [&] {
+            launch_init(ctl, counters, hist_rank, k * 4 * RADIX_HOST, lb[0], pass_tiles[0] * RADIX_HOST,
+                        level1_global ? hist[1] : nullptr, 2u * p.P * RADIX_HOST, st);
+        }))
+        return s;
+    if (kdt_status s = run_kernel(st, KIND_PREP, N * 8.0 * K,
+                                  [&] { launch_prep((int)k, pts, n, keys, hist_rank, ctl, widest, st); }))
+        return s;
+    if (widest)
+        if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, [&] { launch_root_dim((int)k, ctl, dimnode, st); }))
+            return s;
 
     // presort: per dimension, 4 stable digit passes of (key, index)
     uint32_t q = 0;
@@ -232,8 +290,9 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
             a.k = k;
             a.dim = d;
             a.status = ctl + CTL_STATUS;
-            launch_presort_pass(a, ps == 0, ps == 3, presort_tiles, st);
-            if (kdt_status s = check_launch("presort")) return s;
+            if (kdt_status s = run_kernel(st, KIND_PRESORT, N * (ps == 0 ? 12.0 : 16.0),
+                                          [&] { launch_presort_pass(a, ps == 0, ps == 3, presort_tiles, st); }))
+                return s;
         }
     }
 
@@ -258,8 +317,9 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
         a.hist_next = (level1_global && !widest) ? hist[1] : nullptr;
         a.next_passes = p.P;
         a.o = o;
-        launch_level0((int)k, a, widest, st);
-        if (kdt_status s = check_launch("level0")) return s;
+        if (kdt_status s = run_kernel(st, KIND_LEVEL0, N * (4.0 + 8.0 * K),
+                                      [&] { launch_level0((int)k, a, widest, st); }))
+            return s;
     }
 
     // iterations 1 .. L-2
@@ -277,8 +337,9 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                 ha.v = v;
                 ha.tl = tiles_level(v, HIST_TILE);
                 ha.status = ctl + CTL_STATUS;
-                launch_level_hist((int)k, ha, st);
-                if (kdt_status s = check_launch("level_hist")) return s;
+                if (kdt_status s = run_kernel(st, KIND_HIST, (double)(n - v.Fl) * 4.0 * K,
+                                              [&] { launch_level_hist((int)k, ha, st); }))
+                    return s;
             }
             const bool next_global = level_is_global(p, l + 1);
             const uint32_t next_hist_n = next_global ? 2u * v.nseg * p.P * RADIX_HOST : 0u;
@@ -304,8 +365,9 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                 a.next_passes = p.P;
                 a.dim_next_rr = (l + 1) % k;
                 a.o = o;
-                launch_level_pass((int)k, a, last, widest, st);
-                if (kdt_status s = check_launch("level_pass")) return s;
+                if (kdt_status s = run_kernel(st, KIND_PASS, (double)(n - v.Fl) * 8.0 * K,
+                                              [&] { launch_level_pass((int)k, a, last, widest, st); }))
+                    return s;
                 cur ^= 1;
             }
         } else {
@@ -320,14 +382,16 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
             a.rank_bits = p.B;
             a.dim_rr = l % k;
             a.o = o;
-            launch_level_local((int)k, a, widest, st);
-            if (kdt_status s = check_launch("level_local")) return s;
+            if (kdt_status s = run_kernel(st, KIND_LOCAL, (double)(n - v.Fl) * 8.0 * K,
+                                          [&] { launch_level_local((int)k, a, widest, st); }))
+                return s;
             cur ^= 1;
         }
     }
     if (status) {
-        launch_copy_word(status, ctl + CTL_STATUS, st);
-        if (kdt_status s = check_launch("status")) return s;
+        if (kdt_status s = run_kernel(st, KIND_STATUS, 8.0,
+                                      [&] { launch_copy_word(status, ctl + CTL_STATUS, st); }))
+            return s;
     }
     return KDT_OK;
 }
@@ -450,5 +514,43 @@ const char* kdt_status_string(int status)
 }
 
 const char* kdt_last_error(void) { return g_err; }
+
+kdt_status kdt_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return KDT_OK;
+}
+
+int kdt_profile_collect(kdt_kernel_stat* out, int max_entries)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    kdt_kernel_stat acc[KIND_COUNT];
+    memset(acc, 0, sizeof acc);
+    int rc = 0;
+    for (const ProfRec& r : g_prof.recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            set_err("profiling events could not be read");
+            rc = -1;
+            continue;
+        }
+        acc[r.kind].launches += 1;
+        acc[r.kind].total_ms += ms;
+        acc[r.kind].alg_bytes += r.bytes;
+    }
+    g_prof.recs.clear();
+    g_prof.used = 0;
+    if (rc < 0) return rc;
+    int m = 0;
+    for (int kk = 0; kk < KIND_COUNT && m < max_entries; ++kk) {
+        if (!acc[kk].launches) continue;
+        acc[kk].name[0] = 0;
+        strncpy(acc[kk].name, kind_names[kk], sizeof acc[kk].name - 1);
+        if (out) out[m] = acc[kk];
+        ++m;
+    }
+    return m;
+}
 
 }  // extern "C"

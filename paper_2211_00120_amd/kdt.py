@@ -35,9 +35,16 @@ _SIGS = {
     "kdt_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                  ctypes.c_void_p]),
     "kdt_release_cached": (None, []),
+    "kdt_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "kdt_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "kdt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "kdt_last_error": (ctypes.c_char_p, []),
 }
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
 
 
 class KdtError(RuntimeError):
@@ -131,3 +138,19 @@ def build(points, mode: int = ROUND_ROBIN, stream=None):
 
 def release_cached():
     lib().kdt_release_cached()
+
+
+def profile_enable(on: bool = True):
+    """Bracket every kernel of subsequent builds with hipEvents on the build's
+    stream (kdt_profile_enable)."""
+    lib().kdt_profile_enable(1 if on else 0)
+
+
+def profile_collect():
+    """Per-kernel {launches, total_ms, alg_bytes} recorded since the last call."""
+    arr = (KernelStat * 32)()
+    m = lib().kdt_profile_collect(ctypes.cast(arr, ctypes.c_void_p), 32)
+    if m < 0:
+        raise RuntimeError(f"kdt_profile_collect failed: {last_error()}")
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
+                                   "alg_bytes": float(arr[i].alg_bytes)} for i in range(m)}
