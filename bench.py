@@ -36,7 +36,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_2211_00120_amd/csrc/kdt_kernels.hip", "paper_2211_00120_amd/csrc/kdt_device.h",
+KERNEL_SOURCES = ["paper_2211_00120_amd/csrc/kdt_kernels.hip", "paper_2211_00120_amd/csrc/kdt_tail.hip",
+                  "paper_2211_00120_amd/csrc/kdt_common.h", "paper_2211_00120_amd/csrc/kdt_device.h",
                   "paper_2211_00120_amd/csrc/kdt_layout.h", "paper_2211_00120_amd/csrc/kdt_kernels.h"]
 
 
@@ -119,6 +120,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="before warmup, run one device-to-device copy of this many MiB (a reference kernel "
+                         "of known traffic for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -142,6 +146,14 @@ def main():
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.empty(kdt.workspace_bytes(n, k, mode), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.calibrate_copy_mib:
+        src = torch.ones(args.calibrate_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         kdt.build_ws(d_pts, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws, stream=stream)

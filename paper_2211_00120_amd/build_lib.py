@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kdt_kernels.hip", "kdt_api.hip"]
+SOURCES = ["kdt_kernels.hip", "kdt_tail.hip", "kdt_api.hip"]
 LIB = os.path.join(HERE, "libkdt.so")
 
 HIPCC_FLAGS = [
@@ -23,15 +23,18 @@ HIPCC_FLAGS = [
 ]
 
 
-def build_library(verbose: bool = False) -> str:
+def build_library(verbose: bool = False, out: str = LIB, defines=(), sources_dir: str = CSRC) -> str:
+    """Compile the library; `defines` are extra -D tuning knobs (e.g.
+    "KDT_LEVEL_ITEMS=12"), `out` the path of the shared object."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, *[f"-D{d}" for d in defines], *[os.path.join(sources_dir, s) for s in SOURCES],
+           "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -47,13 +47,14 @@ struct Plan {
     bool widest = false;
     uint32_t L = 0;            // levels of the tree
     uint32_t B = 0;            // bits of a rank
-    uint32_t P = 0;            // 8-bit digit passes per level sort
+    uint32_t P = 0;            // digit passes per level sort
+    uint32_t RB = 8;           // bits per digit of the level sorts
     uint32_t first_local = 0;  // first iteration run block-locally
     uint32_t max_tiles = 1;    // look-back words per buffer / 256
     uint32_t max_hist_segs = 2;
     // workspace offsets (bytes)
     size_t o_ctl, o_counters, o_hist_rank, o_hist[2], o_lb[2], o_keys, o_perms, o_ranks, o_rec, o_nodeperm,
-        o_dimnode, total;
+        o_dimnode, o_box[2], total;
     size_t rec_words;          // words per record buffer
 };
 
@@ -71,12 +72,20 @@ Plan make_plan(uint32_t n, uint32_t k, bool widest)
     p.widest = widest;
     p.L = num_levels(n);
     p.B = rank_bits(n);
-    p.P = (p.B + DIGIT_BITS_HOST - 1) / DIGIT_BITS_HOST;
+    // fewest digit passes over a B-bit rank with 8..10-bit digits, then the
+    // narrowest digit that keeps that pass count
+    {
+        const uint32_t pmin = p.B ? (p.B + 9u) / 10u : 0u;
+        p.RB = 10;
+        for (uint32_t rb = 8; rb <= 10; ++rb)
+            if (p.B == 0 || (p.B + rb - 1u) / rb == pmin) { p.RB = rb; break; }
+        p.P = p.B ? (p.B + p.RB - 1u) / p.RB : 0u;
+    }
     // first iteration whose largest subtree (2W - 1 points) fits a local tile
     p.first_local = 1;
     while (p.first_local + 2 <= p.L) {
         const uint32_t W = 1u << (p.L - p.first_local - 1u);
-        if (2u * W - 1u <= LOCAL_TILE) break;
+        if (2u * W - 1u <= TAIL_CAP) break;
         ++p.first_local;
     }
     p.max_tiles = n ? ceil_div(n, PRESORT_TILE) : 1u;
@@ -97,10 +106,10 @@ Plan make_plan(uint32_t n, uint32_t k, bool widest)
     p.o_ctl = take(CTL_WORDS * 4);
     p.o_counters = take(MAX_PASSES * 4);
     p.o_hist_rank = take((size_t)k * 4 * RADIX_HOST * 4);
-    const size_t hist_bytes = (size_t)p.max_hist_segs * MAX_LEVEL_PASSES * RADIX_HOST * 4;
+    const size_t hist_bytes = (size_t)p.max_hist_segs * (p.P ? p.P : 1u) * (1u << p.RB) * 4;
     p.o_hist[0] = take(hist_bytes);
     p.o_hist[1] = take(hist_bytes);
-    const size_t lb_bytes = (size_t)p.max_tiles * RADIX_HOST * 4;
+    const size_t lb_bytes = (size_t)p.max_tiles * MAX_BINS * 4;
     p.o_lb[0] = take(lb_bytes);
     p.o_lb[1] = take(lb_bytes);
     p.o_keys = take(N * k * 4);
@@ -110,6 +119,11 @@ Plan make_plan(uint32_t n, uint32_t k, bool widest)
     p.o_rec = take(p.rec_words * 2 * 4);
     p.o_nodeperm = take(N * 4);
     p.o_dimnode = take(N);
+    // split-widest domain tables: levels up to the tail's first level
+    const uint32_t box_level = p.L >= 2 ? (p.first_local < p.L - 2 ? p.first_local : p.L - 2) : 0u;
+    const size_t box_bytes = ((size_t)1 << box_level) * 8 * 4;
+    p.o_box[0] = take(box_bytes);
+    p.o_box[1] = take(box_bytes);
     p.total = off;
     return p;
 }
@@ -137,10 +151,10 @@ kdt_status check_launch(const char* what)
 // While enabled, every kernel enqueued by a build is bracketed by two
 // hipEvents on the build's stream and tagged with its kind and algorithmic
 // bytes (the bytes the step must move by definition).
-enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_HIST, KIND_PASS, KIND_LOCAL,
+enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_HIST, KIND_PASS, KIND_TAIL,
             KIND_STATUS, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass", "k_level0",
-                                            "k_level_hist", "k_level_pass", "k_level_local", "k_word"};
+                                            "k_level_hist", "k_level_pass", "k_tail", "k_word"};
 
 struct ProfRec {
     int kind;
@@ -240,48 +254,49 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
     // Onesweep passes of the build, in order, with their tile counts: the
     // look-back buffer of pass q is lb[q & 1], cleared by pass q-1 (or init).
     const uint32_t presort_tiles = ceil_div(n, PRESORT_TILE);
-    uint32_t pass_tiles[MAX_PASSES];
+    // (look-back words a pass uses = its tiles * its digit values)
+    uint32_t pass_words[MAX_PASSES];
     uint32_t npass = 0;
     for (uint32_t d = 0; d < k; ++d)
-        for (int q = 0; q < 4; ++q) pass_tiles[npass++] = presort_tiles;
+        for (int q = 0; q < 4; ++q) pass_words[npass++] = presort_tiles * RADIX_HOST;
     for (uint32_t l = 1; l + 2 <= p.L; ++l)
         if (level_is_global(p, l)) {
             const uint32_t t = tiles_level(make_level(n, l), LEVEL_TILE).tiles;
-            for (uint32_t q = 0; q < p.P; ++q) pass_tiles[npass++] = t;
+            for (uint32_t q = 0; q < p.P; ++q) pass_words[npass++] = t << p.RB;
         }
-    auto next_tiles = [&](uint32_t q) { return q + 1 < npass ? pass_tiles[q + 1] : 0u; };
+    auto next_words = [&](uint32_t q) { return q + 1 < npass ? pass_words[q + 1] : 0u; };
+    const uint32_t NBL = 1u << p.RB;
 
     const bool level1_global = level_is_global(p, 1);
     const double N = n, K = k;
-    if (kdt_status s = run_kernel(st, KIND_INIT, 4.0 * (pass_tiles[0] + k * 4 + 2 * p.P) * RADIX_HOST, [&] {
-            launch_init(ctl, counters, hist_rank, k * 4 * RADIX_HOST, lb[0], pass_tiles[0] * RADIX_HOST,
-                        level1_global ? hist[1] : nullptr, 2u * p.P * RADIX_HOST, st);
+    if (kdt_status s = run_kernel(st, KIND_INIT, 4.0 * (pass_words[0] + (k * 4 + 2 * p.P) * RADIX_HOST), [&] {
+            launch_init(ctl, counters, hist_rank, k * 4 * RADIX_HOST, lb[0], pass_words[0],
+                        level1_global ? hist[1] : nullptr, 2u * p.P * NBL, st);
         }))
         return s;
     if (kdt_status s = run_kernel(st, KIND_PREP, N * 8.0 * K,
                                   [&] { launch_prep((int)k, pts, n, keys, hist_rank, ctl, widest, st); }))
         return s;
     if (widest)
-        if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, [&] { launch_root_dim((int)k, ctl, dimnode, st); }))
+        if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0,
+                                      [&] { launch_root_dim((int)k, ctl, dimnode, (float*)(ws + p.o_box[0]), st); }))
             return s;
 
     // presort: per dimension, 4 stable digit passes of (key, index)
     uint32_t q = 0;
-    // (key, index) ping-pong of the presort: four n-word arrays inside the
+    // (key, index) ping-pong of the presort: two n-pair arrays inside the
     // record region (2 * rec_words >= 4n words), free until iteration 0
-    uint32_t* kv_k[2] = {recbase, recbase + n};
-    uint32_t* kv_v[2] = {recbase + 2 * (size_t)n, recbase + 3 * (size_t)n};
+    uint32_t* kv[2] = {recbase, recbase + 2 * (size_t)n};
     for (uint32_t d = 0; d < k; ++d) {
         for (uint32_t ps = 0; ps < 4; ++ps, ++q) {
             PresortArgs a{};
-            a.kin = ps == 0 ? keys + (size_t)d * n : kv_k[(ps - 1) & 1];
-            a.vin = ps == 0 ? nullptr : kv_v[(ps - 1) & 1];
-            a.kout = kv_k[ps & 1];
-            a.vout = kv_v[ps & 1];
+            a.kin = keys + (size_t)d * n;
+            a.kvin = ps == 0 ? nullptr : kv[(ps - 1) & 1];
+            a.kvout = kv[ps & 1];
             a.hist = hist_rank + (d * 4 + ps) * RADIX_HOST;
             a.lb = lb[q & 1];
             a.lb_zero = lb[(q + 1) & 1];
-            a.lb_zero_n = next_tiles(q) * RADIX_HOST;
+            a.lb_zero_n = next_words(q);
             a.counter = counters + q;
             a.n = n;
             a.shift = 8 * ps;
@@ -305,6 +320,8 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
     o.perm0 = perms;
     o.ctl = ctl;
     o.status = ctl + CTL_STATUS;
+    o.box[0] = (float*)(ws + p.o_box[0]);
+    o.box[1] = (float*)(ws + p.o_box[1]);
     o.n = n;
 
     // iteration 0
@@ -316,6 +333,7 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
         a.rout = rec[cur];
         a.hist_next = (level1_global && !widest) ? hist[1] : nullptr;
         a.next_passes = p.P;
+        a.radix_bits = p.RB;
         a.o = o;
         if (kdt_status s = run_kernel(st, KIND_LEVEL0, N * (4.0 + 8.0 * K),
                                       [&] { launch_level0((int)k, a, widest, st); }))
@@ -334,6 +352,7 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                 ha.dimnode = dimnode;
                 ha.hist = h;
                 ha.passes = p.P;
+                ha.radix_bits = p.RB;
                 ha.v = v;
                 ha.tl = tiles_level(v, HIST_TILE);
                 ha.status = ctl + CTL_STATUS;
@@ -342,7 +361,7 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                     return s;
             }
             const bool next_global = level_is_global(p, l + 1);
-            const uint32_t next_hist_n = next_global ? 2u * v.nseg * p.P * RADIX_HOST : 0u;
+            const uint32_t next_hist_n = next_global ? 2u * v.nseg * p.P * NBL : 0u;
             for (uint32_t ps = 0; ps < p.P; ++ps, ++q) {
                 const bool last = ps + 1 == p.P;
                 LevelPassArgs a{};
@@ -351,10 +370,11 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                 a.hist = h;
                 a.passes = p.P;
                 a.pass = ps;
-                a.shift = 8 * ps;
+                a.shift = p.RB * ps;
+                a.radix_bits = p.RB;
                 a.lb = lb[q & 1];
                 a.lb_zero = lb[(q + 1) & 1];
-                a.lb_zero_n = next_tiles(q) * RADIX_HOST;
+                a.lb_zero_n = next_words(q);
                 a.zero2 = (ps == 0 && next_global) ? hist[(l + 1) & 1] : nullptr;
                 a.zero2_n = (ps == 0) ? next_hist_n : 0u;
                 a.counter = counters + q;
@@ -371,21 +391,21 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                 cur ^= 1;
             }
         } else {
-            LevelLocalArgs a{};
+            // every subtree of iteration l fits one workgroup: the tail runs
+            // iterations l .. L-2 in one launch
+            TailArgs a{};
             a.rin = rec[cur];
-            a.rout = rec[cur ^ 1];
-            a.v = v;
+            a.v0 = v;
             const uint32_t big = 2u * v.W - 1u;
-            a.G = LOCAL_TILE / big;
+            a.G = TAIL_CAP / big;
             if (a.G > v.nseg) a.G = v.nseg;
-            a.group_bits = rank_bits(a.G);
+            if (a.G > 2u) a.G = 2u;
             a.rank_bits = p.B;
-            a.dim_rr = l % k;
             a.o = o;
-            if (kdt_status s = run_kernel(st, KIND_LOCAL, (double)(n - v.Fl) * 8.0 * K,
-                                          [&] { launch_level_local((int)k, a, widest, st); }))
+            if (kdt_status s = run_kernel(st, KIND_TAIL, (double)(n - v.Fl) * 4.0 * K,
+                                          [&] { launch_tail((int)k, a, widest, st); }))
                 return s;
-            cur ^= 1;
+            break;
         }
     }
     if (status) {

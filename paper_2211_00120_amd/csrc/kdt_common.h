@@ -1,0 +1,205 @@
+// kdt_common.h -- device helpers shared by the build kernels: placement of
+// fixed nodes, split-widest child dimensions, record load/store.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kdt_device.h"
+#include "kdt_kernels.h"
+#include "kdt_layout.h"
+
+namespace kdt {
+
+
+
+
+// Bounds guard of every scatter: a position outside its buffer flags an
+// internal error in the status word instead of writing.
+__device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t* status)
+{
+    if (pos < limit) return true;
+    atomicOr(status, KDT_STATUS_INTERNAL);
+    return false;
+}
+
+template <int K, bool WIDEST>
+__device__ __forceinline__ void place(const Outs& o, uint32_t node, uint32_t idx)
+{
+    if (!in_bounds(node, o.n, o.status) || !in_bounds(idx, o.n, o.status)) return;
+    if (o.tree) {
+#pragma unroll
+        for (int d = 0; d < K; ++d) o.tree[(size_t)node * K + d] = o.pts[(size_t)idx * K + d];
+    }
+    o.nodeperm[node] = idx;
+    if (!WIDEST && o.dim) o.dim[node] = (uint8_t)(level_of(node) % (uint32_t)K);
+}
+
+// place() with the point's coordinates already loaded.
+template <int K, bool WIDEST>
+__device__ __forceinline__ void place_pt(const Outs& o, uint32_t node, uint32_t idx, const float4& p)
+{
+    if (!in_bounds(node, o.n, o.status)) return;
+    if (o.tree) {
+        float* t = o.tree + (size_t)node * K;
+        t[0] = p.x;
+        if (K > 1) t[1] = p.y;
+        if (K > 2) t[2] = p.z;
+        if (K > 3) t[3] = p.w;
+    }
+    o.nodeperm[node] = idx;
+    if (!WIDEST && o.dim) o.dim[node] = (uint8_t)(level_of(node) % (uint32_t)K);
+}
+
+template <int K>
+__device__ __forceinline__ float4 load_point(const float* __restrict__ pts, uint32_t idx)
+{
+    const float* p = pts + (size_t)idx * K;
+    if constexpr (K == 4) return *reinterpret_cast<const float4*>(p);
+    else if constexpr (K == 3) return make_float4(p[0], p[1], p[2], 0.f);
+    else if constexpr (K == 2) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        return make_float4(v.x, v.y, 0.f, 0.f);
+    } else return make_float4(p[0], 0.f, 0.f, 0.f);
+}
+
+__device__ __forceinline__ float pickf(const float4& p, uint32_t d)
+{
+    return d == 0u ? p.x : (d == 1u ? p.y : (d == 2u ? p.z : p.w));
+}
+
+// Split-widest (Sec. 6): the domain of a child of subtree s is s's domain
+// clipped by s's plane (left child: hi = plane, right child: lo = plane); the
+// child's split dimension is its domain's widest extent.  s is the i-th
+// subtree of its level, box_cur[i] its domain; the children's domains go to
+// box_next[2i], box_next[2i+1] (when box_next is set) and their dimensions to
+// dimnode.  pidx is the pivot's original index, ds the split dimension of s.
+template <int K>
+__device__ void widest_children(const Outs& o, uint32_t s, uint32_t i, uint32_t pidx, uint32_t ds,
+                                const float* box_cur, float* box_next)
+{
+    float lo[K], hi[K];
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+        lo[d] = box_cur[(size_t)i * 8 + d];
+        hi[d] = box_cur[(size_t)i * 8 + 4 + d];
+    }
+    const float plane = o.pts[(size_t)pidx * K + ds];
+#pragma unroll
+    for (uint32_t c = 0; c < 2u; ++c) {
+        const uint32_t child = 2u * s + 1u + c;
+        if (child >= o.n) continue;
+        float l2[K], h2[K];
+#pragma unroll
+        for (int d = 0; d < K; ++d) {
+            l2[d] = lo[d];
+            h2[d] = hi[d];
+            if ((uint32_t)d == ds) {
+                if (c == 0u) h2[d] = fminf(hi[d], plane);
+                else l2[d] = fmaxf(lo[d], plane);
+            }
+        }
+        o.dimnode[child] = (uint8_t)widest_dim<K>(l2, h2);
+        if (box_next) {
+#pragma unroll
+            for (int d = 0; d < K; ++d) {
+                box_next[(size_t)(2u * i + c) * 8 + d] = l2[d];
+                box_next[(size_t)(2u * i + c) * 8 + 4 + d] = h2[d];
+            }
+        }
+    }
+}
+
+// r[d] for a runtime d without dynamic register indexing.
+template <int K>
+__device__ __forceinline__ uint32_t pick(const uint32_t (&r)[K], uint32_t d)
+{
+    uint32_t v = r[0];
+#pragma unroll
+    for (int q = 1; q < K; ++q) v = ((uint32_t)q == d) ? r[q] : v;
+    return v;
+}
+
+template <int K>
+__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ p, size_t i, uint32_t (&r)[K])
+{
+    if constexpr (K == 4) {
+        const uint4 v = reinterpret_cast<const uint4*>(p)[i];
+        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
+    } else if constexpr (K == 2) {
+        const uint2 v = reinterpret_cast<const uint2*>(p)[i];
+        r[0] = v.x; r[1] = v.y;
+    } else {
+#pragma unroll
+        for (int w = 0; w < K; ++w) r[w] = p[i * K + w];
+    }
+}
+template <int K>
+__device__ __forceinline__ void store_rec(uint32_t* __restrict__ p, size_t i, const uint32_t (&r)[K])
+{
+    if constexpr (K == 4) {
+        reinterpret_cast<uint4*>(p)[i] = make_uint4(r[0], r[1], r[2], r[3]);
+    } else if constexpr (K == 2) {
+        reinterpret_cast<uint2*>(p)[i] = make_uint2(r[0], r[1]);
+    } else {
+#pragma unroll
+        for (int w = 0; w < K; ++w) p[i * K + w] = r[w];
+    }
+}
+
+// Records held in registers as uint4 (k <= 4 ranks; unused words are 0).
+template <int K>
+__device__ __forceinline__ uint4 load_rec4(const uint32_t* __restrict__ p, size_t i)
+{
+    if constexpr (K == 4) {
+        return reinterpret_cast<const uint4*>(p)[i];
+    } else if constexpr (K == 2) {
+        const uint2 v = reinterpret_cast<const uint2*>(p)[i];
+        return make_uint4(v.x, v.y, 0u, 0u);
+    } else if constexpr (K == 3) {
+        return make_uint4(p[i * 3], p[i * 3 + 1], p[i * 3 + 2], 0u);
+    } else {
+        return make_uint4(p[i], 0u, 0u, 0u);
+    }
+}
+template <int K>
+__device__ __forceinline__ void store_rec4(uint32_t* __restrict__ p, size_t i, uint4 r)
+{
+    if constexpr (K == 4) {
+        reinterpret_cast<uint4*>(p)[i] = r;
+    } else if constexpr (K == 2) {
+        reinterpret_cast<uint2*>(p)[i] = make_uint2(r.x, r.y);
+    } else if constexpr (K == 3) {
+        p[i * 3] = r.x;
+        p[i * 3 + 1] = r.y;
+        p[i * 3 + 2] = r.z;
+    } else {
+        p[i] = r.x;
+    }
+}
+__device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t d)
+{
+    return d == 0u ? r.x : (d == 1u ? r.y : (d == 2u ? r.z : r.w));
+}
+
+// Lanes of this wave whose (valid, value) agree with this lane's on the low
+// `bits` bits of value (bits <= 16; one ballot per bit).
+__device__ __forceinline__ uint64_t match_bits(uint32_t value, uint32_t bits, bool valid)
+{
+    uint64_t peers = __ballot(valid);
+    for (uint32_t b = 0; b < bits; ++b) {
+        const bool bit = (value >> b) & 1u;
+        const uint64_t bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+    }
+    return peers;
+}
+
+__device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)
+{
+    if (!p) return;
+    for (uint32_t x = blockIdx.x * BLOCK + threadIdx.x; x < n; x += gridDim.x * BLOCK) p[x] = 0u;
+}
+
+
+}  // namespace kdt

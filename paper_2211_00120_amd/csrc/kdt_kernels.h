@@ -22,14 +22,22 @@ constexpr uint32_t KDT_STATUS_INTERNAL = 0x100; // an internal bound or wait che
 constexpr uint32_t RADIX_HOST = 256;
 constexpr uint32_t DIGIT_BITS_HOST = 8;
 constexpr uint32_t MAX_PASSES = 256;       // onesweep passes per build (tile counters)
-constexpr uint32_t MAX_LEVEL_PASSES = 4;   // 8-bit digit passes over a 30-bit rank
-constexpr int PRESORT_ITEMS = 16;          // presort tile: 256 x 16 (key, index) pairs
-constexpr int LEVEL_ITEMS = 8;             // level tile: 256 x 8 records
-constexpr int LOCAL_ITEMS = 8;             // block-local level: up to 2048 points per workgroup
+constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digit passes over a rank of at most 30 bits (8..10-bit digits)
+constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
+// Tile shapes (items per thread of a 256-thread workgroup); tuning knobs.
+#ifndef KDT_PRESORT_ITEMS
+#define KDT_PRESORT_ITEMS 16
+#endif
+#ifndef KDT_LEVEL_ITEMS
+#define KDT_LEVEL_ITEMS 8
+#endif
+constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;   // presort tile: (key, index) pairs
+constexpr int LEVEL_ITEMS = KDT_LEVEL_ITEMS;       // level tile: records
 constexpr uint32_t PRESORT_TILE = 256u * PRESORT_ITEMS;
 constexpr uint32_t LEVEL_TILE = 256u * LEVEL_ITEMS;
-constexpr uint32_t LOCAL_TILE = 256u * LOCAL_ITEMS;
-constexpr uint32_t HIST_TILE = 8u * LEVEL_TILE;   // chunk of the split-widest histogram kernel
+constexpr uint32_t HIST_TILE = 8u * LEVEL_TILE;
+constexpr int TAIL_ITEMS = 8;                     // subtree tail: up to 2048 points per workgroup
+constexpr uint32_t TAIL_CAP = 256u * TAIL_ITEMS;   // chunk of the split-widest histogram kernel
 
 struct Outs {
     const float* pts;
@@ -40,14 +48,14 @@ struct Outs {
     const uint32_t* perm0;  // rank in dimension 0 -> original index
     const uint32_t* ctl;    // control words (scene box)
     uint32_t* status;       // device status word (ctl + CTL_STATUS)
+    float* box[2];          // split-widest: domain of every live subtree, [level & 1][i*8 + (0..3 lo, 4..7 hi)]
     uint32_t n;
 };
 
 struct PresortArgs {
-    const uint32_t* kin;    // keys (first pass: prep's keys of this dimension)
-    const uint32_t* vin;    // values (unused by the first pass: index)
-    uint32_t* kout;
-    uint32_t* vout;
+    const uint32_t* kin;    // first pass: prep's keys of this dimension (value = index)
+    const uint32_t* kvin;   // later passes: (key, index) pairs, interleaved
+    uint32_t* kvout;
     const uint32_t* hist;   // 256 counts of this pass's digit
     uint32_t* lb;           // look-back words of this pass
     uint32_t* lb_zero;      // look-back words to clear for the next pass
@@ -68,14 +76,16 @@ struct Level0Args {
     uint32_t* rout;              // iteration-1 records
     uint32_t* hist_next;         // nullable: iteration-1 digit histograms (2 segments)
     uint32_t next_passes;
+    uint32_t radix_bits;
     Outs o;
 };
 
 struct LevelHistArgs {
     const uint32_t* rin;
     const uint8_t* dimnode;
-    uint32_t* hist;              // [seg][pass][256]
+    uint32_t* hist;              // [seg][pass][2^radix_bits]
     uint32_t passes;
+    uint32_t radix_bits;
     Level v;
     SegTiles tl;                 // tiling with HIST_TILE capacity
     uint32_t* status;
@@ -84,8 +94,8 @@ struct LevelHistArgs {
 struct LevelPassArgs {
     const uint32_t* rin;
     uint32_t* rout;              // next pass's input, or (last pass) next iteration's records
-    const uint32_t* hist;        // [seg][pass][256] of this iteration
-    uint32_t passes, pass, shift;
+    const uint32_t* hist;        // [seg][pass][2^radix_bits] of this iteration
+    uint32_t passes, pass, shift, radix_bits;
     uint32_t* lb;
     uint32_t* lb_zero;
     uint32_t lb_zero_n;
@@ -101,28 +111,26 @@ struct LevelPassArgs {
     Outs o;
 };
 
-struct LevelLocalArgs {
-    const uint32_t* rin;
-    uint32_t* rout;
-    Level v;
-    uint32_t G;                  // segments per workgroup
-    uint32_t group_bits;         // bits of G-1
+
+struct TailArgs {
+    const uint32_t* rin;         // records of iteration v0.l
+    Level v0;                    // first iteration handled by the tail
+    uint32_t G;                  // level-l0 subtrees per workgroup (1 or 2)
     uint32_t rank_bits;
-    uint32_t dim_rr;
     Outs o;
 };
 
+void launch_tail(int k, const TailArgs& a, bool widest, hipStream_t st);
 void launch_set_word(uint32_t* dst, uint32_t value, hipStream_t st);
 void launch_copy_word(uint32_t* dst, const uint32_t* src, hipStream_t st);
 void launch_init(uint32_t* ctl, uint32_t* counters, uint32_t* z1, uint32_t n1, uint32_t* z2, uint32_t n2,
                  uint32_t* z3, uint32_t n3, hipStream_t st);
 void launch_prep(int k, const float* pts, uint32_t n, uint32_t* keys, uint32_t* hist, uint32_t* ctl, bool widest,
                  hipStream_t st);
-void launch_root_dim(int k, uint32_t* ctl, uint8_t* dimnode, hipStream_t st);
+void launch_root_dim(int k, uint32_t* ctl, uint8_t* dimnode, float* box0, hipStream_t st);
 void launch_presort_pass(const PresortArgs& a, bool first, bool last, uint32_t tiles, hipStream_t st);
 void launch_level0(int k, const Level0Args& a, bool widest, hipStream_t st);
 void launch_level_hist(int k, const LevelHistArgs& a, hipStream_t st);
 void launch_level_pass(int k, const LevelPassArgs& a, bool last, bool widest, hipStream_t st);
-void launch_level_local(int k, const LevelLocalArgs& a, bool widest, hipStream_t st);
 
 }  // namespace kdt

@@ -32,122 +32,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kdt_common.h"
 #include "kdt_device.h"
 #include "kdt_kernels.h"
 #include "kdt_layout.h"
+#include "kdt_sweep.h"
 
 namespace kdt {
-
-// ------------------------------------------------------------------ helpers
-
-
-
-// Bounds guard of every scatter: a position outside its buffer flags an
-// internal error in the status word instead of writing.
-__device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t* status)
-{
-    if (pos < limit) return true;
-    atomicOr(status, KDT_STATUS_INTERNAL);
-    return false;
-}
-
-template <int K, bool WIDEST>
-__device__ __forceinline__ void place(const Outs& o, uint32_t node, uint32_t idx)
-{
-    if (!in_bounds(node, o.n, o.status) || !in_bounds(idx, o.n, o.status)) return;
-    if (o.tree) {
-#pragma unroll
-        for (int d = 0; d < K; ++d) o.tree[(size_t)node * K + d] = o.pts[(size_t)idx * K + d];
-    }
-    o.nodeperm[node] = idx;
-    if (!WIDEST && o.dim) o.dim[node] = (uint8_t)(level_of(node) % (uint32_t)K);
-}
-
-// Split-widest (Sec. 6): the domain of a child of s is the scene box clipped
-// by s's plane and by the plane of every ancestor of s (already fixed).  The
-// pivot of s is the point `pidx`; its split dimension is ds.  Writes the
-// dimension of each existing child into dst[child].
-template <int K>
-__device__ void widest_children(const Outs& o, uint32_t s, uint32_t pidx, uint32_t ds, uint8_t* dst)
-{
-    float lo[K], hi[K];
-#pragma unroll
-    for (int d = 0; d < K; ++d) {
-        lo[d] = __uint_as_float(o.ctl[CTL_SCENE_LO + d]);
-        hi[d] = __uint_as_float(o.ctl[CTL_SCENE_HI + d]);
-    }
-    uint32_t c = s;
-    while (c > 0u) {
-        const uint32_t a = (c - 1u) >> 1;
-        const uint32_t da = o.dimnode[a];
-        const float plane = o.pts[(size_t)o.nodeperm[a] * K + da];
-#pragma unroll
-        for (int d = 0; d < K; ++d) {
-            if ((uint32_t)d == da) {
-                if (c == 2u * a + 1u) hi[d] = fminf(hi[d], plane);
-                else lo[d] = fmaxf(lo[d], plane);
-            }
-        }
-        c = a;
-    }
-    const float plane = o.pts[(size_t)pidx * K + ds];
-    const uint32_t cl = 2u * s + 1u, cr = 2u * s + 2u;
-    if (cl < o.n) {
-        float h2[K];
-#pragma unroll
-        for (int d = 0; d < K; ++d) h2[d] = ((uint32_t)d == ds) ? fminf(hi[d], plane) : hi[d];
-        dst[cl] = (uint8_t)widest_dim<K>(lo, h2);
-    }
-    if (cr < o.n) {
-        float l2[K];
-#pragma unroll
-        for (int d = 0; d < K; ++d) l2[d] = ((uint32_t)d == ds) ? fmaxf(lo[d], plane) : lo[d];
-        dst[cr] = (uint8_t)widest_dim<K>(l2, hi);
-    }
-}
-
-// r[d] for a runtime d without dynamic register indexing.
-template <int K>
-__device__ __forceinline__ uint32_t pick(const uint32_t (&r)[K], uint32_t d)
-{
-    uint32_t v = r[0];
-#pragma unroll
-    for (int q = 1; q < K; ++q) v = ((uint32_t)q == d) ? r[q] : v;
-    return v;
-}
-
-template <int K>
-__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ p, size_t i, uint32_t (&r)[K])
-{
-    if constexpr (K == 4) {
-        const uint4 v = reinterpret_cast<const uint4*>(p)[i];
-        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
-    } else if constexpr (K == 2) {
-        const uint2 v = reinterpret_cast<const uint2*>(p)[i];
-        r[0] = v.x; r[1] = v.y;
-    } else {
-#pragma unroll
-        for (int w = 0; w < K; ++w) r[w] = p[i * K + w];
-    }
-}
-template <int K>
-__device__ __forceinline__ void store_rec(uint32_t* __restrict__ p, size_t i, const uint32_t (&r)[K])
-{
-    if constexpr (K == 4) {
-        reinterpret_cast<uint4*>(p)[i] = make_uint4(r[0], r[1], r[2], r[3]);
-    } else if constexpr (K == 2) {
-        reinterpret_cast<uint2*>(p)[i] = make_uint2(r[0], r[1]);
-    } else {
-#pragma unroll
-        for (int w = 0; w < K; ++w) p[i * K + w] = r[w];
-    }
-}
-
-__device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)
-{
-    if (!p) return;
-    for (uint32_t x = blockIdx.x * BLOCK + threadIdx.x; x < n; x += gridDim.x * BLOCK) p[x] = 0u;
-}
 
 // --------------------------------------------------------------------- init
 
@@ -215,7 +106,7 @@ __global__ void __launch_bounds__(BLOCK) k_prep(const float* __restrict__ pts, u
 
 // Split-widest: scene box back to floats, root dimension (Sec. 6).
 template <int K>
-__global__ void k_root_dim(uint32_t* ctl, uint8_t* dimnode)
+__global__ void k_root_dim(uint32_t* ctl, uint8_t* dimnode, float* box0)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     float lo[K], hi[K];
@@ -229,6 +120,11 @@ __global__ void k_root_dim(uint32_t* ctl, uint8_t* dimnode)
     const uint32_t d0 = widest_dim<K>(lo, hi);
     ctl[CTL_DIM0] = d0;
     dimnode[0] = (uint8_t)d0;
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+        box0[d] = lo[d];
+        box0[4 + d] = hi[d];
+    }
 }
 
 // ------------------------------------------------------------ presort passes
@@ -236,70 +132,57 @@ __global__ void k_root_dim(uint32_t* ctl, uint8_t* dimnode)
 // One stable LSD digit pass of the (key, index) sort of one dimension.
 // FIRST reads the keys of prep and takes the index as value; LAST writes the
 // sorted indices (rank -> index) and scatters each index's rank into the
-// point-major rank table.
+// point-major rank table.  Pairs are stored interleaved (uint2).
 template <bool FIRST, bool LAST>
 __global__ void __launch_bounds__(BLOCK) k_presort_pass(PresortArgs a)
 {
     constexpr int ITEMS = PRESORT_ITEMS;
+    constexpr int RB = 8;
     constexpr uint32_t T = BLOCK * ITEMS;
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t wh[NWAVE * RADIX];
-    __shared__ uint32_t dstart[RADIX];
-    __shared__ uint32_t gbase[RADIX];
-    __shared__ uint32_t sh[NWAVE];
-    __shared__ uint32_t stage_k[T];
-    __shared__ uint32_t stage_v[T];
+    __shared__ SweepSmem<RB, ITEMS, 2> sm;
 
-    if (threadIdx.x == 0) s_tile = atomicAdd(a.counter, 1u);
+    if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
     zero_range(a.lb_zero, a.lb_zero_n);
     __syncthreads();
-    const uint32_t g = s_tile;
+    const uint32_t g = sm.tile;
     const uint32_t start = g * T;
     const uint32_t cnt = min(T, a.n - start);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t shift = a.shift;
 
-    uint32_t key[ITEMS], val[ITEMS], dig[ITEMS], rnk[ITEMS];
+    uint4 rec[ITEMS];
+    uint32_t dig[ITEMS];
     bool ok[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
         ok[i] = j < cnt;
-        key[i] = 0u;
-        val[i] = 0u;
+        rec[i] = make_uint4(0u, 0u, 0u, 0u);
         if (ok[i]) {
-            key[i] = a.kin[start + j];
-            val[i] = FIRST ? start + j : a.vin[start + j];
+            if (FIRST) {
+                rec[i].x = a.kin[start + j];
+                rec[i].y = start + j;
+            } else {
+                const uint2 kv = reinterpret_cast<const uint2*>(a.kvin)[start + j];
+                rec[i].x = kv.x;
+                rec[i].y = kv.y;
+            }
         }
-        dig[i] = (key[i] >> a.shift) & 0xFFu;
+        dig[i] = (rec[i].x >> shift) & 0xFFu;
     }
-    wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
-    const uint32_t t = threadIdx.x;
-    const uint32_t c = tile_digit_counts(wh, dstart, sh);
-    const uint32_t dex = block_excl_scan(a.hist[t], sh);
-    const uint32_t ex = lookback(a.lb, g, 0u, t, c, a.status);
-    gbase[t] = dex + ex - dstart[t];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (ok[i]) {
-            const uint32_t dst = dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i];
-            stage_k[dst] = key[i];
-            stage_v[dst] = val[i];
-        }
-    }
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
-        const uint32_t kk = stage_k[j], vv = stage_v[j];
-        const uint32_t pos = gbase[(kk >> a.shift) & 0xFFu] + j;
-        if (!in_bounds(pos, a.n, a.status) || !in_bounds(vv, a.n, a.status)) continue;
-        if (LAST) {
-            a.perm_out[pos] = vv;
-            a.rank_table[(size_t)vv * a.k + a.dim] = pos;
-        } else {
-            a.kout[pos] = kk;
-            a.vout[pos] = vv;
-        }
-    }
+    const uint32_t n = a.n;
+    sweep_tile<RB, ITEMS, 2>(
+        sm, rec, ok, dig, cnt, a.hist, 0u, a.lb, g, 0u, a.status,
+        [&](const uint4& r) { return (r.x >> shift) & 0xFFu; },
+        [&](uint32_t, uint32_t pos, const uint4& r) {
+            if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
+            if (LAST) {
+                a.perm_out[pos] = r.y;
+                a.rank_table[(size_t)r.y * a.k + a.dim] = pos;
+            } else {
+                reinterpret_cast<uint2*>(a.kvout)[pos] = make_uint2(r.x, r.y);
+            }
+        });
 }
 
 // ------------------------------------------------------------------ level 0
@@ -313,11 +196,13 @@ __global__ void __launch_bounds__(BLOCK) k_presort_pass(PresortArgs a)
 template <int K, bool WIDEST>
 __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
 {
-    __shared__ uint32_t nh[2 * MAX_LEVEL_PASSES * RADIX];
+    __shared__ uint32_t nh[2 * MAX_LEVEL_PASSES * MAX_BINS];
     const uint32_t P = a.next_passes;
+    const uint32_t RBv = a.radix_bits;
+    const uint32_t NB = 1u << RBv;
     const bool acc = a.hist_next != nullptr;
     if (acc)
-        for (uint32_t x = threadIdx.x; x < 2u * P * RADIX; x += BLOCK) nh[x] = 0u;
+        for (uint32_t x = threadIdx.x; x < 2u * P * NB; x += BLOCK) nh[x] = 0u;
     __syncthreads();
     const uint32_t n = a.o.n;
     const uint32_t L = num_levels(n);
@@ -329,7 +214,7 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
         const uint32_t idx = perm_d0[r];
         if (r == piv) {
             place<K, WIDEST>(a.o, 0u, idx);
-            if (WIDEST && L >= 2) widest_children<K>(a.o, 0u, idx, d0, a.o.dimnode);
+            if (WIDEST && L >= 2) widest_children<K>(a.o, 0u, 0u, idx, d0, a.o.box[0], L > 2 ? a.o.box[1] : nullptr);
             continue;
         }
         if (L == 2) {                       // N = 2 or 3: children are leaves
@@ -343,12 +228,12 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
         if (acc) {
             const uint32_t u = pick<K>(rec, dn);
             for (uint32_t p = 0; p < P; ++p)
-                atomicAdd(&nh[(side * P + p) * RADIX + ((u >> (8u * p)) & 0xFFu)], 1u);
+                atomicAdd(&nh[(side * P + p) * NB + ((u >> (RBv * p)) & (NB - 1u))], 1u);
         }
     }
     if (acc) {
         __syncthreads();
-        for (uint32_t x = threadIdx.x; x < 2u * P * RADIX; x += BLOCK)
+        for (uint32_t x = threadIdx.x; x < 2u * P * NB; x += BLOCK)
             if (nh[x]) atomicAdd(&a.hist_next[x], nh[x]);
     }
 }
@@ -361,9 +246,11 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
 template <int K>
 __global__ void __launch_bounds__(BLOCK) k_level_hist(LevelHistArgs a)
 {
-    __shared__ uint32_t h[MAX_LEVEL_PASSES * RADIX];
+    __shared__ uint32_t h[MAX_LEVEL_PASSES * MAX_BINS];
     const uint32_t P = a.passes;
-    for (uint32_t x = threadIdx.x; x < P * RADIX; x += BLOCK) h[x] = 0u;
+    const uint32_t RBv = a.radix_bits;
+    const uint32_t NB = 1u << RBv;
+    for (uint32_t x = threadIdx.x; x < P * NB; x += BLOCK) h[x] = 0u;
     __syncthreads();
     uint32_t seg, u;
     tile_locate(a.tl, blockIdx.x, seg, u);
@@ -374,41 +261,39 @@ __global__ void __launch_bounds__(BLOCK) k_level_hist(LevelHistArgs a)
     const uint32_t d = a.dimnode[a.v.Fl + seg];
     for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
         const uint32_t r = a.rin[(size_t)(off + start + j) * K + d];
-        for (uint32_t p = 0; p < P; ++p) atomicAdd(&h[p * RADIX + ((r >> (8u * p)) & 0xFFu)], 1u);
+        for (uint32_t p = 0; p < P; ++p) atomicAdd(&h[p * NB + ((r >> (RBv * p)) & (NB - 1u))], 1u);
     }
     __syncthreads();
-    uint32_t* dst = a.hist + (size_t)seg * P * RADIX;
-    for (uint32_t x = threadIdx.x; x < P * RADIX; x += BLOCK)
+    uint32_t* dst = a.hist + (size_t)seg * P * NB;
+    for (uint32_t x = threadIdx.x; x < P * NB; x += BLOCK)
         if (h[x]) atomicAdd(&dst[x], h[x]);
 }
 
 // One stable digit pass of the per-segment sort of iteration l, ordering each
-// subtree's points by the rank of its split dimension.  Tiles never straddle
-// a segment; global offsets are segment offset + digit prefix inside the
-// segment (from the histogram) + look-back over the segment's earlier tiles.
-// LAST fuses the tag update of Sec. 3.2 into the scatter.
-template <int K, bool LAST, bool WIDEST>
+// subtree's points by the rank of its split dimension (RB-bit digits).  Tiles
+// never straddle a segment; global offsets are segment offset + digit prefix
+// inside the segment (from the histogram) + look-back over the segment's
+// earlier tiles.  LAST fuses the tag update of Sec. 3.2 into the scatter and,
+// for round robin, accumulates the next iteration's digit histograms.
+template <int K, bool LAST, bool WIDEST, int RB>
 __global__ void __launch_bounds__(BLOCK) k_level_pass(LevelPassArgs a)
 {
     constexpr int ITEMS = LEVEL_ITEMS;
     constexpr uint32_t T = BLOCK * ITEMS;
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t wh[NWAVE * RADIX];
-    __shared__ uint32_t dstart[RADIX];
-    __shared__ uint32_t gbase[RADIX];
-    __shared__ uint32_t sh[NWAVE];
-    __shared__ uint32_t stage[K][T];
-    __shared__ uint32_t nh[LAST ? 2 * MAX_LEVEL_PASSES * RADIX : 1];
+    constexpr uint32_t NB = 1u << RB;
+    constexpr uint32_t MASK = NB - 1u;
+    __shared__ SweepSmem<RB, ITEMS, K> sm;
+    __shared__ uint32_t nh[LAST ? 2 * MAX_LEVEL_PASSES * NB : 1];
 
-    if (threadIdx.x == 0) s_tile = atomicAdd(a.counter, 1u);
+    if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
     zero_range(a.lb_zero, a.lb_zero_n);
     zero_range(a.zero2, a.zero2_n);
     const uint32_t NP = a.next_passes;
     const bool acc = LAST && a.hist_next != nullptr;
     if (acc)
-        for (uint32_t x = threadIdx.x; x < 2u * NP * RADIX; x += BLOCK) nh[x] = 0u;
+        for (uint32_t x = threadIdx.x; x < 2u * NP * NB; x += BLOCK) nh[x] = 0u;
     __syncthreads();
-    const uint32_t g = s_tile;
+    const uint32_t g = sm.tile;
     uint32_t seg, u;
     tile_locate(a.tl, g, seg, u);
     const uint32_t soff = tiles_seg_offset(a.tl, seg);
@@ -418,42 +303,25 @@ __global__ void __launch_bounds__(BLOCK) k_level_pass(LevelPassArgs a)
     const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[a.v.Fl + seg] : a.dim_rr;
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint32_t live = a.v.n - a.v.Fl;
+    const uint32_t shift = a.shift;
 
-    uint32_t rec[ITEMS][K], dig[ITEMS], rnk[ITEMS];
+    uint4 rec[ITEMS];
+    uint32_t dig[ITEMS];
     bool ok[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
         ok[i] = j < cnt;
-#pragma unroll
-        for (int q = 0; q < K; ++q) rec[i][q] = 0u;
-        if (ok[i]) load_rec<K>(a.rin, (size_t)soff + start + j, rec[i]);
-        dig[i] = (pick<K>(rec[i], d) >> a.shift) & 0xFFu;
+        rec[i] = ok[i] ? load_rec4<K>(a.rin, (size_t)soff + start + j) : make_uint4(0u, 0u, 0u, 0u);
+        dig[i] = (pick4(rec[i], d) >> shift) & MASK;
     }
-    wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
-    const uint32_t t = threadIdx.x;
-    const uint32_t c = tile_digit_counts(wh, dstart, sh);
-    const uint32_t dex = block_excl_scan(a.hist[((size_t)seg * a.passes + a.pass) * RADIX + t], sh);
-    const uint32_t ex = lookback(a.lb, g, g - u, t, c, a.o.status);
-    gbase[t] = soff + dex + ex - dstart[t];
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (ok[i]) {
-            const uint32_t dst = dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i];
-#pragma unroll
-            for (int q = 0; q < K; ++q) stage[q][dst] = rec[i][q];
-        }
-    }
-    __syncthreads();
+    const uint32_t* seg_hist = a.hist + ((size_t)seg * a.passes + a.pass) * NB;
+    auto digit_of = [&](const uint4& r) { return (pick4(r, d) >> shift) & MASK; };
     if (!LAST) {
-        for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
-            uint32_t r[K];
-#pragma unroll
-            for (int q = 0; q < K; ++q) r[q] = stage[q][j];
-            const uint32_t pos = gbase[(pick<K>(r, d) >> a.shift) & 0xFFu] + j;
-            if (in_bounds(pos, live, a.o.status)) store_rec<K>(a.rout, pos, r);
-        }
+        sweep_tile<RB, ITEMS, K>(sm, rec, ok, dig, cnt, seg_hist, soff, a.lb, g, g - u, a.o.status, digit_of,
+                                 [&](uint32_t, uint32_t pos, const uint4& r) {
+                                     if (in_bounds(pos, live, a.o.status)) store_rec4<K>(a.rout, pos, r);
+                                 });
         return;
     }
     // tag update (Sec. 3.2) for subtree s = F(l) + seg: the sorted segment is
@@ -461,135 +329,32 @@ __global__ void __launch_bounds__(BLOCK) k_level_pass(LevelPassArgs a)
     const uint32_t piv = seg_pivot(a.v, seg);
     const uint32_t s = a.v.Fl + seg;
     const uint32_t dn = a.dim_next_rr;
-    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
-        uint32_t r[K];
-#pragma unroll
-        for (int q = 0; q < K; ++q) r[q] = stage[q][j];
-        const uint32_t pos = gbase[(pick<K>(r, d) >> a.shift) & 0xFFu] + j;
-        if (pos == piv) {
-            if (!in_bounds(r[0], a.o.n, a.o.status)) continue;
-            const uint32_t idx = a.o.perm0[r[0]];
-            place<K, WIDEST>(a.o, s, idx);
-            if (WIDEST) widest_children<K>(a.o, s, idx, d, a.o.dimnode);
-            continue;
-        }
-        const uint32_t side = pos > piv ? 1u : 0u;
-        const uint32_t nxt = pos - seg - side;
-        if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - a.v.nseg, a.o.status)) continue;
-        store_rec<K>(a.rout, nxt, r);
-        if (acc) {
-            const uint32_t v = pick<K>(r, dn);
-            for (uint32_t p = 0; p < NP; ++p)
-                atomicAdd(&nh[(side * NP + p) * RADIX + ((v >> (8u * p)) & 0xFFu)], 1u);
-        }
-    }
+    sweep_tile<RB, ITEMS, K>(
+        sm, rec, ok, dig, cnt, seg_hist, soff, a.lb, g, g - u, a.o.status, digit_of,
+        [&](uint32_t, uint32_t pos, const uint4& r) {
+            if (pos == piv) {
+                if (!in_bounds(r.x, a.o.n, a.o.status)) return;
+                const uint32_t idx = a.o.perm0[r.x];
+                place<K, WIDEST>(a.o, s, idx);
+                if (WIDEST)
+                    widest_children<K>(a.o, s, seg, idx, d, a.o.box[a.v.l & 1u], a.o.box[(a.v.l + 1u) & 1u]);
+                return;
+            }
+            const uint32_t side = pos > piv ? 1u : 0u;
+            const uint32_t nxt = pos - seg - side;
+            if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - a.v.nseg, a.o.status)) return;
+            store_rec4<K>(a.rout, nxt, r);
+            if (acc) {
+                const uint32_t v = pick4(r, dn);
+                for (uint32_t p = 0; p < NP; ++p)
+                    atomicAdd(&nh[(side * NP + p) * NB + ((v >> (RB * p)) & MASK)], 1u);
+            }
+        });
     if (acc) {
         __syncthreads();
-        uint32_t* dst = a.hist_next + (size_t)(2u * seg) * NP * RADIX;   // children 2seg, 2seg+1 are adjacent
-        for (uint32_t x = threadIdx.x; x < 2u * NP * RADIX; x += BLOCK)
+        uint32_t* dst = a.hist_next + (size_t)(2u * seg) * NP * NB;   // children 2seg, 2seg+1 are adjacent
+        for (uint32_t x = threadIdx.x; x < 2u * NP * NB; x += BLOCK)
             if (nh[x]) atomicAdd(&dst[x], nh[x]);
-    }
-}
-
-// --------------------------------------------------------- block-local level
-
-// Iteration l when every subtree segment fits in one workgroup: each
-// workgroup takes G consecutive whole segments, sorts them in LDS by
-// (segment, rank of the segment's split dimension) with a stable LSD radix
-// sort over (key << 12 | slot) items, then applies the tag update and writes
-// the next iteration's records (or, at l = L-2, places pivots and leaves).
-template <int K, bool WIDEST>
-__global__ void __launch_bounds__(BLOCK) k_level_local(LevelLocalArgs a)
-{
-    constexpr int ITEMS = LOCAL_ITEMS;
-    constexpr uint32_t T = BLOCK * ITEMS;
-    __shared__ uint32_t srec[K][T];
-    __shared__ uint64_t sitem[T];
-    __shared__ uint32_t wh[NWAVE * RADIX];
-    __shared__ uint32_t dstart[RADIX];
-    __shared__ uint32_t sh[NWAVE];
-
-    const Level& v = a.v;
-    const uint32_t live = v.n - v.Fl;
-    const uint32_t i0 = blockIdx.x * a.G;
-    const uint32_t i1 = min(i0 + a.G, v.nseg);
-    const uint32_t off0 = seg_offset(v, i0);
-    const uint32_t off1 = (i1 == v.nseg) ? live : seg_offset(v, i1);
-    const uint32_t m = off1 - off0;
-    for (uint32_t j = threadIdx.x; j < m; j += BLOCK) {
-        uint32_t r[K];
-        load_rec<K>(a.rin, (size_t)off0 + j, r);
-#pragma unroll
-        for (int q = 0; q < K; ++q) srec[q][j] = r[q];
-    }
-    __syncthreads();
-    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t B = a.rank_bits;
-    uint64_t it[ITEMS];
-    bool ok[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
-        ok[i] = j < m;
-        it[i] = 0u;
-        if (ok[i]) {
-            const uint32_t sl = seg_of_pos(v, off0 + j) - i0;
-            const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[v.Fl + i0 + sl] : a.dim_rr;
-            uint32_t key = srec[0][j];
-#pragma unroll
-            for (int q = 1; q < K; ++q) key = ((uint32_t)q == d) ? srec[q][j] : key;
-            it[i] = ((((uint64_t)sl << B) | key) << 12) | j;
-        }
-    }
-    const uint32_t keybits = B + a.group_bits;
-    for (uint32_t sft = 12; sft < 12 + keybits; sft += DIGIT_BITS) {
-        uint32_t dig[ITEMS], rnk[ITEMS];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(it[i] >> sft) & 0xFFu;
-        wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
-        tile_digit_counts(wh, dstart, sh);
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (ok[i]) sitem[dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i]] = it[i];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
-            if (ok[i]) it[i] = sitem[j];
-        }
-        __syncthreads();
-    }
-    const bool last = (v.l + 2u == v.L);
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (!ok[i]) continue;
-        const uint32_t q = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
-        const uint32_t slot = (uint32_t)(it[i] & 0xFFFu);
-        const uint32_t seg = i0 + (uint32_t)(it[i] >> (12 + B));
-        const uint32_t pos = off0 + q;
-        const uint32_t piv = seg_pivot(v, seg);
-        const uint32_t s = v.Fl + seg;
-        uint32_t r[K];
-#pragma unroll
-        for (int qq = 0; qq < K; ++qq) r[qq] = srec[qq][slot];
-        if (!in_bounds(r[0], a.o.n, a.o.status)) continue;
-        if (pos == piv) {
-            const uint32_t idx = a.o.perm0[r[0]];
-            place<K, WIDEST>(a.o, s, idx);
-            if (WIDEST) {
-                uint32_t ds = a.o.dimnode[s];
-                widest_children<K>(a.o, s, idx, ds, a.o.dimnode);
-            }
-            continue;
-        }
-        const uint32_t side = pos > piv ? 1u : 0u;
-        if (last) {
-            place<K, WIDEST>(a.o, 2u * s + 1u + side, a.o.perm0[r[0]]);
-        } else {
-            const uint32_t nxt = pos - seg - side;
-            if (in_bounds(nxt, live - v.nseg, a.o.status)) store_rec<K>(a.rout, nxt, r);
-        }
     }
 }
 
@@ -641,13 +406,13 @@ void launch_prep(int k, const float* pts, uint32_t n, uint32_t* keys, uint32_t* 
     }
 }
 
-void launch_root_dim(int k, uint32_t* ctl, uint8_t* dimnode, hipStream_t st)
+void launch_root_dim(int k, uint32_t* ctl, uint8_t* dimnode, float* box0, hipStream_t st)
 {
     switch (k) {
-    case 1: k_root_dim<1><<<1, 64, 0, st>>>(ctl, dimnode); break;
-    case 2: k_root_dim<2><<<1, 64, 0, st>>>(ctl, dimnode); break;
-    case 3: k_root_dim<3><<<1, 64, 0, st>>>(ctl, dimnode); break;
-    default: k_root_dim<4><<<1, 64, 0, st>>>(ctl, dimnode); break;
+    case 1: k_root_dim<1><<<1, 64, 0, st>>>(ctl, dimnode, box0); break;
+    case 2: k_root_dim<2><<<1, 64, 0, st>>>(ctl, dimnode, box0); break;
+    case 3: k_root_dim<3><<<1, 64, 0, st>>>(ctl, dimnode, box0); break;
+    default: k_root_dim<4><<<1, 64, 0, st>>>(ctl, dimnode, box0); break;
     }
 }
 
@@ -690,16 +455,26 @@ void launch_level_hist(int k, const LevelHistArgs& a, hipStream_t st)
     }
 }
 
-template <int K>
-static void level_pass_k(const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
+template <int K, int RB>
+static void level_pass_kr(const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
 {
     const uint32_t grid = a.tl.tiles;
     if (last) {
-        if (widest) k_level_pass<K, true, true><<<grid, BLOCK, 0, st>>>(a);
-        else k_level_pass<K, true, false><<<grid, BLOCK, 0, st>>>(a);
+        if (widest) k_level_pass<K, true, true, RB><<<grid, BLOCK, 0, st>>>(a);
+        else k_level_pass<K, true, false, RB><<<grid, BLOCK, 0, st>>>(a);
     } else {
-        if (widest) k_level_pass<K, false, true><<<grid, BLOCK, 0, st>>>(a);
-        else k_level_pass<K, false, false><<<grid, BLOCK, 0, st>>>(a);
+        if (widest) k_level_pass<K, false, true, RB><<<grid, BLOCK, 0, st>>>(a);
+        else k_level_pass<K, false, false, RB><<<grid, BLOCK, 0, st>>>(a);
+    }
+}
+
+template <int K>
+static void level_pass_k(const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
+{
+    switch (a.radix_bits) {
+    case 8: level_pass_kr<K, 8>(a, last, widest, st); break;
+    case 9: level_pass_kr<K, 9>(a, last, widest, st); break;
+    default: level_pass_kr<K, 10>(a, last, widest, st); break;
     }
 }
 
@@ -710,24 +485,6 @@ void launch_level_pass(int k, const LevelPassArgs& a, bool last, bool widest, hi
     case 2: level_pass_k<2>(a, last, widest, st); break;
     case 3: level_pass_k<3>(a, last, widest, st); break;
     default: level_pass_k<4>(a, last, widest, st); break;
-    }
-}
-
-template <int K>
-static void level_local_k(const LevelLocalArgs& a, bool widest, uint32_t grid, hipStream_t st)
-{
-    if (widest) k_level_local<K, true><<<grid, BLOCK, 0, st>>>(a);
-    else k_level_local<K, false><<<grid, BLOCK, 0, st>>>(a);
-}
-
-void launch_level_local(int k, const LevelLocalArgs& a, bool widest, hipStream_t st)
-{
-    const uint32_t grid = ceil_div(a.v.nseg, a.G);
-    switch (k) {
-    case 1: level_local_k<1>(a, widest, grid, st); break;
-    case 2: level_local_k<2>(a, widest, grid, st); break;
-    case 3: level_local_k<3>(a, widest, grid, st); break;
-    default: level_local_k<4>(a, widest, grid, st); break;
     }
 }
 

@@ -1,0 +1,303 @@
+// kdt_tail.hip -- the deep iterations of the build, one subtree per workgroup.
+//
+// Once every subtree of iteration l0 holds at most TAIL_CAP points, the
+// remaining iterations l0 .. L-2 only ever compare points of the same
+// subtree.  Each workgroup therefore takes one (or two) whole level-l0
+// subtrees, reads their records from HBM once and runs the rest of the
+// paper's loop on them in LDS:
+//
+//   * once per dimension d, the subtree's points are sorted by rank_d (LDS
+//     radix sort of (rank, slot)), giving the list ord_d.  Any subset of the
+//     points keeps its relative order in ord_d, so ord_d restricted to a
+//     deeper subtree is that subtree's sorted order in dimension d;
+//   * iteration l: a point's position inside its subtree segment after the
+//     sort of Sec. 3.1 is the number of points of the same segment that
+//     precede it in ord_d (d = the segment's split dimension).  Waves walk
+//     ord_d with one counter per (wave, segment), ranking lanes of equal
+//     segment with ballots;
+//   * the tag update of Sec. 3.2 then compares that position with the pivot
+//     position ss(2s+1): the pivot is placed at node s, the others move to
+//     segment 2q or 2q+1 of the next iteration; at l = L-2 the children are
+//     leaves and are placed directly.
+//
+// The input order of a subtree is its parent's sorted order, so the parent's
+// dimension needs no sort (round robin: dimension (l0-1) mod k).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kdt_common.h"
+#include "kdt_device.h"
+#include "kdt_kernels.h"
+#include "kdt_layout.h"
+
+namespace kdt {
+
+constexpr uint32_t DONE = 0xFFFFu;
+
+// Domain of local node (t, q) for split-widest: the subtree root's box
+// clipped by the planes of its local ancestors (stored per local node).
+template <int K>
+__device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, const float (*rootbox)[8],
+                                          const uint8_t* ndim, const float* nplane, float (&lo)[K], float (&hi)[K])
+{
+    const uint32_t r = q >> t;
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+        lo[d] = rootbox[r][d];
+        hi[d] = rootbox[r][4 + d];
+    }
+    uint32_t qq = q;
+    for (uint32_t tt = t; tt > 0; --tt) {
+        const uint32_t pq = qq >> 1;
+        const uint32_t idx = gc * ((1u << (tt - 1u)) - 1u) + pq;
+        const uint32_t da = ndim[idx];
+        const float plane = nplane[idx];
+#pragma unroll
+        for (int d = 0; d < K; ++d) {
+            if ((uint32_t)d == da) {
+                if ((qq & 1u) == 0u) hi[d] = fminf(hi[d], plane);
+                else lo[d] = fmaxf(lo[d], plane);
+            }
+        }
+        qq = pq;
+    }
+}
+
+template <int K, bool WIDEST>
+__global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
+{
+    constexpr int ITEMS = TAIL_ITEMS;
+    constexpr uint32_t C = TAIL_CAP;
+    constexpr uint32_t CW = 64u * ITEMS;           // positions walked per wave
+    constexpr uint32_t NODES = WIDEST ? 2u * C + 64u : 1u;
+    __shared__ uint16_t ord[K][C];
+    __shared__ uint16_t seg[C];
+    __shared__ uint16_t tmp[C];
+    __shared__ uint64_t ubuf[C];                   // sort exchange / per-wave segment counters
+    __shared__ uint32_t wh[NWAVE * RADIX];
+    __shared__ uint32_t dstart[RADIX];
+    __shared__ uint32_t sh[NWAVE];
+    __shared__ uint8_t segdim[2][WIDEST ? C : 1];
+    __shared__ uint8_t ndim[NODES];
+    __shared__ float nplane[NODES];
+    __shared__ float rootbox[2][8];
+    __shared__ uint32_t node[C];                   // final node of each slot
+    uint16_t(*cnt)[C] = reinterpret_cast<uint16_t(*)[C]>(ubuf);   // [NWAVE][C]
+
+    const Outs& o = a.o;
+    const Level v0 = a.v0;
+    const uint32_t l0 = v0.l;
+    const uint32_t L = v0.L;
+    const uint32_t i0 = blockIdx.x * a.G;
+    const uint32_t i1 = min(i0 + a.G, v0.nseg);
+    const uint32_t gc = i1 - i0;
+    const uint32_t live0 = v0.n - v0.Fl;
+    const uint32_t off0 = seg_offset(v0, i0);
+    const uint32_t m = ((i1 == v0.nseg) ? live0 : seg_offset(v0, i1)) - off0;
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t B = a.rank_bits;
+    if (m > C) {                                   // the host sizes groups to fit
+        if (threadIdx.x == 0) atomicOr(o.status, KDT_STATUS_INTERNAL);
+        return;
+    }
+
+    // ---- load the group's records (slot e = its position in the input) ----
+    uint4 rec[ITEMS];
+    uint32_t idx[ITEMS];                           // original index of each slot
+    bool ok[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+        ok[i] = e < m;
+        rec[i] = ok[i] ? load_rec4<K>(a.rin, (size_t)off0 + e) : make_uint4(0u, 0u, 0u, 0u);
+        seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
+        node[e] = 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        idx[i] = 0u;
+        if (ok[i] && in_bounds(rec[i].x, o.n, o.status)) idx[i] = o.perm0[rec[i].x];
+    }
+    float4 pc[ITEMS];                              // coordinates of each slot's point
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) pc[i] = ok[i] ? load_point<K>(o.pts, idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (WIDEST && threadIdx.x < gc) {
+        // domain of each group root, written by its parent's pivot
+        const uint32_t q = threadIdx.x;
+        const float* bx = o.box[l0 & 1u] + (size_t)(i0 + q) * 8;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) rootbox[q][d] = bx[d];
+        segdim[0][q] = o.dimnode[v0.Fl + i0 + q];
+    }
+    // dimension whose order the input already has (within every segment)
+    uint32_t free_dim = 0xFFFFFFFFu;
+    if (!WIDEST) free_dim = (l0 + (uint32_t)K - 1u) % (uint32_t)K;
+    else if (gc == 1u) free_dim = o.dimnode[(v0.Fl + i0 - 1u) >> 1];
+    __syncthreads();
+
+    // ---- ord_d: the group sorted by rank_d (stable LSD over 8-bit digits) ----
+    for (uint32_t d = 0; d < (uint32_t)K; ++d) {
+        if (d == free_dim) {
+            for (uint32_t p = threadIdx.x; p < m; p += BLOCK) ord[d][p] = (uint16_t)p;
+            continue;
+        }
+        uint64_t it[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            it[i] = ((uint64_t)pick4(rec[i], d) << 12) | e;
+        }
+        for (uint32_t sft = 12; sft < 12 + B; sft += DIGIT_BITS) {
+            uint32_t dig[ITEMS], rnk[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(it[i] >> sft) & 0xFFu;
+            wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
+            tile_digit_counts(wh, dstart, sh);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i)
+                if (ok[i]) ubuf[dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i]] = it[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+                if (ok[i]) it[i] = ubuf[p];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+            if (ok[i]) ord[d][p] = (uint16_t)(it[i] & 0xFFFu);
+        }
+    }
+    __syncthreads();
+
+    // ---- iterations l0 .. L-2 ----
+    uint32_t cur = 0;
+    for (uint32_t l = l0; l + 2u <= L; ++l) {
+        const uint32_t t = l - l0;
+        const Level vl = make_level(v0.n, l);
+        const uint32_t S = gc << t;                       // group segments on this level
+        const uint32_t gbits = rank_bits(S);
+        const bool last = (l + 2u == L);
+        for (uint32_t q = threadIdx.x; q < S; q += BLOCK) {
+#pragma unroll
+            for (int ww = 0; ww < NWAVE; ++ww) cnt[ww][q] = 0;
+        }
+        __syncthreads();
+        // position of each point inside its segment in the order of the
+        // segment's split dimension
+        for (uint32_t d = 0; d < (uint32_t)K; ++d) {
+            if (!WIDEST && d != l % (uint32_t)K) continue;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+                uint32_t e = 0, q = DONE;
+                if (p < m) {
+                    e = ord[d][p];
+                    q = seg[e];
+                }
+                bool valid = q != DONE;
+                if (WIDEST && valid) valid = segdim[cur][q] == d;
+                const uint64_t peers = match_bits(q, gbits, valid);
+                const uint32_t below = count_below(peers);
+                uint32_t base = 0;
+                if (valid) base = cnt[w][q];
+                if (valid && below == 0) cnt[w][q] = (uint16_t)(base + (uint32_t)__popcll(peers));
+                if (valid) tmp[e] = (uint16_t)((w << 12) | (base + below));
+            }
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < S; q += BLOCK) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int ww = 0; ww < NWAVE; ++ww) {
+                const uint32_t c = cnt[ww][q];
+                cnt[ww][q] = (uint16_t)run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        // tag update (Sec. 3.2)
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            if (!ok[i]) continue;
+            const uint32_t q = seg[e];
+            if (q == DONE) continue;
+            const uint32_t tv = tmp[e];
+            const uint32_t wr = (tv & 0xFFFu) + cnt[tv >> 12][q];
+            const uint32_t gq = (i0 << t) + q;
+            const uint32_t ls = seg_left_size(vl, gq);
+            if (wr == ls) {
+                const uint32_t sn = vl.Fl + gq;
+                node[e] = sn;
+                if (WIDEST) {
+                    const uint32_t ds = segdim[cur][q];
+                    const float plane = pickf(pc[i], ds);
+                    const uint32_t nidx = gc * ((1u << t) - 1u) + q;
+                    ndim[nidx] = (uint8_t)ds;
+                    nplane[nidx] = plane;
+                    float lo[K], hi[K];
+                    local_box<K>(t, q, gc, rootbox, ndim, nplane, lo, hi);
+#pragma unroll
+                    for (uint32_t c = 0; c < 2u; ++c) {
+                        const uint32_t child = 2u * sn + 1u + c;
+                        if (child >= o.n) continue;
+                        float l2[K], h2[K];
+#pragma unroll
+                        for (int dd = 0; dd < K; ++dd) {
+                            l2[dd] = lo[dd];
+                            h2[dd] = hi[dd];
+                            if ((uint32_t)dd == ds) {
+                                if (c == 0u) h2[dd] = fminf(hi[dd], plane);
+                                else l2[dd] = fmaxf(lo[dd], plane);
+                            }
+                        }
+                        const uint32_t cd = widest_dim<K>(l2, h2);
+                        o.dimnode[child] = (uint8_t)cd;
+                        if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
+                    }
+                }
+                seg[e] = (uint16_t)DONE;
+            } else {
+                const uint32_t side = wr > ls ? 1u : 0u;
+                if (last) {
+                    node[e] = vl.Fl + vl.nseg + 2u * gq + side;
+                    seg[e] = (uint16_t)DONE;
+                } else {
+                    seg[e] = (uint16_t)(2u * q + side);
+                }
+            }
+        }
+        __syncthreads();
+        cur ^= 1u;
+    }
+    // placement of every slot at its node
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+        if (ok[i]) place_pt<K, WIDEST>(o, node[e], idx[i], pc[i]);
+    }
+}
+
+template <int K>
+static void tail_k(const TailArgs& a, bool widest, uint32_t grid, hipStream_t st)
+{
+    if (widest) k_tail<K, true><<<grid, BLOCK, 0, st>>>(a);
+    else k_tail<K, false><<<grid, BLOCK, 0, st>>>(a);
+}
+
+void launch_tail(int k, const TailArgs& a, bool widest, hipStream_t st)
+{
+    const uint32_t grid = ceil_div(a.v0.nseg, a.G);
+    switch (k) {
+    case 1: tail_k<1>(a, widest, grid, st); break;
+    case 2: tail_k<2>(a, widest, grid, st); break;
+    case 3: tail_k<3>(a, widest, grid, st); break;
+    default: tail_k<4>(a, widest, grid, st); break;
+    }
+}
+
+}  // namespace kdt

@@ -11,7 +11,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libkdt.so")
+# KDT_LIB selects another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("KDT_LIB") or os.path.join(_HERE, "libkdt.so")
 
 OK = 0
 EINVAL = 1
