@@ -58,6 +58,19 @@ struct Plan {
     size_t rec_words;          // words per record buffer
 };
 
+// Records per thread of the level-l sort tiles (tile = 512 * items): the
+// largest tile that the level's biggest subtree still fills.
+#ifndef KDT_LEVEL_MAX_ITEMS
+#define KDT_LEVEL_MAX_ITEMS 8
+#endif
+uint32_t level_items(uint32_t n, uint32_t l)
+{
+    const kdt::Level v = kdt::make_level(n, l);
+    const uint32_t big = 2u * v.W - 1u;
+    uint32_t items = big >= 8192u ? 16u : (big >= 4096u ? 8u : 4u);
+    return items < KDT_LEVEL_MAX_ITEMS ? items : KDT_LEVEL_MAX_ITEMS;
+}
+
 bool level_is_global(const Plan& p, uint32_t l)
 {
     return l >= 1 && l + 2 <= p.L && l < p.first_local;
@@ -92,7 +105,7 @@ Plan make_plan(uint32_t n, uint32_t k, bool widest)
     for (uint32_t l = 1; l + 2 <= p.L; ++l) {
         if (!level_is_global(p, l)) continue;
         const Level v = make_level(n, l);
-        const SegTiles t = tiles_level(v, LEVEL_TILE);
+        const SegTiles t = tiles_level(v, 512u * level_items(n, l));
         if (t.tiles > p.max_tiles) p.max_tiles = t.tiles;
         if (v.nseg * 2u > p.max_hist_segs) p.max_hist_segs = v.nseg * 2u;
     }
@@ -261,7 +274,7 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
         for (int q = 0; q < 4; ++q) pass_words[npass++] = presort_tiles * RADIX_HOST;
     for (uint32_t l = 1; l + 2 <= p.L; ++l)
         if (level_is_global(p, l)) {
-            const uint32_t t = tiles_level(make_level(n, l), LEVEL_TILE).tiles;
+            const uint32_t t = tiles_level(make_level(n, l), 512u * level_items(n, l)).tiles;
             for (uint32_t q = 0; q < p.P; ++q) pass_words[npass++] = t << p.RB;
         }
     auto next_words = [&](uint32_t q) { return q + 1 < npass ? pass_words[q + 1] : 0u; };
@@ -344,7 +357,8 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
     for (uint32_t l = 1; l + 2 <= p.L; ++l) {
         const Level v = make_level(n, l);
         if (level_is_global(p, l)) {
-            const SegTiles tl = tiles_level(v, LEVEL_TILE);
+            const uint32_t items = level_items(n, l);
+            const SegTiles tl = tiles_level(v, 512u * items);
             uint32_t* h = hist[l & 1];
             if (widest) {
                 LevelHistArgs ha{};
@@ -372,6 +386,7 @@ kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t*
                 a.pass = ps;
                 a.shift = p.RB * ps;
                 a.radix_bits = p.RB;
+                a.items = items;
                 a.lb = lb[q & 1];
                 a.lb_zero = lb[(q + 1) & 1];
                 a.lb_zero_n = next_words(q);

@@ -198,7 +198,7 @@ __device__ __forceinline__ uint64_t match_bits(uint32_t value, uint32_t bits, bo
 __device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)
 {
     if (!p) return;
-    for (uint32_t x = blockIdx.x * BLOCK + threadIdx.x; x < n; x += gridDim.x * BLOCK) p[x] = 0u;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) p[x] = 0u;
 }
 
 

@@ -25,17 +25,13 @@ constexpr uint32_t MAX_PASSES = 256;       // onesweep passes per build (tile co
 constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digit passes over a rank of at most 30 bits (8..10-bit digits)
 constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
 // Tile shapes (items per thread of a 256-thread workgroup); tuning knobs.
+// (512-thread workgroups for the onesweep passes.)
 #ifndef KDT_PRESORT_ITEMS
-#define KDT_PRESORT_ITEMS 16
+#define KDT_PRESORT_ITEMS 8
 #endif
-#ifndef KDT_LEVEL_ITEMS
-#define KDT_LEVEL_ITEMS 8
-#endif
-constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;   // presort tile: (key, index) pairs
-constexpr int LEVEL_ITEMS = KDT_LEVEL_ITEMS;       // level tile: records
-constexpr uint32_t PRESORT_TILE = 256u * PRESORT_ITEMS;
-constexpr uint32_t LEVEL_TILE = 256u * LEVEL_ITEMS;
-constexpr uint32_t HIST_TILE = 8u * LEVEL_TILE;
+constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;   // presort tile: 512 x this many (key, index) pairs
+constexpr uint32_t PRESORT_TILE = 512u * PRESORT_ITEMS;
+constexpr uint32_t HIST_TILE = 16384;               // chunk of the split-widest histogram kernel
 constexpr int TAIL_ITEMS = 8;                     // subtree tail: up to 2048 points per workgroup
 constexpr uint32_t TAIL_CAP = 256u * TAIL_ITEMS;   // chunk of the split-widest histogram kernel
 
@@ -96,6 +92,7 @@ struct LevelPassArgs {
     uint32_t* rout;              // next pass's input, or (last pass) next iteration's records
     const uint32_t* hist;        // [seg][pass][2^radix_bits] of this iteration
     uint32_t passes, pass, shift, radix_bits;
+    uint32_t items;              // records per thread in this launch's tiles (tile = 512 * items)
     uint32_t* lb;
     uint32_t* lb_zero;
     uint32_t lb_zero_n;

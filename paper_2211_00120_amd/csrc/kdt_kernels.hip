@@ -134,15 +134,14 @@ __global__ void k_root_dim(uint32_t* ctl, uint8_t* dimnode, float* box0)
 // sorted indices (rank -> index) and scatters each index's rank into the
 // point-major rank table.  Pairs are stored interleaved (uint2).
 template <bool FIRST, bool LAST>
-__global__ void __launch_bounds__(BLOCK) k_presort_pass(PresortArgs a)
+__global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 {
     constexpr int ITEMS = PRESORT_ITEMS;
     constexpr int RB = 8;
-    constexpr uint32_t T = BLOCK * ITEMS;
-    __shared__ SweepSmem<RB, ITEMS, 2> sm;
+    constexpr uint32_t T = SWEEP_THREADS * ITEMS;
+    __shared__ SweepSmem<RB, 2> sm;
 
     if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
-    zero_range(a.lb_zero, a.lb_zero_n);
     __syncthreads();
     const uint32_t g = sm.tile;
     const uint32_t start = g * T;
@@ -172,7 +171,7 @@ __global__ void __launch_bounds__(BLOCK) k_presort_pass(PresortArgs a)
     }
     const uint32_t n = a.n;
     sweep_tile<RB, ITEMS, 2>(
-        sm, rec, ok, dig, cnt, a.hist, 0u, a.lb, g, 0u, a.status,
+        sm, rec, ok, dig, ITEMS, cnt, a.hist, 0u, a.lb, g, 0u, a.status,
         [&](const uint4& r) { return (r.x >> shift) & 0xFFu; },
         [&](uint32_t, uint32_t pos, const uint4& r) {
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
@@ -183,6 +182,8 @@ __global__ void __launch_bounds__(BLOCK) k_presort_pass(PresortArgs a)
                 reinterpret_cast<uint2*>(a.kvout)[pos] = make_uint2(r.x, r.y);
             }
         });
+    // clear the next pass's look-back words (nothing waits on these stores)
+    zero_range(a.lb_zero, a.lb_zero_n);
 }
 
 // ------------------------------------------------------------------ level 0
@@ -269,92 +270,16 @@ __global__ void __launch_bounds__(BLOCK) k_level_hist(LevelHistArgs a)
         if (h[x]) atomicAdd(&dst[x], h[x]);
 }
 
-// One stable digit pass of the per-segment sort of iteration l, ordering each
-// subtree's points by the rank of its split dimension (RB-bit digits).  Tiles
-// never straddle a segment; global offsets are segment offset + digit prefix
-// inside the segment (from the histogram) + look-back over the segment's
-// earlier tiles.  LAST fuses the tag update of Sec. 3.2 into the scatter and,
-// for round robin, accumulates the next iteration's digit histograms.
-template <int K, bool LAST, bool WIDEST, int RB>
-__global__ void __launch_bounds__(BLOCK) k_level_pass(LevelPassArgs a)
+template <int K>
+void launch_level_pass_k(const LevelPassArgs& a, bool last, bool widest, hipStream_t st);
+
+void launch_level_pass(int k, const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
 {
-    constexpr int ITEMS = LEVEL_ITEMS;
-    constexpr uint32_t T = BLOCK * ITEMS;
-    constexpr uint32_t NB = 1u << RB;
-    constexpr uint32_t MASK = NB - 1u;
-    __shared__ SweepSmem<RB, ITEMS, K> sm;
-    __shared__ uint32_t nh[LAST ? 2 * MAX_LEVEL_PASSES * NB : 1];
-
-    if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
-    zero_range(a.lb_zero, a.lb_zero_n);
-    zero_range(a.zero2, a.zero2_n);
-    const uint32_t NP = a.next_passes;
-    const bool acc = LAST && a.hist_next != nullptr;
-    if (acc)
-        for (uint32_t x = threadIdx.x; x < 2u * NP * NB; x += BLOCK) nh[x] = 0u;
-    __syncthreads();
-    const uint32_t g = sm.tile;
-    uint32_t seg, u;
-    tile_locate(a.tl, g, seg, u);
-    const uint32_t soff = tiles_seg_offset(a.tl, seg);
-    const uint32_t ssz = tiles_seg_size(a.tl, seg);
-    const uint32_t start = u * T;
-    const uint32_t cnt = min(T, ssz - start);
-    const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[a.v.Fl + seg] : a.dim_rr;
-    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t live = a.v.n - a.v.Fl;
-    const uint32_t shift = a.shift;
-
-    uint4 rec[ITEMS];
-    uint32_t dig[ITEMS];
-    bool ok[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
-        ok[i] = j < cnt;
-        rec[i] = ok[i] ? load_rec4<K>(a.rin, (size_t)soff + start + j) : make_uint4(0u, 0u, 0u, 0u);
-        dig[i] = (pick4(rec[i], d) >> shift) & MASK;
-    }
-    const uint32_t* seg_hist = a.hist + ((size_t)seg * a.passes + a.pass) * NB;
-    auto digit_of = [&](const uint4& r) { return (pick4(r, d) >> shift) & MASK; };
-    if (!LAST) {
-        sweep_tile<RB, ITEMS, K>(sm, rec, ok, dig, cnt, seg_hist, soff, a.lb, g, g - u, a.o.status, digit_of,
-                                 [&](uint32_t, uint32_t pos, const uint4& r) {
-                                     if (in_bounds(pos, live, a.o.status)) store_rec4<K>(a.rout, pos, r);
-                                 });
-        return;
-    }
-    // tag update (Sec. 3.2) for subtree s = F(l) + seg: the sorted segment is
-    // [soff, soff + ssz); the pivot is the entry at soff + ss(2s+1).
-    const uint32_t piv = seg_pivot(a.v, seg);
-    const uint32_t s = a.v.Fl + seg;
-    const uint32_t dn = a.dim_next_rr;
-    sweep_tile<RB, ITEMS, K>(
-        sm, rec, ok, dig, cnt, seg_hist, soff, a.lb, g, g - u, a.o.status, digit_of,
-        [&](uint32_t, uint32_t pos, const uint4& r) {
-            if (pos == piv) {
-                if (!in_bounds(r.x, a.o.n, a.o.status)) return;
-                const uint32_t idx = a.o.perm0[r.x];
-                place<K, WIDEST>(a.o, s, idx);
-                if (WIDEST)
-                    widest_children<K>(a.o, s, seg, idx, d, a.o.box[a.v.l & 1u], a.o.box[(a.v.l + 1u) & 1u]);
-                return;
-            }
-            const uint32_t side = pos > piv ? 1u : 0u;
-            const uint32_t nxt = pos - seg - side;
-            if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - a.v.nseg, a.o.status)) return;
-            store_rec4<K>(a.rout, nxt, r);
-            if (acc) {
-                const uint32_t v = pick4(r, dn);
-                for (uint32_t p = 0; p < NP; ++p)
-                    atomicAdd(&nh[(side * NP + p) * NB + ((v >> (RB * p)) & MASK)], 1u);
-            }
-        });
-    if (acc) {
-        __syncthreads();
-        uint32_t* dst = a.hist_next + (size_t)(2u * seg) * NP * NB;   // children 2seg, 2seg+1 are adjacent
-        for (uint32_t x = threadIdx.x; x < 2u * NP * NB; x += BLOCK)
-            if (nh[x]) atomicAdd(&dst[x], nh[x]);
+    switch (k) {
+    case 1: launch_level_pass_k<1>(a, last, widest, st); break;
+    case 2: launch_level_pass_k<2>(a, last, widest, st); break;
+    case 3: launch_level_pass_k<3>(a, last, widest, st); break;
+    default: launch_level_pass_k<4>(a, last, widest, st); break;
     }
 }
 
@@ -418,10 +343,10 @@ void launch_root_dim(int k, uint32_t* ctl, uint8_t* dimnode, float* box0, hipStr
 
 void launch_presort_pass(const PresortArgs& a, bool first, bool last, uint32_t tiles, hipStream_t st)
 {
-    if (first && last) k_presort_pass<true, true><<<tiles, BLOCK, 0, st>>>(a);
-    else if (first) k_presort_pass<true, false><<<tiles, BLOCK, 0, st>>>(a);
-    else if (last) k_presort_pass<false, true><<<tiles, BLOCK, 0, st>>>(a);
-    else k_presort_pass<false, false><<<tiles, BLOCK, 0, st>>>(a);
+    if (first && last) k_presort_pass<true, true><<<tiles, SWEEP_THREADS, 0, st>>>(a);
+    else if (first) k_presort_pass<true, false><<<tiles, SWEEP_THREADS, 0, st>>>(a);
+    else if (last) k_presort_pass<false, true><<<tiles, SWEEP_THREADS, 0, st>>>(a);
+    else k_presort_pass<false, false><<<tiles, SWEEP_THREADS, 0, st>>>(a);
 }
 
 template <int K>
@@ -452,39 +377,6 @@ void launch_level_hist(int k, const LevelHistArgs& a, hipStream_t st)
     case 2: k_level_hist<2><<<grid, BLOCK, 0, st>>>(a); break;
     case 3: k_level_hist<3><<<grid, BLOCK, 0, st>>>(a); break;
     default: k_level_hist<4><<<grid, BLOCK, 0, st>>>(a); break;
-    }
-}
-
-template <int K, int RB>
-static void level_pass_kr(const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
-{
-    const uint32_t grid = a.tl.tiles;
-    if (last) {
-        if (widest) k_level_pass<K, true, true, RB><<<grid, BLOCK, 0, st>>>(a);
-        else k_level_pass<K, true, false, RB><<<grid, BLOCK, 0, st>>>(a);
-    } else {
-        if (widest) k_level_pass<K, false, true, RB><<<grid, BLOCK, 0, st>>>(a);
-        else k_level_pass<K, false, false, RB><<<grid, BLOCK, 0, st>>>(a);
-    }
-}
-
-template <int K>
-static void level_pass_k(const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
-{
-    switch (a.radix_bits) {
-    case 8: level_pass_kr<K, 8>(a, last, widest, st); break;
-    case 9: level_pass_kr<K, 9>(a, last, widest, st); break;
-    default: level_pass_kr<K, 10>(a, last, widest, st); break;
-    }
-}
-
-void launch_level_pass(int k, const LevelPassArgs& a, bool last, bool widest, hipStream_t st)
-{
-    switch (k) {
-    case 1: level_pass_k<1>(a, last, widest, st); break;
-    case 2: level_pass_k<2>(a, last, widest, st); break;
-    case 3: level_pass_k<3>(a, last, widest, st); break;
-    default: level_pass_k<4>(a, last, widest, st); break;
     }
 }
 

@@ -1,13 +1,21 @@
 // kdt_sweep.h -- one stable LSD digit pass of a segmented onesweep radix sort.
 //
-// A tile is up to BLOCK*ITEMS consecutive elements of ONE segment.  Its
-// elements are held in registers in wave-striped order (item i of lane j of
-// wave w is tile element w*64*ITEMS + i*64 + j), ranked by digit with wave64
-// ballots (stable), counted per digit, and scattered through LDS so that the
-// global writes of one digit are contiguous.  The global position of a digit
-// run is: segment offset + count of smaller digits in the segment (from the
-// segment's digit histogram) + count of the same digit in the segment's
-// earlier tiles (decoupled look-back that stops at the segment's first tile).
+// A tile is up to SWEEP_THREADS*active consecutive elements of ONE segment
+// (active <= ITEMS items per thread, chosen per launch).  Its elements are
+// held in registers in wave-striped order (item i of lane j of wave w is tile
+// element w*64*active + i*64 + j), ranked by digit with wave64 ballots
+// (stable), counted per digit, and written out through an LDS stage in
+// rounds of SWEEP_STAGE elements so that the global writes of one digit are
+// contiguous.  The global position of a digit run is: segment offset + count
+// of smaller digits in the segment (from the segment's digit histogram) +
+// count of the same digit in the segment's earlier tiles (decoupled
+// look-back that stops at the segment's first tile).
+//
+// Large tiles matter on this part: the look-back reads every digit's status
+// word of each predecessor still in flight with device-coherent (uncached)
+// loads, and the number of predecessors in flight grows with the tile rate,
+// so the status traffic per byte of data falls with the square of the tile
+// size.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,27 +25,55 @@
 
 namespace kdt {
 
-template <int RB, int ITEMS, int RW>
+constexpr int SWEEP_THREADS = 512;
+constexpr int SWEEP_WAVES = SWEEP_THREADS / 64;
+constexpr uint32_t SWEEP_STAGE = 2048;
+
+// Predecessor windows of the look-back: a short first window (the common
+// case is a nearby inclusive prefix), then wider ones.
+constexpr int LB_FIRST = 4;
+#ifndef KDT_LB_WINDOW
+#define KDT_LB_WINDOW 16
+#endif
+constexpr int LB_WINDOW = KDT_LB_WINDOW;
+
+template <int RB, int RW>
 struct SweepSmem {
     static constexpr uint32_t NB = 1u << RB;
-    static constexpr uint32_t T = BLOCK * ITEMS;
-    uint32_t wh[NWAVE * NB];     // per-wave digit counters, then per-wave exclusive offsets
-    uint32_t dstart[NB];         // tile-local start of each digit run
-    uint32_t gbase[NB];          // global position of the run minus dstart
-    uint32_t sh[NWAVE];
+    uint16_t wh[SWEEP_WAVES * NB];   // per-wave digit counters, then per-wave exclusive offsets
+    uint32_t dstart[NB];             // tile-local start of each digit run
+    uint32_t gbase[NB];              // global position of the run minus dstart
+    uint32_t sh[SWEEP_WAVES];
     uint32_t tile;
-    uint32_t stage[RW][T];       // records in sorted tile order
+    uint32_t stage[RW][SWEEP_STAGE]; // one round of records in sorted tile order
 };
 
-// Stable wave multisplit over RB-bit digits (see wave_multisplit).
+// Exclusive scan of one value per thread over SWEEP_THREADS threads.
+__device__ __forceinline__ uint32_t sweep_excl_scan(uint32_t v, uint32_t* sh)
+{
+    const int lane = (int)lane_id();
+    const int w = (int)(threadIdx.x >> 6);
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int i = 0; i < SWEEP_WAVES; ++i)
+        if (i < w) base += sh[i];
+    __syncthreads();
+    return base + inc - v;
+}
+
+// Stable wave multisplit over RB-bit digits of the first `active` items.
 template <int RB, int ITEMS>
-__device__ __forceinline__ void wave_multisplit_rb(const uint32_t (&digit)[ITEMS], const bool (&valid)[ITEMS],
-                                                   uint32_t (&rank)[ITEMS], uint32_t* wh)
+__device__ __forceinline__ void wave_multisplit16(const uint32_t (&digit)[ITEMS], const bool (&valid)[ITEMS],
+                                                  uint32_t (&rank)[ITEMS], uint16_t* wh, int active)
 {
     constexpr uint32_t NB = 1u << RB;
     for (uint32_t j = lane_id(); j < NB; j += 64) wh[j] = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
+        if (i >= active) break;
         uint64_t peers = __ballot(valid[i]);
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
@@ -48,83 +84,86 @@ __device__ __forceinline__ void wave_multisplit_rb(const uint32_t (&digit)[ITEMS
         const uint32_t below = count_below(peers);
         uint32_t base = 0;
         if (valid[i]) base = wh[digit[i]];
-        if (valid[i] && below == 0) wh[digit[i]] = base + (uint32_t)__popcll(peers);
+        if (valid[i] && below == 0) wh[digit[i]] = (uint16_t)(base + (uint32_t)__popcll(peers));
         rank[i] = base + below;
     }
 }
 
-// Number of predecessor tiles whose look-back words are fetched at once.
-#ifndef KDT_LB_WINDOW
-#define KDT_LB_WINDOW 16
-#endif
-constexpr int LB_WINDOW = KDT_LB_WINDOW;
-
 // Decoupled look-back of digit `bin` for tile g (g > g0): sums the published
 // counts of tiles g-1, g-2, ... until one with an inclusive prefix (the
-// segment's first tile g0 always publishes one).  The words of LB_WINDOW
-// predecessors are requested together, so a long chain of aggregates costs
-// one memory round trip per window instead of one per tile; a word that is not
-// published yet is polled alone (bounded, see LB_MAX_POLLS).
-__device__ __forceinline__ uint32_t lookback_window(const uint32_t* lb, uint32_t NB, uint32_t g, uint32_t g0,
-                                                    uint32_t bin, uint32_t* status)
+// segment's first tile g0 always publishes one).  Predecessor words are
+// requested a window at a time; a word that is not published yet is polled
+// alone (bounded, see LB_MAX_POLLS).
+template <int W>
+__device__ __forceinline__ bool lookback_round(const uint32_t* lb, uint32_t NB, uint32_t& gg, uint32_t g0,
+                                               uint32_t bin, uint32_t& excl, uint32_t* status)
 {
-    uint32_t excl = 0;
-    uint32_t gg = g - 1u;          // next predecessor to consume
-    for (;;) {
-        uint32_t v[LB_WINDOW];
+    uint32_t v[W];
 #pragma unroll
-        for (int j = 0; j < LB_WINDOW; ++j)
-            v[j] = (gg >= g0 + (uint32_t)j) ? lb_load(&lb[(size_t)(gg - j) * NB + bin]) : 0u;
+    for (int j = 0; j < W; ++j) v[j] = (gg >= g0 + (uint32_t)j) ? lb_load(&lb[(size_t)(gg - j) * NB + bin]) : 0u;
 #pragma unroll
-        for (int j = 0; j < LB_WINDOW; ++j) {
-            uint32_t s = v[j];
-            uint32_t polls = 0;
-            while ((s & ~LB_VAL) == 0u) {
-                if (++polls > LB_MAX_POLLS) {
-                    atomicOr(status, 0x100u);
-                    return excl;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                s = lb_load(&lb[(size_t)(gg - j) * NB + bin]);
+    for (int j = 0; j < W; ++j) {
+        uint32_t s = v[j];
+        uint32_t polls = 0;
+        while ((s & ~LB_VAL) == 0u) {
+            if (++polls > LB_MAX_POLLS) {
+                atomicOr(status, 0x100u);
+                return true;
             }
-            excl += s & LB_VAL;
-            if ((s & ~LB_VAL) == LB_INC || gg - j == g0) return excl;
+            __builtin_amdgcn_s_sleep(1);
+            s = lb_load(&lb[(size_t)(gg - j) * NB + bin]);
         }
-        gg -= LB_WINDOW;
+        excl += s & LB_VAL;
+        if ((s & ~LB_VAL) == LB_INC || gg - j == g0) return true;
     }
+    gg -= W;
+    return false;
+}
+
+__device__ __forceinline__ uint32_t lookback_bin(const uint32_t* lb, uint32_t NB, uint32_t g, uint32_t g0,
+                                                 uint32_t bin, uint32_t* status)
+{
+    uint32_t excl = 0, gg = g - 1u;
+    if (lookback_round<LB_FIRST>(lb, NB, gg, g0, bin, excl, status)) return excl;
+    while (!lookback_round<LB_WINDOW>(lb, NB, gg, g0, bin, excl, status)) {
+    }
+    return excl;
 }
 
 // The digit pass proper, after the caller has loaded the tile into rec/ok
-// and computed dig.  seg_hist: NB digit counts of the whole segment for this
-// pass; seg_off: segment start; lb: look-back words of this pass, tile g of a
-// segment whose first tile is g0.  Calls store(j, pos, r) for every element,
-// j being its tile-local sorted index (consecutive threads get consecutive j)
-// and pos its global position.
+// (first `active` items per thread) and computed dig.  seg_hist: NB digit
+// counts of the whole segment for this pass; seg_off: segment start; lb:
+// look-back words of this pass, tile g of a segment whose first tile is g0.
+// Calls store(j, pos, r) for every element, j being its tile-local sorted
+// index (consecutive threads get consecutive j) and pos its global position.
 template <int RB, int ITEMS, int RW, class Digit, class Store>
-__device__ __forceinline__ void sweep_tile(SweepSmem<RB, ITEMS, RW>& sm, const uint4 (&rec)[ITEMS],
-                                           const bool (&ok)[ITEMS], const uint32_t (&dig)[ITEMS], uint32_t cnt,
+__device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW>& sm, const uint4 (&rec)[ITEMS], const bool (&ok)[ITEMS],
+                                           const uint32_t (&dig)[ITEMS], int active, uint32_t cnt,
                                            const uint32_t* __restrict__ seg_hist, uint32_t seg_off, uint32_t* lb,
                                            uint32_t g, uint32_t g0, uint32_t* status, Digit digit_of, Store store)
 {
     constexpr uint32_t NB = 1u << RB;
-    constexpr uint32_t BPT = NB / BLOCK;      // bins per thread (contiguous)
-    static_assert(NB % BLOCK == 0, "digit bins must be a multiple of the block size");
+    constexpr uint32_t BPT = NB > SWEEP_THREADS ? NB / SWEEP_THREADS : 1u;   // bins per thread (contiguous)
     const uint32_t w = threadIdx.x >> 6;
     uint32_t rnk[ITEMS];
-    wave_multisplit_rb<RB, ITEMS>(dig, ok, rnk, sm.wh + w * NB);
+    wave_multisplit16<RB, ITEMS>(dig, ok, rnk, sm.wh + w * NB, active);
     __syncthreads();
 
     // per-digit tile counts and per-wave exclusive offsets
     const uint32_t t0 = threadIdx.x * BPT;
+    const bool has = t0 < NB;
     uint32_t c[BPT], h[BPT];
     uint32_t csum = 0, hsum = 0;
 #pragma unroll
     for (uint32_t b = 0; b < BPT; ++b) {
+        c[b] = 0;
+        h[b] = 0;
+        if (!has) continue;
         uint32_t run = 0;
 #pragma unroll
-        for (int ww = 0; ww < NWAVE; ++ww) {
+        for (int ww = 0; ww < SWEEP_WAVES; ++ww) {
             const uint32_t x = sm.wh[ww * NB + t0 + b];
-            sm.wh[ww * NB + t0 + b] = run;
+            sm.wh[ww * NB + t0 + b] = (uint16_t)run;
             run += x;
         }
         c[b] = run;
@@ -132,41 +171,57 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, ITEMS, RW>& sm, const u
         h[b] = seg_hist[t0 + b];
         hsum += h[b];
     }
-    // publish this tile's counts before anything else, so successors can go on
+    // publish this tile's counts first, so successors can go on
     const bool first = (g == g0);
+    if (has) {
 #pragma unroll
-    for (uint32_t b = 0; b < BPT; ++b) lb_store(&lb[(size_t)g * NB + t0 + b], (first ? LB_INC : LB_AGG) | c[b]);
-    uint32_t cex = block_excl_scan(csum, sm.sh);
-    uint32_t hex = block_excl_scan(hsum, sm.sh);
-#pragma unroll
-    for (uint32_t b = 0; b < BPT; ++b) {
-        const uint32_t bin = t0 + b;
-        const uint32_t excl = first ? 0u : lookback_window(lb, NB, g, g0, bin, status);
-        if (!first) lb_store(&lb[(size_t)g * NB + bin], LB_INC | (excl + c[b]));
-        sm.dstart[bin] = cex;
-        sm.gbase[bin] = seg_off + hex + excl - cex;
-        cex += c[b];
-        hex += h[b];
+        for (uint32_t b = 0; b < BPT; ++b) lb_store(&lb[(size_t)g * NB + t0 + b], (first ? LB_INC : LB_AGG) | c[b]);
     }
-    __syncthreads();
+    uint32_t cex = sweep_excl_scan(csum, sm.sh);
+    uint32_t hex = sweep_excl_scan(hsum, sm.sh);
+    if (has) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        if (ok[i]) {
-            const uint32_t dst = sm.dstart[dig[i]] + sm.wh[w * NB + dig[i]] + rnk[i];
-            sm.stage[0][dst] = rec[i].x;
-            if constexpr (RW > 1) sm.stage[1][dst] = rec[i].y;
-            if constexpr (RW > 2) sm.stage[2][dst] = rec[i].z;
-            if constexpr (RW > 3) sm.stage[3][dst] = rec[i].w;
+        for (uint32_t b = 0; b < BPT; ++b) {
+            const uint32_t bin = t0 + b;
+            const uint32_t excl = first ? 0u : lookback_bin(lb, NB, g, g0, bin, status);
+            if (!first) lb_store(&lb[(size_t)g * NB + bin], LB_INC | (excl + c[b]));
+            sm.dstart[bin] = cex;
+            sm.gbase[bin] = seg_off + hex + excl - cex;
+            cex += c[b];
+            hex += h[b];
         }
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
-        uint4 r = make_uint4(sm.stage[0][j], 0u, 0u, 0u);
-        if constexpr (RW > 1) r.y = sm.stage[1][j];
-        if constexpr (RW > 2) r.z = sm.stage[2][j];
-        if constexpr (RW > 3) r.w = sm.stage[3][j];
-        const uint32_t d = digit_of(r);
-        store(j, sm.gbase[d] + j, r);
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        dst[i] = 0xFFFFFFFFu;
+        if (i < active && ok[i]) dst[i] = sm.dstart[dig[i]] + sm.wh[w * NB + dig[i]] + rnk[i];
+    }
+    // write-out in rounds of SWEEP_STAGE sorted positions
+    for (uint32_t base = 0; base < cnt; base += SWEEP_STAGE) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i >= active) break;
+            const uint32_t o = dst[i] - base;
+            if (o < SWEEP_STAGE) {
+                sm.stage[0][o] = rec[i].x;
+                if constexpr (RW > 1) sm.stage[1][o] = rec[i].y;
+                if constexpr (RW > 2) sm.stage[2][o] = rec[i].z;
+                if constexpr (RW > 3) sm.stage[3][o] = rec[i].w;
+            }
+        }
+        __syncthreads();
+        const uint32_t m = min(SWEEP_STAGE, cnt - base);
+        for (uint32_t j = threadIdx.x; j < m; j += SWEEP_THREADS) {
+            uint4 r = make_uint4(sm.stage[0][j], 0u, 0u, 0u);
+            if constexpr (RW > 1) r.y = sm.stage[1][j];
+            if constexpr (RW > 2) r.z = sm.stage[2][j];
+            if constexpr (RW > 3) r.w = sm.stage[3][j];
+            const uint32_t d = digit_of(r);
+            store(base + j, sm.gbase[d] + base + j, r);
+        }
+        __syncthreads();
     }
 }
 
