@@ -102,8 +102,41 @@ kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_m
 kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode,
                      hipStream_t stream);
 
-/* Free every workspace cached by kdt_build (synchronises the streams that
- * used them). */
+/*
+ * Batched build: C independent trees (one per cloud) in one call.
+ *
+ * Cloud c is the points [h_offsets[c], h_offsets[c+1]) of d_points (row-major
+ * float32, k per point); its tree, permutation and dimensions go to the same
+ * entry range of d_tree / d_perm / d_dim, exactly as kdt_build_ws would write
+ * them for that cloud alone (d_perm holds indices local to the cloud).  All
+ * clouds share k and dim_mode.  The build is the same sequence of iterations
+ * for every cloud (Sec. 3); one launch runs a step for every cloud that has
+ * that step, each cloud a separate key range of the segmented sorts, so a
+ * batch costs the launches of its largest cloud.
+ *
+ *   h_offsets  host array of C+1 non-decreasing entries, h_offsets[0] = 0,
+ *              h_offsets[C] <= KDT_MAX_POINTS (empty clouds are allowed).
+ *   d_status   nullable; set to KDT_OK, or KDT_ENONFINITE if any coordinate of
+ *              any cloud is NaN or infinite.
+ *   d_ws       at least kdt_batched_workspace_bytes(h_offsets, C, k, mode)
+ *              bytes, 256-byte aligned.
+ *
+ * The first call for a given (h_offsets, k, mode) plans the batch on the host
+ * and keeps the plan, with its launch tables in pinned host memory, until
+ * kdt_release_cached(); each call uploads the tables into d_ws on `stream`.
+ * Apart from that first planning the call neither allocates nor
+ * synchronises, so it can be captured into a HIP graph (the graph then
+ * refers to the cached tables: release the cache only after the graph).
+ */
+size_t kdt_batched_workspace_bytes(const uint32_t* h_offsets, uint32_t C, uint32_t k, int dim_mode);
+
+kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C,
+                             uint32_t k, int dim_mode, float* d_tree, uint32_t* d_perm,
+                             uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* Free every workspace cached by kdt_build and every cached batch plan
+ * (synchronises the device first). */
 void kdt_release_cached(void);
 
 /*

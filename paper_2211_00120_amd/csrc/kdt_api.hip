@@ -1,11 +1,21 @@
 // kdt_api.hip -- host driver and C ABI (include/kdt.h) of the k-d tree build.
 //
-// The driver validates arguments, carves the caller's workspace, and
-// enqueues the kernel sequence of one build on the caller's stream:
+// A call builds a list of independent trees (one for kdt_build_ws, one per
+// cloud for kdt_build_batched).  The planner splits them:
 //
-//   init, prep, [root dim], k presorts x 4 passes, iteration 0,
-//   iterations 1.. with segmented onesweep passes while a subtree is larger
-//   than one workgroup's tile, then block-local iterations down to L-2.
+//   * a tree of at most TAIL_CAP points is built whole by one workgroup
+//     (k_tail from the points: keys, per-dimension orders and every
+//     iteration in LDS);
+//   * larger trees go through init, prep, [root dims], k presorts x 4
+//     passes, iteration 0, then iterations 1.. as segmented onesweep passes
+//     while some subtree is larger than TAIL_CAP, then one tail launch that
+//     runs each tree's remaining iterations, each tree from its own level.
+//
+// Every launch covers all trees that have work at that step, so the launch
+// count of a batch is that of its largest tree.  With a single share the
+// share travels in the kernel arguments; otherwise the launch reads a table
+// that the call uploads into its workspace (from pinned host memory that the
+// plan cache owns).
 //
 // The loop bounds follow the paper's iteration count with the two savings of
 // Sec. 7.1: entries of fixed nodes are dropped from every iteration, and the
@@ -17,16 +27,21 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
-#include <vector>
+#include <memory>
 #include <mutex>
+#include <string>
 #include <utility>
+#include <vector>
 
 #include "../../include/kdt.h"
 #include "kdt_kernels.h"
 #include "kdt_layout.h"
 
 namespace {
+
+using namespace kdt;
 
 thread_local char g_err[512] = "";
 
@@ -40,104 +55,251 @@ void set_err(const char* fmt, ...)
 
 constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+constexpr uint32_t NONE = 0xFFFFFFFFu;
 
-// Everything about one build that depends only on (n, k, mode).
-struct Plan {
-    uint32_t n = 0, k = 0;
-    bool widest = false;
-    uint32_t L = 0;            // levels of the tree
-    uint32_t B = 0;            // bits of a rank
-    uint32_t P = 0;            // digit passes per level sort
-    uint32_t RB = 8;           // bits per digit of the level sorts
-    uint32_t first_local = 0;  // first iteration run block-locally
-    uint32_t max_tiles = 1;    // look-back words per buffer / 256
-    uint32_t max_hist_segs = 2;
-    // workspace offsets (bytes)
-    size_t o_ctl, o_counters, o_hist_rank, o_hist[2], o_lb[2], o_keys, o_perms, o_ranks, o_rec, o_nodeperm,
-        o_dimnode, o_box[2], total;
-    size_t rec_words;          // words per record buffer
-};
-
-// Records per thread of the level-l sort tiles (tile = 512 * items): the
-// largest tile that the level's biggest subtree still fills.
 #ifndef KDT_LEVEL_MAX_ITEMS
 #define KDT_LEVEL_MAX_ITEMS 8
 #endif
-uint32_t level_items(uint32_t n, uint32_t l)
+
+// Records per thread of an iteration's sort tiles (tile = 512 * items): the
+// largest tile that the iteration's biggest subtree still fills.
+uint32_t level_items(uint32_t big)
 {
-    const kdt::Level v = kdt::make_level(n, l);
-    const uint32_t big = 2u * v.W - 1u;
-    uint32_t items = big >= 8192u ? 16u : (big >= 4096u ? 8u : 4u);
+    const uint32_t items = big >= 4096u ? 8u : 4u;
     return items < KDT_LEVEL_MAX_ITEMS ? items : KDT_LEVEL_MAX_ITEMS;
 }
 
-bool level_is_global(const Plan& p, uint32_t l)
+// First iteration at which every subtree of an n-point tree (n > TAIL_CAP)
+// holds at most TAIL_CAP points; the largest subtree of iteration l has
+// 2^(L-l) - 1 points.  Always in 1 .. L-2.
+uint32_t first_tail_level(uint32_t n)
 {
-    return l >= 1 && l + 2 <= p.L && l < p.first_local;
+    const uint32_t L = num_levels(n);
+    uint32_t l = 1;
+    while (l + 2 <= L && (1u << (L - l)) - 1u > TAIL_CAP) ++l;
+    return l;
 }
 
-Plan make_plan(uint32_t n, uint32_t k, bool widest)
+TreeStep step(uint32_t tree, uint32_t level, uint32_t tile0)
 {
-    using namespace kdt;
+    TreeStep s{};
+    s.tree = tree;
+    s.level = level;
+    s.tile0 = tile0;
+    s.hist = 0;
+    s.hist_next = NONE;
+    s.G = 0;
+    s.buf = 0;
+    return s;
+}
+
+// One iteration run as digit passes over every tree that still has subtrees
+// larger than TAIL_CAP.
+struct LevelLaunch {
+    uint32_t level = 0;
+    uint32_t items = 4;              // records per thread of its sort tiles
+    uint32_t tiles = 0;              // sort tiles
+    uint32_t hist_tiles = 0;         // split-widest histogram tiles
+    uint32_t hist_words = 0;         // words of its digit histograms
+    std::vector<TreeStep> steps;     // sort shares
+    std::vector<TreeStep> hsteps;    // split-widest histogram shares (tiles of HIST_TILE)
+};
+
+// Everything about one call that depends only on the tree sizes, k and mode.
+struct Plan {
+    uint32_t k = 0;
+    bool widest = false;
+    uint64_t ntotal = 0;
+    std::vector<TreeInfo> trees;     // every tree of the call
+    std::vector<uint32_t> large;     // trees built by digit passes
+    std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
+    uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / passes of the level sorts
+    std::vector<TreeStep> prep, presort, level0, tail, roots;
+    uint32_t prep_tiles = 0, presort_tiles = 0, tail_groups = 0;
+    std::vector<LevelLaunch> levels; // iterations 1.. run as passes
+    uint32_t hist_words = 0;         // per parity half of the histogram region
+    uint32_t lb_words = 0;           // per look-back buffer
+    uint32_t box_entries = 0;        // per split-widest domain buffer
+    std::vector<uint32_t> pass_words;// look-back words of every onesweep pass, in order
+    bool tables = false;             // some launch reads a device share table
+    std::vector<uint8_t> blob;       // the share tables, as uploaded
+    size_t t_trees = 0, t_small = 0, t_prep = 0, t_presort = 0, t_level0 = 0, t_tail = 0, t_roots = 0;
+    std::vector<size_t> t_level, t_hist;
+    // workspace offsets (bytes)
+    size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,
+           o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_tables = 0,
+           total = 0;
+    size_t rec_words = 0;            // words per record buffer
+};
+
+size_t push_table(std::vector<uint8_t>& blob, const void* p, size_t bytes)
+{
+    const size_t at = blob.size();
+    blob.resize(align_up(at + bytes));
+    if (bytes) memcpy(blob.data() + at, p, bytes);
+    return at;
+}
+
+Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest)
+{
     Plan p;
-    p.n = n;
     p.k = k;
     p.widest = widest;
-    p.L = num_levels(n);
-    p.B = rank_bits(n);
-    // fewest digit passes over a B-bit rank with 8..10-bit digits, then the
-    // narrowest digit that keeps that pass count
-    {
-        const uint32_t pmin = p.B ? (p.B + 9u) / 10u : 0u;
+    const uint32_t T = (uint32_t)n.size();
+    p.trees.resize(T);
+    uint64_t off = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+        p.trees[t] = TreeInfo{(uint32_t)off, n[t], 0u, 0u};
+        off += n[t];
+    }
+    p.ntotal = off;
+
+    for (uint32_t t = 0; t < T; ++t) {
+        if (n[t] == 0) continue;
+        if (n[t] <= TAIL_CAP) {
+            TreeStep s = step(t, 0u, (uint32_t)p.small.size());
+            s.G = 1;
+            p.small.push_back(s);
+        } else {
+            p.trees[t].idx = (uint32_t)p.large.size();
+            p.large.push_back(t);
+        }
+    }
+
+    // digit width of the level sorts: fewest passes over the largest rank
+    // with 8..10-bit digits, then the narrowest digit that keeps that count
+    // (a tree of more than TAIL_CAP points has ranks of >= 12 bits, so P >= 2)
+    for (uint32_t t : p.large) p.B = std::max(p.B, rank_bits(n[t]));
+    if (p.B) {
+        const uint32_t pmin = (p.B + 9u) / 10u;
         p.RB = 10;
         for (uint32_t rb = 8; rb <= 10; ++rb)
-            if (p.B == 0 || (p.B + rb - 1u) / rb == pmin) { p.RB = rb; break; }
-        p.P = p.B ? (p.B + p.RB - 1u) / p.RB : 0u;
+            if ((p.B + rb - 1u) / rb == pmin) {
+                p.RB = rb;
+                break;
+            }
+        p.P = (p.B + p.RB - 1u) / p.RB;
     }
-    // first iteration whose largest subtree (2W - 1 points) fits a local tile
-    p.first_local = 1;
-    while (p.first_local + 2 <= p.L) {
-        const uint32_t W = 1u << (p.L - p.first_local - 1u);
-        if (2u * W - 1u <= TAIL_CAP) break;
-        ++p.first_local;
+    const uint32_t NB = 1u << p.RB;
+
+    // per-tree shares of the whole-array steps
+    std::vector<uint32_t> l0(T, 0);
+    uint32_t maxl = 0;
+    for (uint32_t t : p.large) {
+        TreeInfo& ti = p.trees[t];
+        l0[t] = first_tail_level(ti.n);
+        maxl = std::max(maxl, l0[t]);
+        ti.box_off = p.box_entries;
+        p.box_entries += 1u << l0[t];     // subtrees of the deepest iteration with a domain table
+        p.prep.push_back(step(t, 0u, p.prep_tiles));
+        p.level0.push_back(step(t, 0u, p.prep_tiles));
+        p.prep_tiles += ceil_div(ti.n, PREP_TILE);
+        p.presort.push_back(step(t, 0u, p.presort_tiles));
+        p.presort_tiles += ceil_div(ti.n, PRESORT_TILE);
+        p.roots.push_back(step(t, 0u, 0u));
     }
-    p.max_tiles = n ? ceil_div(n, PRESORT_TILE) : 1u;
-    for (uint32_t l = 1; l + 2 <= p.L; ++l) {
-        if (!level_is_global(p, l)) continue;
-        const Level v = make_level(n, l);
-        const SegTiles t = tiles_level(v, 512u * level_items(n, l));
-        if (t.tiles > p.max_tiles) p.max_tiles = t.tiles;
-        if (v.nseg * 2u > p.max_hist_segs) p.max_hist_segs = v.nseg * 2u;
+
+    // iterations 1 .. run as digit passes (tree t takes part while l < l0[t])
+    for (uint32_t l = 1; l < maxl; ++l) {
+        LevelLaunch ll;
+        ll.level = l;
+        uint32_t big = 0;
+        for (uint32_t t : p.large)
+            if (l < l0[t]) big = std::max(big, (1u << (num_levels(n[t]) - l)) - 1u);
+        ll.items = level_items(big);
+        for (uint32_t t : p.large) {
+            if (l >= l0[t]) continue;
+            const Level v = make_level(n[t], l);
+            TreeStep s = step(t, l, ll.tiles);
+            s.hist = ll.hist_words;
+            ll.tiles += tiles_level(v, 512u * ll.items).tiles;
+            ll.hist_words += v.nseg * p.P * NB;
+            ll.steps.push_back(s);
+            TreeStep h = step(t, l, ll.hist_tiles);
+            ll.hist_tiles += tiles_level(v, HIST_TILE).tiles;
+            ll.hsteps.push_back(h);
+        }
+        p.hist_words = std::max(p.hist_words, ll.hist_words);
+        p.levels.push_back(std::move(ll));
     }
-    const size_t N = n;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o = off;
-        off = align_up(off + bytes);
-        return o;
+    // iteration l's histograms live in half (l & 1) of the histogram region
+    for (LevelLaunch& ll : p.levels) {
+        const uint32_t base = (ll.level & 1u) * p.hist_words;
+        for (size_t i = 0; i < ll.steps.size(); ++i) {
+            ll.steps[i].hist += base;
+            ll.hsteps[i].hist = ll.steps[i].hist;
+        }
+    }
+    // each share's histogram offset for the next iteration
+    auto next_hist = [&](size_t li, uint32_t tree) {
+        if (li >= p.levels.size()) return NONE;
+        for (const TreeStep& s : p.levels[li].steps)
+            if (s.tree == tree) return s.hist;
+        return NONE;
     };
-    p.o_ctl = take(CTL_WORDS * 4);
+    for (size_t li = 0; li < p.levels.size(); ++li)
+        for (TreeStep& s : p.levels[li].steps) s.hist_next = next_hist(li + 1, s.tree);
+    for (TreeStep& s : p.level0) s.hist_next = next_hist(0, s.tree);
+
+    // the tail of every large tree from its own first tail iteration; the
+    // level sorts flip the record buffer once per pass
+    for (uint32_t t : p.large) {
+        const Level v = make_level(n[t], l0[t]);
+        const uint32_t G = std::max(1u, std::min({TAIL_CAP / ((1u << (v.L - v.l)) - 1u), v.nseg, 2u}));
+        TreeStep s = step(t, l0[t], p.tail_groups);
+        s.G = G;
+        s.buf = ((l0[t] - 1u) * p.P) & 1u;
+        p.tail.push_back(s);
+        p.tail_groups += ceil_div(v.nseg, G);
+    }
+
+    // look-back words per pass, in the order the passes run
+    if (!p.large.empty())
+        for (uint32_t q = 0; q < 4u * k; ++q) p.pass_words.push_back(p.presort_tiles * RADIX_HOST);
+    for (const LevelLaunch& ll : p.levels)
+        for (uint32_t q = 0; q < p.P; ++q) p.pass_words.push_back(ll.tiles * NB);
+    for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
+
+    // share tables
+    p.t_trees = push_table(p.blob, p.trees.data(), p.trees.size() * sizeof(TreeInfo));
+    p.t_small = push_table(p.blob, p.small.data(), p.small.size() * sizeof(TreeStep));
+    p.t_prep = push_table(p.blob, p.prep.data(), p.prep.size() * sizeof(TreeStep));
+    p.t_presort = push_table(p.blob, p.presort.data(), p.presort.size() * sizeof(TreeStep));
+    p.t_level0 = push_table(p.blob, p.level0.data(), p.level0.size() * sizeof(TreeStep));
+    p.t_tail = push_table(p.blob, p.tail.data(), p.tail.size() * sizeof(TreeStep));
+    p.t_roots = push_table(p.blob, p.roots.data(), p.roots.size() * sizeof(TreeStep));
+    p.tables = p.small.size() > 1 || p.large.size() > 1;
+    for (const LevelLaunch& ll : p.levels) {
+        p.t_level.push_back(push_table(p.blob, ll.steps.data(), ll.steps.size() * sizeof(TreeStep)));
+        p.t_hist.push_back(push_table(p.blob, ll.hsteps.data(), ll.hsteps.size() * sizeof(TreeStep)));
+    }
+
+    // workspace
+    const size_t N = p.ntotal;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + bytes);
+        return r;
+    };
+    p.o_status = take(64);
     p.o_counters = take(MAX_PASSES * 4);
-    p.o_hist_rank = take((size_t)k * 4 * RADIX_HOST * 4);
-    const size_t hist_bytes = (size_t)p.max_hist_segs * (p.P ? p.P : 1u) * (1u << p.RB) * 4;
-    p.o_hist[0] = take(hist_bytes);
-    p.o_hist[1] = take(hist_bytes);
-    const size_t lb_bytes = (size_t)p.max_tiles * MAX_BINS * 4;
-    p.o_lb[0] = take(lb_bytes);
-    p.o_lb[1] = take(lb_bytes);
+    p.o_hist_rank = take((size_t)p.large.size() * k * 4 * RADIX_HOST * 4);
+    p.o_hist = take((size_t)p.hist_words * 2 * 4);
+    p.o_lb[0] = take((size_t)p.lb_words * 4);
+    p.o_lb[1] = take((size_t)p.lb_words * 4);
     p.o_keys = take(N * k * 4);
     p.o_perms = take(N * k * 4);
     p.o_ranks = take(N * k * 4);
-    p.rec_words = N * k > 2 * N ? N * k : 2 * N;     // also holds the presort's (key, value) ping-pong
+    p.rec_words = std::max(N * k, 2 * N);   // also holds the presort's (key, index) ping-pong
     p.o_rec = take(p.rec_words * 2 * 4);
     p.o_nodeperm = take(N * 4);
     p.o_dimnode = take(N);
-    // split-widest domain tables: levels up to the tail's first level
-    const uint32_t box_level = p.L >= 2 ? (p.first_local < p.L - 2 ? p.first_local : p.L - 2) : 0u;
-    const size_t box_bytes = ((size_t)1 << box_level) * 8 * 4;
-    p.o_box[0] = take(box_bytes);
-    p.o_box[1] = take(box_bytes);
-    p.total = off;
+    p.o_box[0] = take((size_t)p.box_entries * 8 * 4);
+    p.o_box[1] = take((size_t)p.box_entries * 8 * 4);
+    p.o_bbox = take((size_t)p.large.size() * 8 * 4);
+    p.o_tables = take(p.tables ? p.blob.size() : 0);
+    p.total = o;
     return p;
 }
 
@@ -163,11 +325,12 @@ kdt_status check_launch(const char* what)
 // ------------------------------------------------------------ profiling
 // While enabled, every kernel enqueued by a build is bracketed by two
 // hipEvents on the build's stream and tagged with its kind and algorithmic
-// bytes (the bytes the step must move by definition; see DESIGN.md).
+// bytes (the bytes the step must move by definition).
 enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_HIST, KIND_PASS, KIND_TAIL,
-            KIND_STATUS, KIND_COUNT };
-const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass", "k_level0",
-                                            "k_level_hist", "k_level_pass", "k_tail", "k_word"};
+            KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_COUNT };
+const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
+                                            "k_level0", "k_level_hist", "k_level_pass", "k_tail",
+                                            "k_tail_whole", "share_tables", "k_word"};
 
 struct ProfRec {
     int kind;
@@ -192,7 +355,7 @@ struct Profiler {
 };
 Profiler g_prof;
 
-// Enqueue one kernel through `fn`, with profiling events when enabled.
+// Enqueue one kernel (or copy) through `fn`, with profiling events when enabled.
 template <class F>
 kdt_status run_kernel(hipStream_t st, int kind, double bytes, F&& fn)
 {
@@ -214,7 +377,7 @@ kdt_status run_kernel(hipStream_t st, int kind, double bytes, F&& fn)
     return KDT_OK;
 }
 
-kdt_status validate(const float* pts, uint32_t n, uint32_t k, int mode)
+kdt_status validate_k_mode(uint32_t k, int mode)
 {
     if (k < 1 || k > 4) {
         set_err("k must be in 1..4 (got %u)", k);
@@ -222,14 +385,6 @@ kdt_status validate(const float* pts, uint32_t n, uint32_t k, int mode)
     }
     if (mode != KDT_DIM_ROUND_ROBIN && mode != KDT_DIM_WIDEST) {
         set_err("dim_mode must be KDT_DIM_ROUND_ROBIN or KDT_DIM_WIDEST (got %d)", mode);
-        return KDT_EINVAL;
-    }
-    if (n > KDT_MAX_POINTS) {
-        set_err("n = %u exceeds KDT_MAX_POINTS", n);
-        return KDT_EINVAL;
-    }
-    if (n > 0 && !pts) {
-        set_err("points is null");
         return KDT_EINVAL;
     }
     return KDT_OK;
@@ -243,190 +398,315 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb)
     return x < y + nb && y < x + na;
 }
 
-kdt_status enqueue_build(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim,
-                         uint32_t* status, char* ws, hipStream_t st)
+// Checks shared by the caller-workspace entry points.
+kdt_status validate_buffers(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim,
+                            uint32_t* status, void* ws, size_t ws_bytes)
 {
-    using namespace kdt;
-    const uint32_t n = p.n, k = p.k;
+    if (p.ntotal > 0 && !pts) {
+        set_err("points is null");
+        return KDT_EINVAL;
+    }
+    if (!ws || ws_bytes < p.total) {
+        set_err("workspace of %zu bytes needed (got %zu)", p.total, ws ? ws_bytes : (size_t)0);
+        return KDT_EINVAL;
+    }
+    if (((uintptr_t)ws) % ALIGN) {
+        set_err("workspace must be %zu-byte aligned", ALIGN);
+        return KDT_EINVAL;
+    }
+    const size_t n = p.ntotal;
+    const size_t pb = n * p.k * 4;
+    if (overlaps(pts, pb, tree, pb) || overlaps(pts, pb, perm, n * 4) || overlaps(pts, pb, dim, n) ||
+        overlaps(pts, pb, ws, ws_bytes) || overlaps(tree, pb, ws, ws_bytes) || overlaps(perm, n * 4, ws, ws_bytes) ||
+        overlaps(dim, n, ws, ws_bytes) || overlaps(status, 4, ws, ws_bytes)) {
+        set_err("points, outputs and workspace must not overlap");
+        return KDT_EINVAL;
+    }
+    return KDT_OK;
+}
+
+// Shares of one launch: inline for a single share, else the device table.
+Shares shares(const Plan& p, const std::vector<TreeStep>& steps, size_t table_off, const char* ws)
+{
+    Shares s{};
+    s.nsteps = (uint32_t)steps.size();
+    if (steps.size() == 1) {
+        s.step0 = steps[0];
+        s.tree0 = p.trees[steps[0].tree];
+    } else {
+        s.trees = (const TreeInfo*)(ws + p.o_tables + p.t_trees);
+        s.steps = (const TreeStep*)(ws + p.o_tables + table_off);
+    }
+    return s;
+}
+
+// Enqueue every kernel of a planned call on `st`.  h_tables: the plan's
+// share tables in pinned host memory (needed when p.tables).
+kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim, uint32_t* status,
+                   char* ws, const void* h_tables, hipStream_t st)
+{
+    const uint32_t k = p.k;
     const bool widest = p.widest;
-    uint32_t* ctl = (uint32_t*)(ws + p.o_ctl);
+    const double K = k;
+    uint32_t* dstatus = (uint32_t*)(ws + p.o_status);
     uint32_t* counters = (uint32_t*)(ws + p.o_counters);
     uint32_t* hist_rank = (uint32_t*)(ws + p.o_hist_rank);
-    uint32_t* hist[2] = {(uint32_t*)(ws + p.o_hist[0]), (uint32_t*)(ws + p.o_hist[1])};
+    uint32_t* hist = (uint32_t*)(ws + p.o_hist);
     uint32_t* lb[2] = {(uint32_t*)(ws + p.o_lb[0]), (uint32_t*)(ws + p.o_lb[1])};
     uint32_t* keys = (uint32_t*)(ws + p.o_keys);
     uint32_t* perms = (uint32_t*)(ws + p.o_perms);
     uint32_t* ranks = (uint32_t*)(ws + p.o_ranks);
     uint32_t* recbase = (uint32_t*)(ws + p.o_rec);
     uint32_t* rec[2] = {recbase, recbase + p.rec_words};
-    uint32_t* nodeperm = perm ? perm : (uint32_t*)(ws + p.o_nodeperm);
-    uint8_t* dimnode = (widest && dim) ? dim : (uint8_t*)(ws + p.o_dimnode);
-
-    if (n == 0) return KDT_OK;
-
-    // Onesweep passes of the build, in order, with their tile counts: the
-    // look-back buffer of pass q is lb[q & 1], cleared by pass q-1 (or init).
-    const uint32_t presort_tiles = ceil_div(n, PRESORT_TILE);
-    // (look-back words a pass uses = its tiles * its digit values)
-    uint32_t pass_words[MAX_PASSES];
-    uint32_t npass = 0;
-    for (uint32_t d = 0; d < k; ++d)
-        for (int q = 0; q < 4; ++q) pass_words[npass++] = presort_tiles * RADIX_HOST;
-    for (uint32_t l = 1; l + 2 <= p.L; ++l)
-        if (level_is_global(p, l)) {
-            const uint32_t t = tiles_level(make_level(n, l), 512u * level_items(n, l)).tiles;
-            for (uint32_t q = 0; q < p.P; ++q) pass_words[npass++] = t << p.RB;
-        }
-    auto next_words = [&](uint32_t q) { return q + 1 < npass ? pass_words[q + 1] : 0u; };
-    const uint32_t NBL = 1u << p.RB;
-
-    const bool level1_global = level_is_global(p, 1);
-    const double N = n, K = k;
-    if (kdt_status s = run_kernel(st, KIND_INIT, 4.0 * (pass_words[0] + (k * 4 + 2 * p.P) * RADIX_HOST), [&] {
-            launch_init(ctl, counters, hist_rank, k * 4 * RADIX_HOST, lb[0], pass_words[0],
-                        level1_global ? hist[1] : nullptr, 2u * p.P * NBL, st);
-        }))
-        return s;
-    if (kdt_status s = run_kernel(st, KIND_PREP, N * 8.0 * K,
-                                  [&] { launch_prep((int)k, pts, n, keys, hist_rank, ctl, widest, st); }))
-        return s;
-    if (widest)
-        if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0,
-                                      [&] { launch_root_dim((int)k, ctl, dimnode, (float*)(ws + p.o_box[0]), st); }))
-            return s;
-
-    // presort: per dimension, 4 stable digit passes of (key, index)
-    uint32_t q = 0;
-    // (key, index) ping-pong of the presort: two n-pair arrays inside the
-    // record region (2 * rec_words >= 4n words), free until iteration 0
-    uint32_t* kv[2] = {recbase, recbase + 2 * (size_t)n};
-    for (uint32_t d = 0; d < k; ++d) {
-        for (uint32_t ps = 0; ps < 4; ++ps, ++q) {
-            PresortArgs a{};
-            a.kin = keys + (size_t)d * n;
-            a.kvin = ps == 0 ? nullptr : kv[(ps - 1) & 1];
-            a.kvout = kv[ps & 1];
-            a.hist = hist_rank + (d * 4 + ps) * RADIX_HOST;
-            a.lb = lb[q & 1];
-            a.lb_zero = lb[(q + 1) & 1];
-            a.lb_zero_n = next_words(q);
-            a.counter = counters + q;
-            a.n = n;
-            a.shift = 8 * ps;
-            a.perm_out = perms + (size_t)d * n;
-            a.rank_table = ranks;
-            a.k = k;
-            a.dim = d;
-            a.status = ctl + CTL_STATUS;
-            if (kdt_status s = run_kernel(st, KIND_PRESORT, N * (ps == 0 ? 12.0 : 16.0),
-                                          [&] { launch_presort_pass(a, ps == 0, ps == 3, presort_tiles, st); }))
-                return s;
-        }
-    }
+    const uint32_t ntotal = (uint32_t)p.ntotal;
+    const uint32_t nlarge_trees = (uint32_t)p.large.size();
 
     Outs o{};
     o.pts = pts;
     o.tree = tree;
     o.dim = widest ? nullptr : dim;
-    o.nodeperm = nodeperm;
-    o.dimnode = dimnode;
+    o.nodeperm = perm ? perm : (uint32_t*)(ws + p.o_nodeperm);
+    o.dimnode = (widest && dim) ? dim : (uint8_t*)(ws + p.o_dimnode);
     o.perm0 = perms;
-    o.ctl = ctl;
-    o.status = ctl + CTL_STATUS;
+    o.status = dstatus;
     o.box[0] = (float*)(ws + p.o_box[0]);
     o.box[1] = (float*)(ws + p.o_box[1]);
-    o.n = n;
+    o.bbox = (uint32_t*)(ws + p.o_bbox);
 
-    // iteration 0
-    int cur = 0;    // record buffer holding the current iteration's input
-    {
-        Level0Args a{};
-        a.perms = perms;
-        a.rank_table = ranks;
-        a.rout = rec[cur];
-        a.hist_next = (level1_global && !widest) ? hist[1] : nullptr;
-        a.next_passes = p.P;
-        a.radix_bits = p.RB;
-        a.o = o;
-        if (kdt_status s = run_kernel(st, KIND_LEVEL0, N * (4.0 + 8.0 * K),
-                                      [&] { launch_level0((int)k, a, widest, st); }))
+    if (p.tables) {
+        if (!h_tables) {
+            set_err("internal: share tables missing");
+            return KDT_EINVAL;
+        }
+        if (kdt_status s = run_kernel(st, KIND_TABLES, (double)p.blob.size(), [&] {
+                (void)hipMemcpyAsync(ws + p.o_tables, h_tables, p.blob.size(), hipMemcpyHostToDevice, st);
+            }))
             return s;
     }
 
-    // iterations 1 .. L-2
-    for (uint32_t l = 1; l + 2 <= p.L; ++l) {
-        const Level v = make_level(n, l);
-        if (level_is_global(p, l)) {
-            const uint32_t items = level_items(n, l);
-            const SegTiles tl = tiles_level(v, 512u * items);
-            uint32_t* h = hist[l & 1];
-            if (widest) {
-                LevelHistArgs ha{};
-                ha.rin = rec[cur];
-                ha.dimnode = dimnode;
-                ha.hist = h;
-                ha.passes = p.P;
-                ha.radix_bits = p.RB;
-                ha.v = v;
-                ha.tl = tiles_level(v, HIST_TILE);
-                ha.status = ctl + CTL_STATUS;
-                if (kdt_status s = run_kernel(st, KIND_HIST, (double)(n - v.Fl) * 4.0 * K,
-                                              [&] { launch_level_hist((int)k, ha, st); }))
+    // the look-back buffer of onesweep pass q is lb[q & 1]; init clears the
+    // first one, pass q clears the one of pass q+1
+    const std::vector<uint32_t>& pw = p.pass_words;
+    auto next_words = [&](uint32_t q) { return q + 1 < pw.size() ? pw[q + 1] : 0u; };
+    const uint32_t hist1_words = p.levels.empty() ? 0u : p.levels[0].hist_words;
+
+    if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, [&] {
+            launch_init(dstatus, counters, hist_rank, nlarge_trees * k * 4 * RADIX_HOST, lb[0],
+                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist1_words, o.bbox,
+                        widest ? nlarge_trees : 0u, st);
+        }))
+        return s;
+
+    // ---- whole trees of at most TAIL_CAP points ----
+    if (!p.small.empty()) {
+        TailArgs a{};
+        a.sh = shares(p, p.small, p.t_small, ws);
+        a.from_points = 1;
+        a.o = o;
+        double bytes = 0;
+        for (const TreeStep& s : p.small) bytes += p.trees[s.tree].n * (8.0 * K + 4.0);
+        if (kdt_status s = run_kernel(st, KIND_WHOLE, bytes,
+                                      [&] { launch_tail((int)k, a, (uint32_t)p.small.size(), widest, st); }))
+            return s;
+    }
+
+    if (!p.large.empty()) {
+        double nlarge = 0;
+        for (uint32_t t : p.large) nlarge += p.trees[t].n;
+        PrepArgs pa{};
+        pa.sh = shares(p, p.prep, p.t_prep, ws);
+        pa.keys = keys;
+        pa.hist = hist_rank;
+        pa.ntotal = ntotal;
+        pa.o = o;
+        if (kdt_status s = run_kernel(st, KIND_PREP, nlarge * 8.0 * K,
+                                      [&] { launch_prep((int)k, pa, p.prep_tiles, widest, st); }))
+            return s;
+        if (widest)
+            if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, [&] {
+                    launch_root_dim((int)k, shares(p, p.roots, p.t_roots, ws), o, nlarge_trees, st);
+                }))
+                return s;
+
+        // presort: per dimension, 4 stable digit passes of (key, index); the
+        // (key, index) ping-pong lives in the record region (2 * rec_words >=
+        // 4 * ntotal words), which is free until iteration 0
+        uint32_t q = 0;
+        uint32_t* kv[2] = {recbase, recbase + 2 * (size_t)ntotal};
+        for (uint32_t d = 0; d < k; ++d) {
+            for (uint32_t ps = 0; ps < 4; ++ps, ++q) {
+                PresortArgs a{};
+                a.sh = shares(p, p.presort, p.t_presort, ws);
+                a.kin = keys + (size_t)d * ntotal;
+                a.kvin = ps == 0 ? nullptr : kv[(ps - 1) & 1];
+                a.kvout = kv[ps & 1];
+                a.hist = hist_rank + (d * 4 + ps) * RADIX_HOST;
+                a.hist_stride = k * 4 * RADIX_HOST;
+                a.lb = lb[q & 1];
+                a.lb_zero = lb[(q + 1) & 1];
+                a.lb_zero_n = next_words(q);
+                a.counter = counters + q;
+                a.shift = 8 * ps;
+                a.perm_out = perms + (size_t)d * ntotal;
+                a.rank_table = ranks;
+                a.k = k;
+                a.dim = d;
+                a.status = dstatus;
+                if (kdt_status s = run_kernel(st, KIND_PRESORT, nlarge * (ps == 0 ? 12.0 : 16.0), [&] {
+                        launch_presort_pass(a, ps == 0, ps == 3, p.presort_tiles, st);
+                    }))
                     return s;
             }
-            const bool next_global = level_is_global(p, l + 1);
-            const uint32_t next_hist_n = next_global ? 2u * v.nseg * p.P * NBL : 0u;
+        }
+
+        // iteration 0 writes the records of iteration 1 into rec[0]
+        int cur = 0;
+        {
+            Level0Args a{};
+            a.sh = shares(p, p.level0, p.t_level0, ws);
+            a.perms = perms;
+            a.rank_table = ranks;
+            a.rout = rec[cur];
+            a.hist = (!widest && !p.levels.empty()) ? hist : nullptr;
+            a.ntotal = ntotal;
+            a.passes = p.P;
+            a.radix_bits = p.RB;
+            a.o = o;
+            if (kdt_status s = run_kernel(st, KIND_LEVEL0, nlarge * (4.0 + 8.0 * K),
+                                          [&] { launch_level0((int)k, a, p.prep_tiles, widest, st); }))
+                return s;
+        }
+
+        // iterations 1 .. as segmented digit passes
+        for (size_t li = 0; li < p.levels.size(); ++li) {
+            const LevelLaunch& ll = p.levels[li];
+            const uint32_t l = ll.level;
+            double live = 0;
+            for (const TreeStep& s : ll.steps) live += p.trees[s.tree].n - full_nodes(l);
+            if (widest) {
+                LevelHistArgs ha{};
+                ha.sh = shares(p, ll.hsteps, p.t_hist[li], ws);
+                ha.rin = rec[cur];
+                ha.hist = hist;
+                ha.passes = p.P;
+                ha.radix_bits = p.RB;
+                ha.o = o;
+                if (kdt_status s = run_kernel(st, KIND_HIST, live * 4.0 * K,
+                                              [&] { launch_level_hist((int)k, ha, ll.hist_tiles, st); }))
+                    return s;
+            }
+            const uint32_t next_hist_words = li + 1 < p.levels.size() ? p.levels[li + 1].hist_words : 0u;
             for (uint32_t ps = 0; ps < p.P; ++ps, ++q) {
                 const bool last = ps + 1 == p.P;
                 LevelPassArgs a{};
+                a.sh = shares(p, ll.steps, p.t_level[li], ws);
                 a.rin = rec[cur];
                 a.rout = rec[cur ^ 1];
-                a.hist = h;
+                a.hist = hist;
                 a.passes = p.P;
                 a.pass = ps;
                 a.shift = p.RB * ps;
                 a.radix_bits = p.RB;
-                a.items = items;
+                a.items = ll.items;
                 a.lb = lb[q & 1];
                 a.lb_zero = lb[(q + 1) & 1];
                 a.lb_zero_n = next_words(q);
-                a.zero2 = (ps == 0 && next_global) ? hist[(l + 1) & 1] : nullptr;
-                a.zero2_n = (ps == 0) ? next_hist_n : 0u;
+                // pass 0 clears the next iteration's histogram half (P >= 2,
+                // so that happens a launch before anything accumulates there)
+                a.zero2 = (ps == 0 && next_hist_words) ? hist + ((l + 1u) & 1u) * p.hist_words : nullptr;
+                a.zero2_n = ps == 0 ? next_hist_words : 0u;
                 a.counter = counters + q;
-                a.v = v;
-                a.tl = tl;
-                a.dim_rr = l % k;
-                a.hist_next = (last && next_global && !widest) ? hist[(l + 1) & 1] : nullptr;
-                a.next_passes = p.P;
-                a.dim_next_rr = (l + 1) % k;
+                a.k = k;
+                a.acc_next = (last && !widest && next_hist_words) ? 1u : 0u;
                 a.o = o;
-                if (kdt_status s = run_kernel(st, KIND_PASS, (double)(n - v.Fl) * 8.0 * K,
-                                              [&] { launch_level_pass((int)k, a, last, widest, st); }))
+                if (kdt_status s = run_kernel(st, KIND_PASS, live * 8.0 * K,
+                                              [&] { launch_level_pass((int)k, a, ll.tiles, last, widest, st); }))
                     return s;
                 cur ^= 1;
             }
-        } else {
-            // every subtree of iteration l fits one workgroup: the tail runs
-            // iterations l .. L-2 in one launch
-            TailArgs a{};
-            a.rin = rec[cur];
-            a.v0 = v;
-            const uint32_t big = 2u * v.W - 1u;
-            a.G = TAIL_CAP / big;
-            if (a.G > v.nseg) a.G = v.nseg;
-            if (a.G > 2u) a.G = 2u;
-            a.rank_bits = p.B;
-            a.o = o;
-            if (kdt_status s = run_kernel(st, KIND_TAIL, (double)(n - v.Fl) * 4.0 * K,
-                                          [&] { launch_tail((int)k, a, widest, st); }))
-                return s;
-            break;
         }
-    }
-    if (status) {
-        if (kdt_status s = run_kernel(st, KIND_STATUS, 8.0,
-                                      [&] { launch_copy_word(status, ctl + CTL_STATUS, st); }))
+
+        // every large tree's remaining iterations, each from its own level
+        TailArgs a{};
+        a.sh = shares(p, p.tail, p.t_tail, ws);
+        a.rin[0] = rec[0];
+        a.rin[1] = rec[1];
+        a.from_points = 0;
+        a.o = o;
+        double tail_live = 0;
+        for (const TreeStep& s : p.tail) tail_live += p.trees[s.tree].n - full_nodes(s.level);
+        if (kdt_status s = run_kernel(st, KIND_TAIL, tail_live * 4.0 * K,
+                                      [&] { launch_tail((int)k, a, p.tail_groups, widest, st); }))
             return s;
+    }
+    if (status)
+        if (kdt_status s = run_kernel(st, KIND_STATUS, 8.0, [&] { launch_copy_word(status, dstatus, st); }))
+            return s;
+    return KDT_OK;
+}
+
+// Plans of batched calls, keyed by (k, mode, offsets), with their share
+// tables in pinned host memory.  A plan lives until kdt_release_cached(), so
+// an enqueued (or graph-captured) upload always reads valid memory.
+struct CachedPlan {
+    Plan plan;
+    void* pinned = nullptr;
+};
+std::mutex g_plan_mu;
+std::map<std::string, std::shared_ptr<CachedPlan>> g_plans;
+
+// pinned: also make sure the plan's tables are in pinned host memory
+kdt_status batched_plan(const uint32_t* h_offsets, uint32_t C, uint32_t k, bool widest, bool pinned,
+                        std::shared_ptr<CachedPlan>& out)
+{
+    std::string key(8 + (size_t)(C + 1) * 4, '\0');
+    const uint32_t wv = widest ? 1u : 0u;
+    memcpy(&key[0], &k, 4);
+    memcpy(&key[4], &wv, 4);
+    memcpy(&key[8], h_offsets, (size_t)(C + 1) * 4);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    std::shared_ptr<CachedPlan> cp;
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) {
+        cp = it->second;
+    } else {
+        std::vector<uint32_t> n(C);
+        for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
+        cp = std::make_shared<CachedPlan>();
+        cp->plan = make_plan(n, k, widest);
+        g_plans.emplace(key, cp);
+    }
+    if (pinned && cp->plan.tables && !cp->pinned) {
+        if (hipHostMalloc(&cp->pinned, cp->plan.blob.size(), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            cp->pinned = nullptr;
+            set_err("hipHostMalloc of %zu bytes failed", cp->plan.blob.size());
+            return KDT_ENOMEM;
+        }
+        memcpy(cp->pinned, cp->plan.blob.data(), cp->plan.blob.size());
+    }
+    out = cp;
+    return KDT_OK;
+}
+
+kdt_status validate_offsets(const uint32_t* h_offsets, uint32_t C)
+{
+    if (!h_offsets || C == 0) {
+        set_err("h_offsets must hold C+1 entries with C >= 1");
+        return KDT_EINVAL;
+    }
+    if (h_offsets[0] != 0) {
+        set_err("h_offsets[0] must be 0 (got %u)", h_offsets[0]);
+        return KDT_EINVAL;
+    }
+    for (uint32_t c = 0; c < C; ++c)
+        if (h_offsets[c + 1] < h_offsets[c]) {
+            set_err("h_offsets must be non-decreasing (cloud %u)", c);
+            return KDT_EINVAL;
+        }
+    if (h_offsets[C] > KDT_MAX_POINTS) {
+        set_err("total point count %u exceeds KDT_MAX_POINTS", h_offsets[C]);
+        return KDT_EINVAL;
     }
     return KDT_OK;
 }
@@ -439,54 +719,47 @@ struct Cached {
 std::mutex g_cache_mu;
 std::map<std::pair<int, hipStream_t>, Cached> g_cache;
 
+kdt_status write_ok_status(uint32_t* d_status, hipStream_t stream)
+{
+    if (!d_status) return KDT_OK;
+    kdt::launch_set_word(d_status, 0u, stream);
+    return check_launch("status");
+}
+
 }  // namespace
 
 extern "C" {
 
 size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode)
 {
-    if (k < 1 || k > 4 || n > KDT_MAX_POINTS) return 0;
-    if (dim_mode != KDT_DIM_ROUND_ROBIN && dim_mode != KDT_DIM_WIDEST) return 0;
-    return make_plan(n, k, dim_mode == KDT_DIM_WIDEST).total;
+    if (validate_k_mode(k, dim_mode) || n > KDT_MAX_POINTS) return 0;
+    return make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST).total;
 }
 
 kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
                         uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
                         hipStream_t stream)
 {
-    if (kdt_status s = validate(d_points, n, k, dim_mode)) return s;
-    const Plan p = make_plan(n, k, dim_mode == KDT_DIM_WIDEST);
-    if (!d_ws || ws_bytes < p.total) {
-        set_err("workspace of %zu bytes needed (got %zu)", p.total, d_ws ? ws_bytes : (size_t)0);
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (n > KDT_MAX_POINTS) {
+        set_err("n = %u exceeds KDT_MAX_POINTS", n);
         return KDT_EINVAL;
     }
-    if (((uintptr_t)d_ws) % ALIGN) {
-        set_err("workspace must be %zu-byte aligned", ALIGN);
-        return KDT_EINVAL;
-    }
-    const size_t pb = (size_t)n * k * 4;
-    if (overlaps(d_points, pb, d_tree, pb) || overlaps(d_points, pb, d_perm, (size_t)n * 4) ||
-        overlaps(d_points, pb, d_dim, n) || overlaps(d_points, pb, d_ws, ws_bytes) ||
-        overlaps(d_tree, pb, d_ws, ws_bytes) || overlaps(d_perm, (size_t)n * 4, d_ws, ws_bytes) ||
-        overlaps(d_dim, n, d_ws, ws_bytes) || overlaps(d_status, 4, d_ws, ws_bytes)) {
-        set_err("points, outputs and workspace must not overlap");
-        return KDT_EINVAL;
-    }
-    if (n == 0) {
-        if (d_status) {
-            kdt::launch_set_word(d_status, 0u, stream);
-            return check_launch("status");
-        }
-        return KDT_OK;
-    }
-    return enqueue_build(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, stream);
+    const Plan p = make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
+    if (kdt_status s = validate_buffers(p, d_points, d_tree, d_perm, d_dim, d_status, d_ws, ws_bytes)) return s;
+    if (n == 0) return write_ok_status(d_status, stream);
+    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, nullptr, stream);
 }
 
 kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipStream_t stream)
 {
-    if (kdt_status s = validate(d_points, n, k, dim_mode)) return s;
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (n > KDT_MAX_POINTS || (n > 0 && !d_points)) {
+        set_err("points is null or n exceeds KDT_MAX_POINTS");
+        return KDT_EINVAL;
+    }
     if (n == 0) return KDT_OK;
-    const Plan p = make_plan(n, k, dim_mode == KDT_DIM_WIDEST);
+    const Plan p = make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
     const size_t pb = align_up((size_t)n * k * 4);
     const size_t need = p.total + pb;
     int dev = 0;
@@ -516,22 +789,55 @@ kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipS
     // from a copy and writes the tree over the caller's array
     float* copy = (float*)((char*)ws + p.total);
     HIP_TRY(hipMemcpyAsync(copy, d_points, (size_t)n * k * 4, hipMemcpyDeviceToDevice, stream));
-    return enqueue_build(p, copy, d_points, nullptr, nullptr, nullptr, (char*)ws, stream);
+    return enqueue(p, copy, d_points, nullptr, nullptr, nullptr, (char*)ws, nullptr, stream);
+}
+
+size_t kdt_batched_workspace_bytes(const uint32_t* h_offsets, uint32_t C, uint32_t k, int dim_mode)
+{
+    if (validate_k_mode(k, dim_mode) || validate_offsets(h_offsets, C)) return 0;
+    std::shared_ptr<CachedPlan> cp;
+    if (batched_plan(h_offsets, C, k, dim_mode == KDT_DIM_WIDEST, false, cp)) return 0;
+    return cp->plan.total;
+}
+
+kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
+                             int dim_mode, float* d_tree, uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status,
+                             void* d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (kdt_status s = validate_offsets(h_offsets, C)) return s;
+    std::shared_ptr<CachedPlan> cp;
+    if (kdt_status s = batched_plan(h_offsets, C, k, dim_mode == KDT_DIM_WIDEST, false, cp)) return s;
+    const Plan& p = cp->plan;
+    if (kdt_status s = validate_buffers(p, d_points, d_tree, d_perm, d_dim, d_status, d_ws, ws_bytes)) return s;
+    if (p.ntotal == 0) return write_ok_status(d_status, stream);
+    if (kdt_status s = batched_plan(h_offsets, C, k, dim_mode == KDT_DIM_WIDEST, true, cp)) return s;
+    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, cp->pinned, stream);
 }
 
 void kdt_release_cached(void)
 {
-    std::lock_guard<std::mutex> lk(g_cache_mu);
-    int prev = 0;
-    (void)hipGetDevice(&prev);
-    for (auto& kv : g_cache) {
-        if (!kv.second.ptr) continue;
-        (void)hipSetDevice(kv.first.first);
-        (void)hipStreamSynchronize(kv.first.second);
-        (void)hipFree(kv.second.ptr);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        for (auto& kv : g_cache) {
+            if (!kv.second.ptr) continue;
+            (void)hipSetDevice(kv.first.first);
+            (void)hipStreamSynchronize(kv.first.second);
+            (void)hipFree(kv.second.ptr);
+        }
+        g_cache.clear();
+        (void)hipSetDevice(prev);
     }
-    g_cache.clear();
-    (void)hipSetDevice(prev);
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (!g_plans.empty()) {
+        // uploads of batched share tables may still be queued on any stream
+        (void)hipDeviceSynchronize();
+        for (auto& kv : g_plans)
+            if (kv.second->pinned) (void)hipHostFree(kv.second->pinned);
+        g_plans.clear();
+    }
 }
 
 const char* kdt_status_string(int status)

@@ -1,5 +1,5 @@
-// kdt_common.h -- device helpers shared by the build kernels: placement of
-// fixed nodes, split-widest child dimensions, record load/store.
+// kdt_common.h -- device helpers shared by the build kernels: share lookup,
+// placement of fixed nodes, split-widest child dimensions, record I/O.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,9 +11,6 @@
 
 namespace kdt {
 
-
-
-
 // Bounds guard of every scatter: a position outside its buffer flags an
 // internal error in the status word instead of writing.
 __device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t* status)
@@ -23,38 +20,60 @@ __device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t
     return false;
 }
 
-template <int K, bool WIDEST>
-__device__ __forceinline__ void place(const Outs& o, uint32_t node, uint32_t idx)
+// The share that tile (or workgroup) g belongs to.
+__device__ __forceinline__ void find_share(const Shares& sh, uint32_t g, TreeStep& st, TreeInfo& ti)
 {
-    if (!in_bounds(node, o.n, o.status) || !in_bounds(idx, o.n, o.status)) return;
+    if (sh.steps == nullptr) {
+        st = sh.step0;
+        ti = sh.tree0;
+        return;
+    }
+    uint32_t lo = 0, hi = sh.nsteps - 1u;
+    while (lo < hi) {                       // largest i with steps[i].tile0 <= g
+        const uint32_t mid = (lo + hi + 1u) >> 1;
+        if (sh.steps[mid].tile0 <= g) lo = mid;
+        else hi = mid - 1u;
+    }
+    st = sh.steps[lo];
+    ti = sh.trees[st.tree];
+}
+
+// Node `node` of tree ti holds its point of local index idx.
+template <int K, bool WIDEST>
+__device__ __forceinline__ void place(const Outs& o, const TreeInfo& ti, uint32_t node, uint32_t idx)
+{
+    if (!in_bounds(node, ti.n, o.status) || !in_bounds(idx, ti.n, o.status)) return;
+    const size_t at = (size_t)ti.off + node;
     if (o.tree) {
 #pragma unroll
-        for (int d = 0; d < K; ++d) o.tree[(size_t)node * K + d] = o.pts[(size_t)idx * K + d];
+        for (int d = 0; d < K; ++d) o.tree[at * K + d] = o.pts[((size_t)ti.off + idx) * K + d];
     }
-    o.nodeperm[node] = idx;
-    if (!WIDEST && o.dim) o.dim[node] = (uint8_t)(level_of(node) % (uint32_t)K);
+    o.nodeperm[at] = idx;
+    if (!WIDEST && o.dim) o.dim[at] = (uint8_t)(level_of(node) % (uint32_t)K);
 }
 
 // place() with the point's coordinates already loaded.
 template <int K, bool WIDEST>
-__device__ __forceinline__ void place_pt(const Outs& o, uint32_t node, uint32_t idx, const float4& p)
+__device__ __forceinline__ void place_pt(const Outs& o, const TreeInfo& ti, uint32_t node, uint32_t idx,
+                                         const float4& p)
 {
-    if (!in_bounds(node, o.n, o.status)) return;
+    if (!in_bounds(node, ti.n, o.status)) return;
+    const size_t at = (size_t)ti.off + node;
     if (o.tree) {
-        float* t = o.tree + (size_t)node * K;
+        float* t = o.tree + at * K;
         t[0] = p.x;
         if (K > 1) t[1] = p.y;
         if (K > 2) t[2] = p.z;
         if (K > 3) t[3] = p.w;
     }
-    o.nodeperm[node] = idx;
-    if (!WIDEST && o.dim) o.dim[node] = (uint8_t)(level_of(node) % (uint32_t)K);
+    o.nodeperm[at] = idx;
+    if (!WIDEST && o.dim) o.dim[at] = (uint8_t)(level_of(node) % (uint32_t)K);
 }
 
 template <int K>
-__device__ __forceinline__ float4 load_point(const float* __restrict__ pts, uint32_t idx)
+__device__ __forceinline__ float4 load_point(const float* __restrict__ pts, size_t i)
 {
-    const float* p = pts + (size_t)idx * K;
+    const float* p = pts + i * K;
     if constexpr (K == 4) return *reinterpret_cast<const float4*>(p);
     else if constexpr (K == 3) return make_float4(p[0], p[1], p[2], 0.f);
     else if constexpr (K == 2) {
@@ -65,30 +84,32 @@ __device__ __forceinline__ float4 load_point(const float* __restrict__ pts, uint
 
 __device__ __forceinline__ float pickf(const float4& p, uint32_t d)
 {
-    return d == 0u ? p.x : (d == 1u ? p.y : (d == 2u ? p.z : p.w));
+    const float x = p.x, y = p.y, z = p.z, w = p.w;
+    return d == 0u ? x : (d == 1u ? y : (d == 2u ? z : w));
 }
 
 // Split-widest (Sec. 6): the domain of a child of subtree s is s's domain
 // clipped by s's plane (left child: hi = plane, right child: lo = plane); the
 // child's split dimension is its domain's widest extent.  s is the i-th
-// subtree of its level, box_cur[i] its domain; the children's domains go to
-// box_next[2i], box_next[2i+1] (when box_next is set) and their dimensions to
-// dimnode.  pidx is the pivot's original index, ds the split dimension of s.
+// subtree of its level in tree ti, box_cur[box_off + i] its domain; the
+// children's domains go to box_next[box_off + 2i (+1)] (when box_next is
+// set) and their dimensions to dimnode.  plane is the pivot's coordinate in
+// s's split dimension ds.
 template <int K>
-__device__ void widest_children(const Outs& o, uint32_t s, uint32_t i, uint32_t pidx, uint32_t ds,
-                                const float* box_cur, float* box_next)
+__device__ void widest_children(const Outs& o, const TreeInfo& ti, uint32_t s, uint32_t i, float plane,
+                                uint32_t ds, const float* box_cur, float* box_next)
 {
     float lo[K], hi[K];
+    const float* bc = box_cur + ((size_t)ti.box_off + i) * 8;
 #pragma unroll
     for (int d = 0; d < K; ++d) {
-        lo[d] = box_cur[(size_t)i * 8 + d];
-        hi[d] = box_cur[(size_t)i * 8 + 4 + d];
+        lo[d] = bc[d];
+        hi[d] = bc[4 + d];
     }
-    const float plane = o.pts[(size_t)pidx * K + ds];
 #pragma unroll
     for (uint32_t c = 0; c < 2u; ++c) {
         const uint32_t child = 2u * s + 1u + c;
-        if (child >= o.n) continue;
+        if (child >= ti.n) continue;
         float l2[K], h2[K];
 #pragma unroll
         for (int d = 0; d < K; ++d) {
@@ -99,51 +120,15 @@ __device__ void widest_children(const Outs& o, uint32_t s, uint32_t i, uint32_t 
                 else l2[d] = fmaxf(lo[d], plane);
             }
         }
-        o.dimnode[child] = (uint8_t)widest_dim<K>(l2, h2);
+        o.dimnode[(size_t)ti.off + child] = (uint8_t)widest_dim<K>(l2, h2);
         if (box_next) {
+            float* bn = box_next + ((size_t)ti.box_off + 2u * i + c) * 8;
 #pragma unroll
             for (int d = 0; d < K; ++d) {
-                box_next[(size_t)(2u * i + c) * 8 + d] = l2[d];
-                box_next[(size_t)(2u * i + c) * 8 + 4 + d] = h2[d];
+                bn[d] = l2[d];
+                bn[4 + d] = h2[d];
             }
         }
-    }
-}
-
-// r[d] for a runtime d without dynamic register indexing.
-template <int K>
-__device__ __forceinline__ uint32_t pick(const uint32_t (&r)[K], uint32_t d)
-{
-    uint32_t v = r[0];
-#pragma unroll
-    for (int q = 1; q < K; ++q) v = ((uint32_t)q == d) ? r[q] : v;
-    return v;
-}
-
-template <int K>
-__device__ __forceinline__ void load_rec(const uint32_t* __restrict__ p, size_t i, uint32_t (&r)[K])
-{
-    if constexpr (K == 4) {
-        const uint4 v = reinterpret_cast<const uint4*>(p)[i];
-        r[0] = v.x; r[1] = v.y; r[2] = v.z; r[3] = v.w;
-    } else if constexpr (K == 2) {
-        const uint2 v = reinterpret_cast<const uint2*>(p)[i];
-        r[0] = v.x; r[1] = v.y;
-    } else {
-#pragma unroll
-        for (int w = 0; w < K; ++w) r[w] = p[i * K + w];
-    }
-}
-template <int K>
-__device__ __forceinline__ void store_rec(uint32_t* __restrict__ p, size_t i, const uint32_t (&r)[K])
-{
-    if constexpr (K == 4) {
-        reinterpret_cast<uint4*>(p)[i] = make_uint4(r[0], r[1], r[2], r[3]);
-    } else if constexpr (K == 2) {
-        reinterpret_cast<uint2*>(p)[i] = make_uint2(r[0], r[1]);
-    } else {
-#pragma unroll
-        for (int w = 0; w < K; ++w) p[i * K + w] = r[w];
     }
 }
 
@@ -179,7 +164,8 @@ __device__ __forceinline__ void store_rec4(uint32_t* __restrict__ p, size_t i, u
 }
 __device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t d)
 {
-    return d == 0u ? r.x : (d == 1u ? r.y : (d == 2u ? r.z : r.w));
+    const uint32_t x = r.x, y = r.y, z = r.z, w = r.w;
+    return d == 0u ? x : (d == 1u ? y : (d == 2u ? z : w));
 }
 
 // Lanes of this wave whose (valid, value) agree with this lane's on the low
@@ -200,6 +186,5 @@ __device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)
     if (!p) return;
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < n; x += gridDim.x * blockDim.x) p[x] = 0u;
 }
-
 
 }  // namespace kdt

@@ -142,7 +142,10 @@ KDT_HD uint32_t tiles_seg_offset(const SegTiles& t, uint32_t i)
 }
 KDT_HD uint32_t tiles_seg_size(const SegTiles& t, uint32_t i)
 {
-    return i < t.a ? t.big : (i == t.a ? t.mid : t.small);
+    // operands as values: a conditional over the members themselves selects
+    // between their addresses, which keeps the struct out of registers
+    const uint32_t big = t.big, mid = t.mid, small = t.small;
+    return i < t.a ? big : (i == t.a ? mid : small);
 }
 
 // Tile g -> (segment, tile index inside the segment).

@@ -22,6 +22,11 @@
 //
 // The input order of a subtree is its parent's sorted order, so the parent's
 // dimension needs no sort (round robin: dimension (l0-1) mod k).
+//
+// A whole tree of at most TAIL_CAP points is built the same way straight
+// from its points (from_points): the per-dimension orders come from a stable
+// radix sort of the order-preserving float keys starting in index order, so
+// equal coordinates keep index order, and the loop starts at iteration 0.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -82,57 +87,120 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
     __shared__ float nplane[NODES];
     __shared__ float rootbox[2][8];
     __shared__ uint32_t node[C];                   // final node of each slot
+    __shared__ uint32_t bxk[8];                    // from_points split-widest: scene box keys
     uint16_t(*cnt)[C] = reinterpret_cast<uint16_t(*)[C]>(ubuf);   // [NWAVE][C]
 
     const Outs& o = a.o;
-    const Level v0 = a.v0;
+    TreeStep stp;
+    TreeInfo ti;
+    find_share(a.sh, blockIdx.x, stp, ti);
+    const bool FP = a.from_points != 0u;
+    const size_t off = ti.off;
+    const Level v0 = make_level(ti.n, FP ? 0u : stp.level);
     const uint32_t l0 = v0.l;
     const uint32_t L = v0.L;
-    const uint32_t i0 = blockIdx.x * a.G;
-    const uint32_t i1 = min(i0 + a.G, v0.nseg);
+    const uint32_t i0 = (blockIdx.x - stp.tile0) * stp.G;
+    const uint32_t i1 = min(i0 + stp.G, v0.nseg);
     const uint32_t gc = i1 - i0;
     const uint32_t live0 = v0.n - v0.Fl;
-    const uint32_t off0 = seg_offset(v0, i0);
-    const uint32_t m = ((i1 == v0.nseg) ? live0 : seg_offset(v0, i1)) - off0;
+    const uint32_t off0 = FP ? 0u : seg_offset(v0, i0);
+    const uint32_t m = FP ? ti.n : ((i1 == v0.nseg) ? live0 : seg_offset(v0, i1)) - off0;
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t B = a.rank_bits;
+    const uint32_t B = FP ? 32u : rank_bits(ti.n);    // ranks of this tree are < n
     if (m > C) {                                   // the host sizes groups to fit
         if (threadIdx.x == 0) atomicOr(o.status, KDT_STATUS_INTERNAL);
         return;
     }
 
-    // ---- load the group's records (slot e = its position in the input) ----
-    uint4 rec[ITEMS];
-    uint32_t idx[ITEMS];                           // original index of each slot
+    // ---- load the group (slot e = its position in the input) ----
+    uint4 rec[ITEMS];                              // per-dimension sort keys of each slot
+    uint32_t idx[ITEMS];                           // original (local) index of each slot
+    float4 pc[ITEMS];                              // coordinates of each slot's point
     bool ok[ITEMS];
+    bool bad = false;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
         ok[i] = e < m;
-        rec[i] = ok[i] ? load_rec4<K>(a.rin, (size_t)off0 + e) : make_uint4(0u, 0u, 0u, 0u);
-        seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
+        rec[i] = make_uint4(0u, 0u, 0u, 0u);
+        idx[i] = 0u;
+        pc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (FP) {
+            if (ok[i]) {
+                idx[i] = e;
+                pc[i] = load_point<K>(o.pts, off + e);
+                const float cf[4] = {pc[i].x, pc[i].y, pc[i].z, pc[i].w};
+                uint32_t kk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int d = 0; d < K; ++d) {
+                    const uint32_t bits = __float_as_uint(cf[d]);
+                    bad |= nonfinite(bits);
+                    kk[d] = orderable(bits);
+                }
+                rec[i] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
+            }
+            seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
+        } else {
+            if (ok[i]) rec[i] = load_rec4<K>(a.rin[stp.buf & 1u], off + off0 + e);
+            seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
+        }
         node[e] = 0xFFFFFFFFu;
     }
+    if (!FP) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        idx[i] = 0u;
-        if (ok[i] && in_bounds(rec[i].x, o.n, o.status)) idx[i] = o.perm0[rec[i].x];
+        for (int i = 0; i < ITEMS; ++i) {
+            if (ok[i] && in_bounds(rec[i].x, ti.n, o.status)) idx[i] = o.perm0[off + rec[i].x];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) pc[i] = ok[i] ? load_point<K>(o.pts, off + idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        if (__any(bad) && lane == 0) atomicOr(o.status, KDT_STATUS_NONFINITE);
+        if (WIDEST) {
+            // scene box of the tree (as orderable keys, then floats)
+            if (threadIdx.x < 8) bxk[threadIdx.x] = threadIdx.x < 4 ? 0xFFFFFFFFu : 0u;
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                if (!ok[i]) continue;
+#pragma unroll
+                for (int d = 0; d < K; ++d) {
+                    atomicMin(&bxk[d], pick4(rec[i], (uint32_t)d));
+                    atomicMax(&bxk[4 + d], pick4(rec[i], (uint32_t)d));
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                float lo[K], hi[K];
+#pragma unroll
+                for (int d = 0; d < K; ++d) {
+                    lo[d] = from_orderable(bxk[d]);
+                    hi[d] = from_orderable(bxk[4 + d]);
+                    rootbox[0][d] = lo[d];
+                    rootbox[0][4 + d] = hi[d];
+                }
+                const uint32_t d0 = widest_dim<K>(lo, hi);
+                segdim[0][0] = (uint8_t)d0;
+                o.dimnode[off] = (uint8_t)d0;
+            }
+        }
     }
-    float4 pc[ITEMS];                              // coordinates of each slot's point
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) pc[i] = ok[i] ? load_point<K>(o.pts, idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
-    if (WIDEST && threadIdx.x < gc) {
+    if (!FP && WIDEST && threadIdx.x < gc) {
         // domain of each group root, written by its parent's pivot
         const uint32_t q = threadIdx.x;
-        const float* bx = o.box[l0 & 1u] + (size_t)(i0 + q) * 8;
+        const float* bx = o.box[l0 & 1u] + ((size_t)ti.box_off + i0 + q) * 8;
 #pragma unroll
         for (int d = 0; d < 8; ++d) rootbox[q][d] = bx[d];
-        segdim[0][q] = o.dimnode[v0.Fl + i0 + q];
+        segdim[0][q] = o.dimnode[off + v0.Fl + i0 + q];
     }
     // dimension whose order the input already has (within every segment)
     uint32_t free_dim = 0xFFFFFFFFu;
-    if (!WIDEST) free_dim = (l0 + (uint32_t)K - 1u) % (uint32_t)K;
-    else if (gc == 1u) free_dim = o.dimnode[(v0.Fl + i0 - 1u) >> 1];
+    if (!FP) {
+        if (!WIDEST) free_dim = (l0 + (uint32_t)K - 1u) % (uint32_t)K;
+        // the parent's dimension (a group of two subtrees starts at an even
+        // i0, so both are children of the same parent)
+        else free_dim = o.dimnode[off + ((v0.Fl + i0 - 1u) >> 1)];
+    }
+    if (FP && L < 2u && threadIdx.x == 0) node[0] = 0u;   // a single point is the root
     __syncthreads();
 
     // ---- ord_d: the group sorted by rank_d (stable LSD over 8-bit digits) ----
@@ -177,7 +245,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
     uint32_t cur = 0;
     for (uint32_t l = l0; l + 2u <= L; ++l) {
         const uint32_t t = l - l0;
-        const Level vl = make_level(v0.n, l);
+        const Level vl = make_level(ti.n, l);
         const uint32_t S = gc << t;                       // group segments on this level
         const uint32_t gbits = rank_bits(S);
         const bool last = (l + 2u == L);
@@ -244,7 +312,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
 #pragma unroll
                     for (uint32_t c = 0; c < 2u; ++c) {
                         const uint32_t child = 2u * sn + 1u + c;
-                        if (child >= o.n) continue;
+                        if (child >= ti.n) continue;
                         float l2[K], h2[K];
 #pragma unroll
                         for (int dd = 0; dd < K; ++dd) {
@@ -256,7 +324,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
                             }
                         }
                         const uint32_t cd = widest_dim<K>(l2, h2);
-                        o.dimnode[child] = (uint8_t)cd;
+                        o.dimnode[off + child] = (uint8_t)cd;
                         if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
                     }
                 }
@@ -278,25 +346,24 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-        if (ok[i]) place_pt<K, WIDEST>(o, node[e], idx[i], pc[i]);
+        if (ok[i]) place_pt<K, WIDEST>(o, ti, node[e], idx[i], pc[i]);
     }
 }
 
 template <int K>
-static void tail_k(const TailArgs& a, bool widest, uint32_t grid, hipStream_t st)
+static void tail_k(const TailArgs& a, uint32_t groups, bool widest, hipStream_t st)
 {
-    if (widest) k_tail<K, true><<<grid, BLOCK, 0, st>>>(a);
-    else k_tail<K, false><<<grid, BLOCK, 0, st>>>(a);
+    if (widest) k_tail<K, true><<<groups, BLOCK, 0, st>>>(a);
+    else k_tail<K, false><<<groups, BLOCK, 0, st>>>(a);
 }
 
-void launch_tail(int k, const TailArgs& a, bool widest, hipStream_t st)
+void launch_tail(int k, const TailArgs& a, uint32_t groups, bool widest, hipStream_t st)
 {
-    const uint32_t grid = ceil_div(a.v0.nseg, a.G);
     switch (k) {
-    case 1: tail_k<1>(a, widest, grid, st); break;
-    case 2: tail_k<2>(a, widest, grid, st); break;
-    case 3: tail_k<3>(a, widest, grid, st); break;
-    default: tail_k<4>(a, widest, grid, st); break;
+    case 1: tail_k<1>(a, groups, widest, st); break;
+    case 2: tail_k<2>(a, groups, widest, st); break;
+    case 3: tail_k<3>(a, groups, widest, st); break;
+    default: tail_k<4>(a, groups, widest, st); break;
     }
 }
 

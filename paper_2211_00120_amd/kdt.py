@@ -35,6 +35,11 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "kdt_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                  ctypes.c_void_p]),
+    "kdt_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                                      ctypes.c_int]),
+    "kdt_build_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "kdt_release_cached": (None, []),
     "kdt_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "kdt_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
@@ -135,6 +140,54 @@ def build(points, mode: int = ROUND_ROBIN, stream=None):
     if rc != OK:
         raise KdtError(rc, "kdt_build")
     return points
+
+
+def _offsets(offsets):
+    """Host uint32 copy of the C+1 cloud offsets (kept alive by the caller)."""
+    import numpy as np
+    o = np.asarray(offsets)
+    if o.ndim != 1 or o.size < 2:
+        raise ValueError("offsets must be a 1-D array of C+1 entries")
+    if int(o[-1]) > MAX_POINTS or int(o.min()) < 0:
+        raise ValueError("offsets out of range")
+    return np.ascontiguousarray(o, dtype=np.uint32)
+
+
+def batched_workspace_bytes(offsets, k: int, mode: int = ROUND_ROBIN) -> int:
+    o = _offsets(offsets)
+    return int(lib().kdt_batched_workspace_bytes(o.ctypes.data_as(ctypes.c_void_p), o.size - 1, k, mode))
+
+
+def build_batched(points, offsets, mode: int = ROUND_ROBIN, *, tree=None, perm=None, dim=None, status=None,
+                  workspace=None, stream=None, want_tree=True, want_perm=True, want_dim=True):
+    """kdt_build_batched over torch tensors: points is the (sum N_c, k)
+    concatenation of the clouds, offsets the host array of C+1 row offsets.
+    Missing outputs are allocated (unless want_* is False); returns
+    (tree, perm, dim, status), with perm local to each cloud."""
+    import torch
+    _check_points(points)
+    n, k = points.shape
+    o = _offsets(offsets)
+    if int(o[-1]) != n:
+        raise ValueError(f"offsets end at {int(o[-1])} but points has {n} rows")
+    dev = points.device
+    if tree is None and want_tree:
+        tree = torch.empty((n, k), dtype=torch.float32, device=dev)
+    if perm is None and want_perm:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    if dim is None and want_dim:
+        dim = torch.empty(n, dtype=torch.uint8, device=dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    if workspace is None:
+        nbytes = batched_workspace_bytes(o, k, mode)
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    rc = lib().kdt_build_batched(_ptr(points), o.ctypes.data_as(ctypes.c_void_p), o.size - 1, k, mode, _ptr(tree),
+                                 _ptr(perm), _ptr(dim), _ptr(status), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _stream(stream))
+    if rc != OK:
+        raise KdtError(rc, "kdt_build_batched")
+    return tree, perm, dim, status
 
 
 def release_cached():

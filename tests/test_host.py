@@ -94,3 +94,32 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(kdt, "_lib", None)
     with pytest.raises(RuntimeError):
         kdt.lib()
+
+
+def test_batched_argument_errors_and_sizes():
+    import numpy as np
+    lib = kdt.lib()
+    offs = np.array([0, 100, 100, 5000, 70000], np.uint32)
+    p = offs.ctypes.data_as(ctypes.c_void_p)
+    need = lib.kdt_batched_workspace_bytes(p, 4, 3, 0)
+    assert need > 0 and need % 256 == 0
+    assert lib.kdt_batched_workspace_bytes(p, 4, 3, 1) >= need
+    assert lib.kdt_batched_workspace_bytes(p, 4, 0, 0) == 0
+    assert lib.kdt_batched_workspace_bytes(None, 4, 3, 0) == 0
+    assert lib.kdt_batched_workspace_bytes(p, 0, 3, 0) == 0
+    bad = np.array([0, 100, 50], np.uint32)                 # decreasing
+    assert lib.kdt_batched_workspace_bytes(bad.ctypes.data_as(ctypes.c_void_p), 2, 3, 0) == 0
+    bad = np.array([1, 100], np.uint32)                     # does not start at 0
+    assert lib.kdt_batched_workspace_bytes(bad.ctypes.data_as(ctypes.c_void_p), 1, 3, 0) == 0
+    fake = ctypes.c_void_p(0x1000)
+    ws = ctypes.c_void_p(0x10000000)
+    args = (None, None, None, None)
+    assert lib.kdt_build_batched(fake, p, 4, 9, 0, *args, ws, need, None) == kdt.EINVAL
+    assert lib.kdt_build_batched(None, p, 4, 3, 0, *args, ws, need, None) == kdt.EINVAL
+    assert lib.kdt_build_batched(fake, p, 4, 3, 0, *args, ws, need - 1, None) == kdt.EINVAL
+    assert "workspace" in kdt.last_error()
+    assert lib.kdt_build_batched(fake, None, 4, 3, 0, *args, ws, need, None) == kdt.EINVAL
+    # one batched plan for one tree needs no more workspace than the single build
+    one = np.array([0, 123457], np.uint32)
+    assert lib.kdt_batched_workspace_bytes(one.ctypes.data_as(ctypes.c_void_p), 1, 3, 1) \
+        == lib.kdt_workspace_bytes(123457, 3, 1)
