@@ -20,22 +20,37 @@ __device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t
     return false;
 }
 
-// The share that tile (or workgroup) g belongs to.
+// The share that tile (or workgroup) g belongs to; g is the same in every
+// lane.  The result is made wave-uniform field by field, so that it and all
+// the segment arithmetic derived from it live in scalar registers.
 __device__ __forceinline__ void find_share(const Shares& sh, uint32_t g, TreeStep& st, TreeInfo& ti)
 {
+    TreeStep s;
+    TreeInfo t;
     if (sh.steps == nullptr) {
-        st = sh.step0;
-        ti = sh.tree0;
-        return;
+        s = sh.step0;
+        t = sh.tree0;
+    } else {
+        uint32_t lo = 0, hi = sh.nsteps - 1u;
+        while (lo < hi) {                   // largest i with steps[i].tile0 <= g
+            const uint32_t mid = (lo + hi + 1u) >> 1;
+            if (sh.steps[mid].tile0 <= g) lo = mid;
+            else hi = mid - 1u;
+        }
+        s = sh.steps[lo];
+        t = sh.trees[s.tree];
     }
-    uint32_t lo = 0, hi = sh.nsteps - 1u;
-    while (lo < hi) {                       // largest i with steps[i].tile0 <= g
-        const uint32_t mid = (lo + hi + 1u) >> 1;
-        if (sh.steps[mid].tile0 <= g) lo = mid;
-        else hi = mid - 1u;
-    }
-    st = sh.steps[lo];
-    ti = sh.trees[st.tree];
+    st.tree = uniform(s.tree);
+    st.level = uniform(s.level);
+    st.tile0 = uniform(s.tile0);
+    st.hist = uniform(s.hist);
+    st.hist_next = uniform(s.hist_next);
+    st.G = uniform(s.G);
+    st.buf = uniform(s.buf);
+    ti.off = uniform(t.off);
+    ti.n = uniform(t.n);
+    ti.box_off = uniform(t.box_off);
+    ti.idx = uniform(t.idx);
 }
 
 // Node `node` of tree ti holds its point of local index idx.

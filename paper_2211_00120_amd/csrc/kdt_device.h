@@ -22,6 +22,9 @@ constexpr uint32_t LB_VAL = (1u << 30) - 1u;
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
+// A value every lane of the wave holds alike, moved to a scalar register.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Lanes of this wave whose (valid, digit) equal this lane's: 8 ballots.
 __device__ __forceinline__ uint64_t match_digit(uint32_t digit, bool valid)
 {

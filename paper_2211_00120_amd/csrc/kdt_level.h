@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_pass(LevelPassArgs a)
 
     if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
     __syncthreads();
-    const uint32_t g = sm.tile;
+    const uint32_t g = uniform(sm.tile);
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, g, st, ti);
