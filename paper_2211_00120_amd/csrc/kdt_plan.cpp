@@ -1,0 +1,220 @@
+// kdt_plan.cpp -- host planner of a build call (see kdt_plan.h).
+#include "kdt_plan.h"
+
+#include <string.h>
+
+#include <algorithm>
+
+#include "kdt_layout.h"
+
+namespace kdt {
+
+namespace {
+
+// Records per thread of an iteration's sort tiles (tile = 512 * items): the
+// largest tile that the iteration's biggest subtree still fills.
+uint32_t level_items(uint32_t big, uint32_t cap)
+{
+    const uint32_t items = big >= 4096u ? 8u : 4u;
+    return items < cap ? items : cap;
+}
+
+TreeStep step(uint32_t tree, uint32_t level, uint32_t tile0)
+{
+    TreeStep s{};
+    s.tree = tree;
+    s.level = level;
+    s.tile0 = tile0;
+    s.hist = 0;
+    s.hist_next = NO_HIST;
+    s.G = 0;
+    s.buf = 0;
+    return s;
+}
+
+size_t push_table(std::vector<uint8_t>& blob, const void* p, size_t bytes)
+{
+    const size_t at = blob.size();
+    blob.resize(align_up(at + bytes));
+    if (bytes) memcpy(blob.data() + at, p, bytes);
+    return at;
+}
+
+}  // namespace
+
+uint32_t first_tail_level(uint32_t n)
+{
+    // the first subtree of a level is its largest; subtrees of level L-2
+    // hold at most 3 points, so for n > TAIL_CAP the result is in 1 .. L-2
+    const uint32_t L = num_levels(n);
+    uint32_t l = 1;
+    while (l + 2 <= L && seg_size(make_level(n, l), 0) > TAIL_CAP) ++l;
+    return l;
+}
+
+Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& opt)
+{
+    Plan p;
+    p.k = k;
+    p.widest = widest;
+    const uint32_t T = (uint32_t)n.size();
+    p.trees.resize(T);
+    uint64_t off = 0;
+    for (uint32_t t = 0; t < T; ++t) {
+        p.trees[t] = TreeInfo{(uint32_t)off, n[t], 0u, 0u};
+        off += n[t];
+    }
+    p.ntotal = off;
+
+    for (uint32_t t = 0; t < T; ++t) {
+        if (n[t] == 0) continue;
+        if (n[t] <= TAIL_CAP) {
+            TreeStep s = step(t, 0u, (uint32_t)p.small.size());
+            s.G = 1;
+            p.small.push_back(s);
+        } else {
+            p.trees[t].idx = (uint32_t)p.large.size();
+            p.large.push_back(t);
+        }
+    }
+
+    // digit width of the level sorts: fewest passes over the largest rank
+    // with 8..10-bit digits, then the narrowest digit that keeps that count
+    // (a tree of more than TAIL_CAP points has ranks of >= 12 bits, so P >= 2)
+    for (uint32_t t : p.large) p.B = std::max(p.B, rank_bits(n[t]));
+    if (p.B) {
+        const uint32_t pmin = (p.B + 9u) / 10u;
+        p.RB = 10;
+        for (uint32_t rb = 8; rb <= 10; ++rb)
+            if ((p.B + rb - 1u) / rb == pmin) {
+                p.RB = rb;
+                break;
+            }
+        if (opt.radix_bits >= 8 && opt.radix_bits <= 10) p.RB = opt.radix_bits;
+        p.P = (p.B + p.RB - 1u) / p.RB;
+    }
+    const uint32_t items_cap = (opt.max_items == 4 || opt.max_items == 8) ? opt.max_items : 8u;
+    const uint32_t NB = 1u << p.RB;
+
+    // per-tree shares of the whole-array steps
+    std::vector<uint32_t> l0(T, 0);
+    uint32_t maxl = 0;
+    for (uint32_t t : p.large) {
+        TreeInfo& ti = p.trees[t];
+        l0[t] = first_tail_level(ti.n);
+        maxl = std::max(maxl, l0[t]);
+        ti.box_off = p.box_entries;
+        p.box_entries += 1u << l0[t];     // subtrees of the deepest iteration with a domain table
+        p.prep.push_back(step(t, 0u, p.prep_tiles));
+        p.level0.push_back(step(t, 0u, p.prep_tiles));
+        p.prep_tiles += ceil_div(ti.n, PREP_TILE);
+        p.presort.push_back(step(t, 0u, p.presort_tiles));
+        p.presort_tiles += ceil_div(ti.n, PRESORT_TILE);
+        p.roots.push_back(step(t, 0u, 0u));
+    }
+
+    // iterations 1 .. run as digit passes (tree t takes part while l < l0[t])
+    for (uint32_t l = 1; l < maxl; ++l) {
+        LevelLaunch ll;
+        ll.level = l;
+        uint32_t big = 0;
+        for (uint32_t t : p.large)
+            if (l < l0[t]) big = std::max(big, seg_size(make_level(n[t], l), 0));
+        ll.items = level_items(big, items_cap);
+        for (uint32_t t : p.large) {
+            if (l >= l0[t]) continue;
+            const Level v = make_level(n[t], l);
+            TreeStep s = step(t, l, ll.tiles);
+            s.hist = ll.hist_words;
+            ll.tiles += tiles_level(v, 512u * ll.items).tiles;
+            ll.hist_words += v.nseg * p.P * NB;
+            ll.steps.push_back(s);
+            TreeStep h = step(t, l, ll.hist_tiles);
+            ll.hist_tiles += tiles_level(v, HIST_TILE).tiles;
+            ll.hsteps.push_back(h);
+        }
+        p.hist_words = std::max(p.hist_words, ll.hist_words);
+        p.levels.push_back(std::move(ll));
+    }
+    // iteration l's histograms live in half (l & 1) of the histogram region
+    for (LevelLaunch& ll : p.levels) {
+        const uint32_t base = (ll.level & 1u) * p.hist_words;
+        for (size_t i = 0; i < ll.steps.size(); ++i) {
+            ll.steps[i].hist += base;
+            ll.hsteps[i].hist = ll.steps[i].hist;
+        }
+    }
+    // each share's histogram offset for the next iteration
+    auto next_hist = [&](size_t li, uint32_t tree) {
+        if (li >= p.levels.size()) return NO_HIST;
+        for (const TreeStep& s : p.levels[li].steps)
+            if (s.tree == tree) return s.hist;
+        return NO_HIST;
+    };
+    for (size_t li = 0; li < p.levels.size(); ++li)
+        for (TreeStep& s : p.levels[li].steps) s.hist_next = next_hist(li + 1, s.tree);
+    for (TreeStep& s : p.level0) s.hist_next = next_hist(0, s.tree);
+
+    // the tail of every large tree from its own first tail iteration; the
+    // level sorts flip the record buffer once per pass
+    for (uint32_t t : p.large) {
+        const Level v = make_level(n[t], l0[t]);
+        const uint32_t G = std::max(1u, std::min({TAIL_CAP / seg_size(v, 0), v.nseg, 2u}));
+        TreeStep s = step(t, l0[t], p.tail_groups);
+        s.G = G;
+        s.buf = ((l0[t] - 1u) * p.P) & 1u;
+        p.tail.push_back(s);
+        p.tail_groups += ceil_div(v.nseg, G);
+    }
+
+    // look-back words per pass, in the order the passes run
+    if (!p.large.empty())
+        for (uint32_t q = 0; q < 4u * k; ++q) p.pass_words.push_back(p.presort_tiles * RADIX_HOST);
+    for (const LevelLaunch& ll : p.levels)
+        for (uint32_t q = 0; q < p.P; ++q) p.pass_words.push_back(ll.tiles * NB);
+    for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
+
+    // share tables
+    p.t_trees = push_table(p.blob, p.trees.data(), p.trees.size() * sizeof(TreeInfo));
+    p.t_small = push_table(p.blob, p.small.data(), p.small.size() * sizeof(TreeStep));
+    p.t_prep = push_table(p.blob, p.prep.data(), p.prep.size() * sizeof(TreeStep));
+    p.t_presort = push_table(p.blob, p.presort.data(), p.presort.size() * sizeof(TreeStep));
+    p.t_level0 = push_table(p.blob, p.level0.data(), p.level0.size() * sizeof(TreeStep));
+    p.t_tail = push_table(p.blob, p.tail.data(), p.tail.size() * sizeof(TreeStep));
+    p.t_roots = push_table(p.blob, p.roots.data(), p.roots.size() * sizeof(TreeStep));
+    p.tables = p.small.size() > 1 || p.large.size() > 1;
+    for (const LevelLaunch& ll : p.levels) {
+        p.t_level.push_back(push_table(p.blob, ll.steps.data(), ll.steps.size() * sizeof(TreeStep)));
+        p.t_hist.push_back(push_table(p.blob, ll.hsteps.data(), ll.hsteps.size() * sizeof(TreeStep)));
+    }
+
+    // workspace
+    const size_t N = p.ntotal;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t r = o;
+        o = align_up(o + bytes);
+        return r;
+    };
+    p.o_status = take(64);
+    p.o_counters = take(MAX_PASSES * 4);
+    p.o_hist_rank = take((size_t)p.large.size() * k * 4 * RADIX_HOST * 4);
+    p.o_hist = take((size_t)p.hist_words * 2 * 4);
+    p.o_lb[0] = take((size_t)p.lb_words * 4);
+    p.o_lb[1] = take((size_t)p.lb_words * 4);
+    p.o_keys = take(N * k * 4);
+    p.o_perms = take(N * k * 4);
+    p.o_ranks = take(N * k * 4);
+    p.rec_words = std::max(N * k, 2 * N);   // also holds the presort's (key, index) ping-pong
+    p.o_rec = take(p.rec_words * 2 * 4);
+    p.o_nodeperm = take(N * 4);
+    p.o_dimnode = take(N);
+    p.o_box[0] = take((size_t)p.box_entries * 8 * 4);
+    p.o_box[1] = take((size_t)p.box_entries * 8 * 4);
+    p.o_bbox = take((size_t)p.large.size() * 8 * 4);
+    p.o_tables = take(p.tables ? p.blob.size() : 0);
+    p.total = o;
+    return p;
+}
+
+}  // namespace kdt

@@ -1,0 +1,75 @@
+// kdt_plan.h -- host planner of a build call (plain C++, no HIP).
+//
+// A call builds a list of independent trees.  The plan fixes, from the tree
+// sizes, k and the split rule alone: which trees are built whole by one
+// workgroup, the launch sequence of the others (prep, presorts, iteration
+// 0, the iterations run as segmented digit passes, the tail), every launch's
+// share table, the digit width of the level sorts and the workspace layout.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "kdt_shares.h"
+
+namespace kdt {
+
+constexpr size_t WS_ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + WS_ALIGN - 1) & ~(WS_ALIGN - 1); }
+constexpr uint32_t NO_HIST = 0xFFFFFFFFu;
+
+// Choices the planner otherwise makes itself (0 = automatic).
+struct PlanOptions {
+    uint32_t radix_bits = 0;   // digit width of the level sorts: 8, 9 or 10
+    uint32_t max_items = 0;    // cap on records per thread of the level-sort tiles: 4 or 8
+};
+
+// One iteration run as digit passes over every tree that still has subtrees
+// larger than TAIL_CAP.
+struct LevelLaunch {
+    uint32_t level = 0;
+    uint32_t items = 4;              // records per thread of its sort tiles
+    uint32_t tiles = 0;              // sort tiles
+    uint32_t hist_tiles = 0;         // split-widest histogram tiles
+    uint32_t hist_words = 0;         // words of its digit histograms
+    std::vector<TreeStep> steps;     // sort shares
+    std::vector<TreeStep> hsteps;    // split-widest histogram shares (tiles of HIST_TILE)
+};
+
+// Everything about one call that depends only on the tree sizes, k and mode.
+struct Plan {
+    uint32_t k = 0;
+    bool widest = false;
+    uint64_t ntotal = 0;
+    std::vector<TreeInfo> trees;     // every tree of the call
+    std::vector<uint32_t> large;     // trees built by digit passes
+    std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
+    uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / passes of the level sorts
+    std::vector<TreeStep> prep, presort, level0, tail, roots;
+    uint32_t prep_tiles = 0, presort_tiles = 0, tail_groups = 0;
+    std::vector<LevelLaunch> levels; // iterations 1.. run as passes
+    uint32_t hist_words = 0;         // per parity half of the histogram region
+    uint32_t lb_words = 0;           // per look-back buffer
+    uint32_t box_entries = 0;        // per split-widest domain buffer
+    std::vector<uint32_t> pass_words;// look-back words of every onesweep pass, in order
+    bool tables = false;             // some launch reads a device share table
+    std::vector<uint8_t> blob;       // the share tables, as uploaded
+    size_t t_trees = 0, t_small = 0, t_prep = 0, t_presort = 0, t_level0 = 0, t_tail = 0, t_roots = 0;
+    std::vector<size_t> t_level, t_hist;
+    // workspace offsets (bytes)
+    size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,
+           o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_tables = 0,
+           total = 0;
+    size_t rec_words = 0;            // words per record buffer
+};
+
+// Plan of a call over trees of n[t] points (in that order, back to back).
+Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& opt = PlanOptions());
+
+// First iteration at which every subtree of an n-point tree holds at most
+// TAIL_CAP points (n > TAIL_CAP).
+uint32_t first_tail_level(uint32_t n);
+
+}  // namespace kdt

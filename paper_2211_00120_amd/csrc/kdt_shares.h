@@ -1,0 +1,47 @@
+// kdt_shares.h -- constants and launch-table records shared by the host
+// planner and the kernels (plain C++: the planner also builds without HIP).
+#pragma once
+
+#include <stdint.h>
+
+namespace kdt {
+
+constexpr uint32_t KDT_STATUS_NONFINITE = 4;    // == KDT_ENONFINITE
+constexpr uint32_t KDT_STATUS_INTERNAL = 0x100; // an internal bound or wait check failed
+
+constexpr uint32_t RADIX_HOST = 256;
+constexpr uint32_t MAX_PASSES = 256;       // onesweep passes per build (tile counters)
+constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digit passes over a rank of at most 30 bits (8..10-bit digits)
+constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
+constexpr uint32_t PREP_TILE = 4096;       // points per workgroup of prep / iteration 0
+
+// Tile shapes (items per thread of a 512-thread workgroup); tuning knobs.
+#ifndef KDT_PRESORT_ITEMS
+#define KDT_PRESORT_ITEMS 8
+#endif
+constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
+constexpr uint32_t PRESORT_TILE = 512u * PRESORT_ITEMS;
+constexpr uint32_t HIST_TILE = 16384;      // chunk of the split-widest histogram kernel
+constexpr int TAIL_ITEMS = 8;              // subtree tail: up to 2048 points per workgroup
+constexpr uint32_t TAIL_CAP = 256u * TAIL_ITEMS;
+
+// One tree of a call.
+struct TreeInfo {
+    uint32_t off;        // first entry of the tree in every per-point array
+    uint32_t n;          // points
+    uint32_t box_off;    // first entry of its split-widest domain tables
+    uint32_t idx;        // position in the call's tree list (histogram / box slots)
+};
+
+// One tree's share of a launch.
+struct TreeStep {
+    uint32_t tree;       // index into the TreeInfo table
+    uint32_t level;      // iteration processed (tail: first iteration it runs)
+    uint32_t tile0;      // first tile (tail: first workgroup) of this share
+    uint32_t hist;       // word offset of the share's digit histograms for this iteration
+    uint32_t hist_next;  // word offset of its histograms for the next iteration (~0u: none)
+    uint32_t G;          // tail: level-l0 subtrees per workgroup
+    uint32_t buf;        // tail: record buffer (0/1) that holds the tree's level-l0 records
+};
+
+}  // namespace kdt

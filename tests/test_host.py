@@ -123,3 +123,17 @@ def test_batched_argument_errors_and_sizes():
     one = np.array([0, 123457], np.uint32)
     assert lib.kdt_batched_workspace_bytes(one.ctypes.data_as(ctypes.c_void_p), 1, 3, 1) \
         == lib.kdt_workspace_bytes(123457, 3, 1)
+
+
+def test_planner_invariants(tmp_path):
+    """Every launch of a planned call tiles exactly the work of its trees;
+    histogram, domain-table and workspace ranges never overlap; tail groups
+    fit one workgroup (random batches and single trees)."""
+    src = os.path.join(ROOT, "tests", "host", "plan_check.cpp")
+    inc = os.path.join(ROOT, "paper_2211_00120_amd", "csrc")
+    exe = str(tmp_path / "plan_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", inc, src, os.path.join(inc, "kdt_plan.cpp"), "-o", exe],
+                   check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("ok")
