@@ -27,6 +27,13 @@ Workloads (--workload):
                graph and replayed; the line also carries the same clouds built
                one kdt_build_ws call after another on one stream
                ("per_cloud"), and whether both give identical bytes
+  serving      an open-loop request trace (Poisson arrivals, 2000 per second;
+               each request k uniform in {2,3,4}, N log-uniform in [1e3, 4e6],
+               points uniform in [0,1)^k) replayed into the build server
+               (64 GiB pool): value is served points per second, with p50/p99
+               latency from the scheduled arrival, beside the same trace built
+               one request at a time in arrival order ("fifo"); --requests
+               sets the trace length
 """
 from __future__ import annotations
 
@@ -267,6 +274,154 @@ def run_batched(args, data, mode, cfg):
     }
 
 
+def run_serving(args):
+    """Replay the request trace into kdt_server_* and, for comparison, build
+    the same requests one at a time in arrival order."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2211_00120_amd import kdt, workloads
+
+    arrivals, ks, ns, _ = workloads.cfg_serving_trace(requests=args.requests, seed=5)
+    R = len(arrivals)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    # request points: views into a few pinned host buffers of uniform points
+    # (request i reads buffer i mod B), so the trace needs no per-request
+    # generation while it is replayed
+    nbuf = 8
+    nmax = int(ns.max())
+    gen = torch.Generator().manual_seed(5)
+    bufs = [torch.rand(nmax * 4, generator=gen, dtype=torch.float32).pin_memory() for _ in range(nbuf)]
+    views = [bufs[i % nbuf][: int(ns[i]) * int(ks[i])].view(int(ns[i]), int(ks[i])) for i in range(R)]
+    total_pts = int(ns.sum())
+    print(f"# serving: {R} requests, {total_pts} points, offered {total_pts / arrivals[-1] / 1e6:.0f} Mpts/s",
+          file=sys.stderr, flush=True)
+
+    def replay(srv):
+        tickets = [None] * R
+        done = {}
+        lock = threading.Lock()
+        submitted = [0]
+
+        def reaper():
+            nxt = 0
+            while len(done) < R:
+                with lock:
+                    hi = submitted[0]
+                progressed = False
+                for i in range(nxt, hi):
+                    if i in done:
+                        continue
+                    r = srv.poll(tickets[i])
+                    if r is None:
+                        continue
+                    done[i] = (r.status, r.t_admit, r.t_done, r.device_ms, r.batch_requests)
+                    srv.release(tickets[i])
+                    progressed = True
+                while nxt in done:
+                    nxt += 1
+                if not progressed:
+                    time.sleep(50e-6)
+
+        th = threading.Thread(target=reaper)
+        th.start()
+        t0 = kdt.clock() + 0.05
+        for i in range(R):
+            target = t0 + float(arrivals[i])
+            while True:
+                dt = target - kdt.clock()
+                if dt <= 0:
+                    break
+                if dt > 300e-6:
+                    time.sleep(dt - 200e-6)
+            tickets[i] = srv.submit(views[i], kdt.ROUND_ROBIN)
+            with lock:
+                submitted[0] = i + 1
+        th.join()
+        return t0, done
+
+    with kdt.Server(64 << 30, max_inflight=args.inflight, max_batch_requests=64, max_batch_points=1 << 26) as srv:
+        # warm-up: one request of each k, small and large, before the replay
+        warm = [srv.submit(bufs[0][: n * k].view(n, k), kdt.ROUND_ROBIN) for k in (2, 3, 4) for n in (1000, nmax)]
+        for t in warm:
+            srv.wait(t)
+            srv.release(t)
+        t0, done = replay(srv)
+    lat = np.array([done[i][2] - (t0 + arrivals[i]) for i in range(R)]) * 1e3
+    dev_ms = np.array([done[i][3] for i in range(R)])
+    bsz = np.array([done[i][4] for i in range(R)])
+    statuses = {done[i][0] for i in range(R)}
+    makespan = max(done[i][2] for i in range(R)) - t0
+    served = total_pts / makespan / 1e6
+    print(f"# served: {served:.1f} Mpts/s, p50 {np.percentile(lat, 50):.2f} ms, p99 {np.percentile(lat, 99):.2f} ms,"
+          f" statuses {statuses}", file=sys.stderr, flush=True)
+
+    # the same requests one at a time in arrival order (kdt_build_ws with a
+    # preallocated workspace; copy-in included, as for the server)
+    stream = torch.cuda.current_stream()
+    d_in = torch.empty(nmax * 4, dtype=torch.float32, device=dev)
+    tree = torch.empty(nmax * 4, dtype=torch.float32, device=dev)
+    perm = torch.empty(nmax, dtype=torch.int32, device=dev)
+    dim = torch.empty(nmax, dtype=torch.uint8, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(kdt.workspace_bytes(nmax, k, 0) for k in (2, 3, 4)), dtype=torch.uint8, device=dev)
+    dur = np.zeros(R)
+    for i in range(R):
+        n, k = int(ns[i]), int(ks[i])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        x = d_in[: n * k].view(n, k)
+        x.copy_(views[i], non_blocking=True)
+        kdt.build_ws(x, kdt.ROUND_ROBIN, tree=tree[: n * k].view(n, k), perm=perm[:n], dim=dim[:n], status=st,
+                     workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        dur[i] = time.perf_counter() - a
+    fin = np.zeros(R)
+    t = 0.0
+    for i in range(R):
+        t = max(t, float(arrivals[i])) + dur[i]
+        fin[i] = t
+    fifo_lat = (fin - arrivals) * 1e3
+    fifo = {"value": round(total_pts / fin[-1] / 1e6, 3), "unit": "Mpoints/s",
+            "p50_ms": round(float(np.percentile(fifo_lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(fifo_lat, 99)), 3),
+            "busy_s": round(float(dur.sum()), 3)}
+    print(f"# fifo: {fifo}", file=sys.stderr, flush=True)
+
+    # each result in the mix equals the request built alone: a sample
+    same = True
+    with kdt.Server(8 << 30, max_inflight=args.inflight, max_batch_requests=64) as srv:
+        pick = list(range(0, R, max(1, R // 24)))[:24]
+        tks = [srv.submit(views[i], kdt.ROUND_ROBIN) for i in pick]
+        for i, t in zip(pick, tks):
+            n, k = int(ns[i]), int(ks[i])
+            t_tree, t_perm, t_dim = srv.fetch(t)
+            x = views[i].to(dev)
+            a_tree, a_perm, a_dim, _ = kdt.build_ws(x, kdt.ROUND_ROBIN)
+            torch.cuda.synchronize()
+            same = same and bool(torch.equal(t_tree, a_tree) and torch.equal(t_perm, a_perm)
+                                 and torch.equal(t_dim, a_dim))
+            srv.release(t)
+    return {
+        "value": round(served, 3), "makespan_s": round(makespan, 4),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3),
+                       "mean": round(float(lat.mean()), 3)},
+        "device_ms_per_batch": {"p50": round(float(np.percentile(dev_ms, 50)), 3),
+                                "p99": round(float(np.percentile(dev_ms, 99)), 3)},
+        "mean_batch_requests": round(float(bsz.mean()), 2),
+        "offered_Mpts_s": round(total_pts / float(arrivals[-1]) / 1e6, 1),
+        "statuses_ok": statuses == {0},
+        "fifo": fifo,
+        "mix_equals_alone": same,
+        "requests": R,
+        "points": total_pts,
+    }
+
+
 def cpu_baseline_clouds(pts, offsets, target_s: float):
     """The oracle over whole clouds, in order, until about target_s seconds."""
     import oracle
@@ -297,6 +452,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
+    ap.add_argument("--inflight", type=int, default=4, help="serving: batches on the device at once")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="before warmup, run one device-to-device copy of this many MiB (a reference kernel "
                          "of known traffic for HBM byte counters)")
@@ -312,6 +469,20 @@ def main():
 
     from paper_2211_00120_amd import kdt
 
+    if args.workload == "serving":
+        r = run_serving(args)
+        cfg = {"workload": "serving", "requests": r["requests"], "points": r["points"],
+               "arrivals": "Poisson 2000/s", "k": "uniform {2,3,4}", "n": "log-uniform [1e3, 4e6]",
+               "dim_mode": "round_robin", "hbm_budget_GiB": 64, "max_inflight": args.inflight, "seed": 5}
+        out = {"metric": METRIC, "value": r["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": 1,
+               "warmup": 0, "ms_per_step": round(r["makespan_s"] * 1e3, 3), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32 in, u32 ranks", "data": "synthetic",
+               "config": cfg, "roofline": None, "cpu_baseline": None, "latency_ms": r["latency_ms"],
+               "device_ms_per_batch": r["device_ms_per_batch"], "mean_batch_requests": r["mean_batch_requests"],
+               "offered_Mpts_s": r["offered_Mpts_s"], "fifo": r["fifo"], "mix_equals_alone": r["mix_equals_alone"],
+               "statuses_ok": r["statuses_ok"]}
+        print(json.dumps(out), flush=True)
+        return
     pts, mode, cfg = make_workload(args.workload, args.n, args.k)
     if args.workload == "batched4096":
         r = run_batched(args, pts, mode, cfg)

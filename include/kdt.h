@@ -140,6 +140,84 @@ kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, u
 void kdt_release_cached(void);
 
 /*
+ * Build server: a request loop that builds trees for a stream of requests of
+ * mixed size, k and split rule on one device.
+ *
+ * The server owns one device pool of hbm_budget_bytes, allocated once.  A
+ * worker thread admits queued requests in arrival order whenever a batch
+ * slot is free and their buffers fit the pool: the oldest request together
+ * with the queued requests of the same k and split rule (up to
+ * max_batch_requests and max_batch_points) becomes one batched build
+ * (kdt_build_batched's kernels) on the slot's own stream, so up to
+ * max_inflight batches run on the device at once and requests that arrive
+ * while others run start as soon as a slot and memory free up.  A request's
+ * points are copied from its host buffer when it is admitted; its tree,
+ * permutation and split dimensions stay in the pool, at the device
+ * addresses the result reports, until kdt_server_release.  Each result is
+ * exactly the tree kdt_build_ws builds for that request alone.
+ *
+ * Timestamps are seconds on the clock kdt_clock() reads (monotonic).
+ * The calls are thread-safe.  No stream priority other than the default is
+ * used.
+ */
+typedef struct kdt_server kdt_server;
+
+typedef struct kdt_server_config {
+    size_t hbm_budget_bytes;     /* device pool; every request must fit it alone */
+    uint32_t max_inflight;       /* batches on the device at once, 1..8 (one stream each) */
+    uint32_t max_batch_requests; /* requests merged into one batch, >= 1 */
+    uint64_t max_batch_points;   /* points merged into one batch (a larger request runs alone) */
+} kdt_server_config;
+
+typedef struct kdt_request {
+    const float* h_points;       /* host, n*k float32; must stay valid until the request is done */
+    uint32_t n, k;               /* 0..KDT_MAX_POINTS points of dimension 1..4 */
+    int dim_mode;                /* KDT_DIM_ROUND_ROBIN or KDT_DIM_WIDEST */
+} kdt_request;
+
+typedef struct kdt_result {
+    int status;                  /* KDT_OK, or KDT_ENONFINITE for a NaN/inf coordinate */
+    uint32_t n, k;
+    const float* d_tree;         /* device, n*k float32 (level order), owned by the server */
+    const uint32_t* d_perm;      /* device, n uint32: original index of node s */
+    const uint8_t* d_dim;        /* device, n uint8: split dimension of node s */
+    double t_submit, t_admit, t_done;
+    double device_ms;            /* device time of the batch that built it (copy-in included) */
+    uint32_t batch_requests;     /* requests in that batch */
+} kdt_result;
+
+/* Create a server on the current device.  KDT_EINVAL for a bad config,
+ * KDT_ENOMEM if the pool cannot be allocated. */
+kdt_status kdt_server_create(const kdt_server_config* cfg, kdt_server** out);
+
+/* Queue a request; *ticket identifies it.  KDT_EINVAL for bad arguments,
+ * KDT_ENOMEM if the request cannot fit the pool even alone. */
+kdt_status kdt_server_submit(kdt_server* server, const kdt_request* req, uint64_t* ticket);
+
+/* KDT_OK and *out filled once the request is done, KDT_EBUSY before,
+ * KDT_ENOTFOUND for an unknown or released ticket. */
+kdt_status kdt_server_poll(kdt_server* server, uint64_t ticket, kdt_result* out);
+
+/* As kdt_server_poll, but blocks until the request is done. */
+kdt_status kdt_server_wait(kdt_server* server, uint64_t ticket, kdt_result* out);
+
+/* Copy a done request's tree, permutation and dimensions (each nullable)
+ * into caller device buffers of n*k float32 / n uint32 / n uint8, enqueued on
+ * `stream`.  KDT_EBUSY if it is not done yet. */
+kdt_status kdt_server_copy_out(kdt_server* server, uint64_t ticket, float* d_tree, uint32_t* d_perm,
+                               uint8_t* d_dim, hipStream_t stream);
+
+/* Give a done request's buffers back to the pool; its device pointers become
+ * invalid.  KDT_EBUSY if it is not done yet. */
+kdt_status kdt_server_release(kdt_server* server, uint64_t ticket);
+
+/* Finish the queued and running requests, then free everything. */
+kdt_status kdt_server_destroy(kdt_server* server);
+
+/* Seconds on the monotonic clock of the server's timestamps. */
+double kdt_clock(void);
+
+/*
  * Measurement hook for benchmarks.  While enabled, every kernel a build
  * enqueues is bracketed by a pair of hipEvents recorded on the build's own
  * stream, tagged with the kernel's name and its algorithmic byte count (the

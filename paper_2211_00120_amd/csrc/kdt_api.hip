@@ -38,6 +38,7 @@
 #include "../../include/kdt.h"
 #include "kdt_kernels.h"
 #include "kdt_layout.h"
+#include "kdt_host.h"
 #include "kdt_plan.h"
 
 namespace {
@@ -480,6 +481,24 @@ kdt_status write_ok_status(uint32_t* d_status, hipStream_t stream)
 }
 
 }  // namespace
+
+namespace kdt {
+
+kdt_status enqueue_plan(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim,
+                        uint32_t* status, char* ws, const void* h_tables, hipStream_t st)
+{
+    return enqueue(p, pts, tree, perm, dim, status, ws, h_tables, st);
+}
+
+void set_last_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+}  // namespace kdt
 
 extern "C" {
 

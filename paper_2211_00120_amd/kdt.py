@@ -41,6 +41,15 @@ _SIGS = {
                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "kdt_release_cached": (None, []),
+    "kdt_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "kdt_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kdt_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "kdt_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]),
+    "kdt_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "kdt_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "kdt_server_copy_out": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "kdt_clock": (ctypes.c_double, []),
     "kdt_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "kdt_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "kdt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -51,6 +60,23 @@ _SIGS = {
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
                 ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_uint32),
+                ("max_batch_requests", ctypes.c_uint32), ("max_batch_points", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("h_points", ctypes.c_void_p), ("n", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("dim_mode", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("d_tree", ctypes.c_void_p), ("d_perm", ctypes.c_void_p), ("d_dim", ctypes.c_void_p),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("device_ms", ctypes.c_double), ("batch_requests", ctypes.c_uint32)]
 
 
 class KdtError(RuntimeError):
@@ -208,3 +234,94 @@ def profile_collect():
         raise RuntimeError(f"kdt_profile_collect failed: {last_error()}")
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
                                    "alg_bytes": float(arr[i].alg_bytes)} for i in range(m)}
+
+
+def clock() -> float:
+    """Seconds on the monotonic clock of the server's timestamps."""
+    return float(lib().kdt_clock())
+
+
+class Server:
+    """kdt_server_*: a request loop that builds trees for submitted host point
+    arrays, batching queued requests of the same shape and running up to
+    `max_inflight` batches at once inside an HBM budget."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_batch_requests: int = 64,
+                 max_batch_points: int = 1 << 26):
+        cfg = ServerConfig(hbm_budget_bytes, max_inflight, max_batch_requests, max_batch_points)
+        h = ctypes.c_void_p()
+        rc = lib().kdt_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != OK:
+            raise KdtError(rc, "kdt_server_create")
+        self._h = h
+        self._keep = {}      # ticket -> host array kept alive until done
+
+    def submit(self, points, mode: int = ROUND_ROBIN) -> int:
+        """Queue a build of `points` (an (n, k) float32 C-contiguous host array:
+        numpy, or a torch CPU tensor, ideally pinned); returns the ticket."""
+        import numpy as np
+        if hasattr(points, "data_ptr"):
+            n, k = points.shape
+            if points.dtype.__str__() != "torch.float32" or not points.is_contiguous() or points.is_cuda:
+                raise ValueError("points must be a contiguous float32 CPU tensor")
+            ptr = points.data_ptr()
+        else:
+            points = np.ascontiguousarray(points, dtype=np.float32)
+            n, k = points.shape
+            ptr = points.ctypes.data
+        req = Request(ctypes.c_void_p(ptr), n, k, mode)
+        t = ctypes.c_uint64()
+        rc = lib().kdt_server_submit(self._h, ctypes.byref(req), ctypes.byref(t))
+        if rc != OK:
+            raise KdtError(rc, "kdt_server_submit")
+        self._keep[t.value] = points
+        return t.value
+
+    def poll(self, ticket: int):
+        """The Result once the request is done, else None."""
+        r = Result()
+        rc = lib().kdt_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == EBUSY:
+            return None
+        if rc != OK:
+            raise KdtError(rc, "kdt_server_poll")
+        return r
+
+    def wait(self, ticket: int):
+        r = Result()
+        rc = lib().kdt_server_wait(self._h, ticket, ctypes.byref(r))
+        if rc != OK:
+            raise KdtError(rc, "kdt_server_wait")
+        return r
+
+    def release(self, ticket: int):
+        rc = lib().kdt_server_release(self._h, ticket)
+        if rc != OK:
+            raise KdtError(rc, "kdt_server_release")
+        self._keep.pop(ticket, None)
+
+    def fetch(self, ticket: int):
+        """Copy a done request's (tree, perm, dim) from the server's pool into
+        new device tensors (on torch's current stream)."""
+        import torch
+        r = self.wait(ticket)
+        n, k = r.n, r.k
+        tree = torch.empty((n, k), dtype=torch.float32, device="cuda")
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        dim = torch.empty(n, dtype=torch.uint8, device="cuda")
+        rc = lib().kdt_server_copy_out(self._h, ticket, _ptr(tree), _ptr(perm), _ptr(dim), _stream(None))
+        if rc != OK:
+            raise KdtError(rc, "kdt_server_copy_out")
+        return tree, perm, dim
+
+    def close(self):
+        if self._h:
+            lib().kdt_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -137,3 +137,34 @@ def test_planner_invariants(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True, timeout=600)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip().endswith("ok")
+
+
+def test_server_pool_and_admission(tmp_path):
+    """The server's pool allocator against a byte-map model, and the batch
+    choice: oldest request first, one (k, split rule) per batch, limits
+    honoured, both blocks fit, and no further candidate would have fitted."""
+    src = os.path.join(ROOT, "tests", "host", "admit_check.cpp")
+    inc = os.path.join(ROOT, "paper_2211_00120_amd", "csrc")
+    exe = str(tmp_path / "admit_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", inc, src, os.path.join(inc, "kdt_plan.cpp"), "-o", exe],
+                   check=True)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.strip().endswith("ok")
+
+
+def test_server_argument_errors():
+    lib = kdt.lib()
+    h = ctypes.c_void_p()
+    bad = kdt.ServerConfig(0, 4, 8, 1 << 20)
+    assert lib.kdt_server_create(ctypes.byref(bad), ctypes.byref(h)) == kdt.EINVAL
+    bad = kdt.ServerConfig(1 << 30, 0, 8, 1 << 20)
+    assert lib.kdt_server_create(ctypes.byref(bad), ctypes.byref(h)) == kdt.EINVAL
+    bad = kdt.ServerConfig(1 << 30, 9, 8, 1 << 20)
+    assert lib.kdt_server_create(ctypes.byref(bad), ctypes.byref(h)) == kdt.EINVAL
+    t = ctypes.c_uint64()
+    req = kdt.Request(None, 10, 3, 0)
+    assert lib.kdt_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == kdt.EINVAL
+    assert lib.kdt_server_poll(None, 1, None) == kdt.EINVAL
+    assert lib.kdt_server_release(None, 1) == kdt.EINVAL
+    assert lib.kdt_clock() > 0.0
