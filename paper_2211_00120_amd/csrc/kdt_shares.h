@@ -22,8 +22,9 @@ constexpr uint32_t PREP_TILE = 4096;       // points per workgroup of prep / ite
 constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
 constexpr uint32_t PRESORT_TILE = 512u * PRESORT_ITEMS;
 constexpr uint32_t HIST_TILE = 16384;      // chunk of the split-widest histogram kernel
-constexpr int TAIL_ITEMS = 8;              // subtree tail: up to 2048 points per workgroup
-constexpr uint32_t TAIL_CAP = 256u * TAIL_ITEMS;
+constexpr int TAIL_THREADS = 512;          // subtree tail: 512 threads x 4 slots = up to 2048 points
+constexpr int TAIL_ITEMS = 4;
+constexpr uint32_t TAIL_CAP = (uint32_t)TAIL_THREADS * TAIL_ITEMS;
 
 // One tree of a call.
 struct TreeInfo {

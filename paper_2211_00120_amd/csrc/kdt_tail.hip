@@ -34,6 +34,7 @@
 #include "kdt_device.h"
 #include "kdt_kernels.h"
 #include "kdt_layout.h"
+#include "kdt_sweep.h"
 
 namespace kdt {
 
@@ -68,27 +69,50 @@ __device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, c
     }
 }
 
+// Digit offsets of one LDS sort pass: wh[w*RADIX + digit] holds wave w's
+// count of each digit; it becomes wave w's exclusive offset inside the
+// digit's run, and dstart[digit] the run's start.  Contains barriers.
+__device__ __forceinline__ void tail_digit_offsets(uint16_t* wh, uint32_t* dstart, uint32_t* sh)
+{
+    const uint32_t t = threadIdx.x;
+    uint32_t run = 0;
+    if (t < RADIX) {
+#pragma unroll
+        for (int ww = 0; ww < TAIL_THREADS / 64; ++ww) {
+            const uint32_t x = wh[ww * RADIX + t];
+            wh[ww * RADIX + t] = (uint16_t)run;
+            run += x;
+        }
+    }
+    const uint32_t ex = sweep_excl_scan(run, sh);
+    if (t < RADIX) dstart[t] = ex;
+}
+
 template <int K, bool WIDEST>
-__global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 {
     constexpr int ITEMS = TAIL_ITEMS;
+    constexpr int NW = TAIL_THREADS / 64;
     constexpr uint32_t C = TAIL_CAP;
-    constexpr uint32_t CW = 64u * ITEMS;           // positions walked per wave
-    constexpr uint32_t NODES = WIDEST ? 2u * C + 64u : 1u;
+    constexpr uint32_t CW = 64u * ITEMS;           // slots (and list positions) per wave
+    // local nodes: every segment of every tail iteration is non-empty, so a
+    // group fixes at most C of them
+    constexpr uint32_t NODES = WIDEST ? C : 1u;
     __shared__ uint16_t ord[K][C];
     __shared__ uint16_t seg[C];
     __shared__ uint16_t tmp[C];
-    __shared__ uint64_t ubuf[C];                   // sort exchange / per-wave segment counters
-    __shared__ uint32_t wh[NWAVE * RADIX];
+    __shared__ union {
+        uint64_t x[C];                             // sort exchange
+        uint16_t cnt[NW][C];                       // per-(wave, segment) counters of an iteration
+    } ub;
+    __shared__ uint16_t wh[NW * RADIX];
     __shared__ uint32_t dstart[RADIX];
-    __shared__ uint32_t sh[NWAVE];
+    __shared__ uint32_t sh[NW];
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
     __shared__ uint8_t ndim[NODES];
     __shared__ float nplane[NODES];
     __shared__ float rootbox[2][8];
-    __shared__ uint32_t node[C];                   // final node of each slot
     __shared__ uint32_t bxk[8];                    // from_points split-widest: scene box keys
-    uint16_t(*cnt)[C] = reinterpret_cast<uint16_t(*)[C]>(ubuf);   // [NWAVE][C]
 
     const Outs& o = a.o;
     TreeStep stp;
@@ -144,7 +168,6 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
             if (ok[i]) rec[i] = load_rec4<K>(a.rin[stp.buf & 1u], off + off0 + e);
             seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
         }
-        node[e] = 0xFFFFFFFFu;
     }
     if (!FP) {
 #pragma unroll
@@ -183,6 +206,8 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
                 o.dimnode[off] = (uint8_t)d0;
             }
         }
+        // a single point is the root
+        if (L < 2u && ok[0] && threadIdx.x == 0) place_pt<K, WIDEST>(o, ti, 0u, idx[0], pc[0]);
     }
     if (!FP && WIDEST && threadIdx.x < gc) {
         // domain of each group root, written by its parent's pivot
@@ -200,13 +225,12 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
         // i0, so both are children of the same parent)
         else free_dim = o.dimnode[off + ((v0.Fl + i0 - 1u) >> 1)];
     }
-    if (FP && L < 2u && threadIdx.x == 0) node[0] = 0u;   // a single point is the root
     __syncthreads();
 
     // ---- ord_d: the group sorted by rank_d (stable LSD over 8-bit digits) ----
     for (uint32_t d = 0; d < (uint32_t)K; ++d) {
         if (d == free_dim) {
-            for (uint32_t p = threadIdx.x; p < m; p += BLOCK) ord[d][p] = (uint16_t)p;
+            for (uint32_t p = threadIdx.x; p < m; p += TAIL_THREADS) ord[d][p] = (uint16_t)p;
             continue;
         }
         uint64_t it[ITEMS];
@@ -219,17 +243,18 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
             uint32_t dig[ITEMS], rnk[ITEMS];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(it[i] >> sft) & 0xFFu;
-            wave_multisplit<ITEMS>(dig, ok, rnk, wh + w * RADIX);
-            tile_digit_counts(wh, dstart, sh);
+            wave_multisplit16<8, ITEMS>(dig, ok, rnk, wh + w * RADIX, ITEMS);
+            __syncthreads();
+            tail_digit_offsets(wh, dstart, sh);
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i)
-                if (ok[i]) ubuf[dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i]] = it[i];
+                if (ok[i]) ub.x[dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i]] = it[i];
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                if (ok[i]) it[i] = ubuf[p];
+                if (ok[i]) it[i] = ub.x[p];
             }
             __syncthreads();
         }
@@ -249,9 +274,9 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
         const uint32_t S = gc << t;                       // group segments on this level
         const uint32_t gbits = rank_bits(S);
         const bool last = (l + 2u == L);
-        for (uint32_t q = threadIdx.x; q < S; q += BLOCK) {
+        for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) {
 #pragma unroll
-            for (int ww = 0; ww < NWAVE; ++ww) cnt[ww][q] = 0;
+            for (int ww = 0; ww < NW; ++ww) ub.cnt[ww][q] = 0;
         }
         __syncthreads();
         // position of each point inside its segment in the order of the
@@ -271,23 +296,24 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
                 const uint64_t peers = match_bits(q, gbits, valid);
                 const uint32_t below = count_below(peers);
                 uint32_t base = 0;
-                if (valid) base = cnt[w][q];
-                if (valid && below == 0) cnt[w][q] = (uint16_t)(base + (uint32_t)__popcll(peers));
+                if (valid) base = ub.cnt[w][q];
+                if (valid && below == 0) ub.cnt[w][q] = (uint16_t)(base + (uint32_t)__popcll(peers));
                 if (valid) tmp[e] = (uint16_t)((w << 12) | (base + below));
             }
         }
         __syncthreads();
-        for (uint32_t q = threadIdx.x; q < S; q += BLOCK) {
+        for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) {
             uint32_t run = 0;
 #pragma unroll
-            for (int ww = 0; ww < NWAVE; ++ww) {
-                const uint32_t c = cnt[ww][q];
-                cnt[ww][q] = (uint16_t)run;
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = ub.cnt[ww][q];
+                ub.cnt[ww][q] = (uint16_t)run;
                 run += c;
             }
         }
         __syncthreads();
-        // tag update (Sec. 3.2)
+        // tag update (Sec. 3.2); each slot's owner places its point as soon
+        // as its node is known
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
@@ -295,12 +321,12 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
             const uint32_t q = seg[e];
             if (q == DONE) continue;
             const uint32_t tv = tmp[e];
-            const uint32_t wr = (tv & 0xFFFu) + cnt[tv >> 12][q];
+            const uint32_t wr = (tv & 0xFFFu) + ub.cnt[tv >> 12][q];
             const uint32_t gq = (i0 << t) + q;
             const uint32_t ls = seg_left_size(vl, gq);
             if (wr == ls) {
                 const uint32_t sn = vl.Fl + gq;
-                node[e] = sn;
+                place_pt<K, WIDEST>(o, ti, sn, idx[i], pc[i]);
                 if (WIDEST) {
                     const uint32_t ds = segdim[cur][q];
                     const float plane = pickf(pc[i], ds);
@@ -332,7 +358,7 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
             } else {
                 const uint32_t side = wr > ls ? 1u : 0u;
                 if (last) {
-                    node[e] = vl.Fl + vl.nseg + 2u * gq + side;
+                    place_pt<K, WIDEST>(o, ti, vl.Fl + vl.nseg + 2u * gq + side, idx[i], pc[i]);
                     seg[e] = (uint16_t)DONE;
                 } else {
                     seg[e] = (uint16_t)(2u * q + side);
@@ -342,19 +368,13 @@ __global__ void __launch_bounds__(BLOCK) k_tail(TailArgs a)
         __syncthreads();
         cur ^= 1u;
     }
-    // placement of every slot at its node
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-        if (ok[i]) place_pt<K, WIDEST>(o, ti, node[e], idx[i], pc[i]);
-    }
 }
 
 template <int K>
 static void tail_k(const TailArgs& a, uint32_t groups, bool widest, hipStream_t st)
 {
-    if (widest) k_tail<K, true><<<groups, BLOCK, 0, st>>>(a);
-    else k_tail<K, false><<<groups, BLOCK, 0, st>>>(a);
+    if (widest) k_tail<K, true><<<groups, TAIL_THREADS, 0, st>>>(a);
+    else k_tail<K, false><<<groups, TAIL_THREADS, 0, st>>>(a);
 }
 
 void launch_tail(int k, const TailArgs& a, uint32_t groups, bool widest, hipStream_t st)
