@@ -140,6 +140,41 @@ kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, u
 void kdt_release_cached(void);
 
 /*
+ * Autotuner.  The level sorts can run with 8-, 9- or 10-bit digits (fewer
+ * bits: more passes, smaller histograms and look-back tables) and with tiles
+ * of 512 x 4 or 512 x 8 records.  Without tuning the planner picks the
+ * fewest passes and the largest tile the level's subtrees fill.
+ * kdt_tune_batched times a whole kdt_build_batched of the given batch (in
+ * device memory) for every combination, `reps` builds each after one
+ * warm-up, and records the fastest for builds of this k, split rule and
+ * rank width (bits of the largest cloud's n-1, counting only clouds of more
+ * than 2048 points); single, batched and served builds of that class use it
+ * from then on.  The choice never changes the tree.  Synchronises `stream`;
+ * d_ws needs kdt_batched_workspace_bytes(...) bytes (those sizes, like
+ * kdt_workspace_bytes, already hold every choice).
+ */
+typedef struct kdt_tuning {
+    uint32_t radix_bits;   /* 0 (planner's choice) or 8..10 */
+    uint32_t level_items;  /* 0 (planner's choice), 4 or 8: cap on records per thread of level-sort tiles */
+    double ms;             /* kdt_tune_batched: time of one build with this choice */
+} kdt_tuning;
+
+kdt_status kdt_tune_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
+                            int dim_mode, void* d_ws, size_t ws_bytes, uint32_t reps,
+                            hipStream_t stream, kdt_tuning* best);
+
+/* Read or set the recorded choice for (k, dim_mode, rank_bits). */
+kdt_status kdt_tuning_get(uint32_t k, int dim_mode, uint32_t rank_bits, kdt_tuning* out);
+kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kdt_tuning* t);
+
+/* Text file of recorded choices, one "k dim_mode rank_bits radix_bits
+ * level_items" line each; load merges into the current table and fails
+ * without changing it on a malformed file. */
+kdt_status kdt_tuning_save(const char* path);
+kdt_status kdt_tuning_load(const char* path);
+void kdt_tuning_clear(void);
+
+/*
  * Build server: a request loop that builds trees for a stream of requests of
  * mixed size, k and split rule on one device.
  *

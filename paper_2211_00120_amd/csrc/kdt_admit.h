@@ -132,7 +132,7 @@ inline BatchChoice choose_batch(const std::vector<QueuedShape>& queue, const Are
             tot += n[j];
         }
         c.out_bytes = batch_output_bytes(tot, h.k);
-        c.ws_bytes = make_plan(n, h.k, h.mode == 1).total;
+        c.ws_bytes = workspace_bytes_any(n, h.k, h.mode == 1);
         ArenaAllocator trial = pool;
         if (trial.alloc(c.out_bytes) == ArenaAllocator::NPOS) return false;
         return trial.alloc(c.ws_bytes) != ArenaAllocator::NPOS;
@@ -153,7 +153,7 @@ inline BatchChoice choose_batch(const std::vector<QueuedShape>& queue, const Are
 // Bytes a single request needs in an otherwise empty pool (both blocks).
 inline size_t request_footprint(uint32_t n, uint32_t k, int mode)
 {
-    return batch_output_bytes(n, k) + make_plan(std::vector<uint32_t>{n}, k, mode == 1).total;
+    return batch_output_bytes(n, k) + workspace_bytes_any(std::vector<uint32_t>{n}, k, mode == 1);
 }
 
 }  // namespace kdt

@@ -303,6 +303,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 a.shift = 8 * ps;
                 a.perm_out = perms + (size_t)d * ntotal;
                 a.rank_table = ranks;
+                a.dimnode = widest ? o.dimnode : nullptr;
                 a.k = k;
                 a.dim = d;
                 a.status = dstatus;
@@ -413,21 +414,22 @@ std::map<std::string, std::shared_ptr<CachedPlan>> g_plans;
 kdt_status batched_plan(const uint32_t* h_offsets, uint32_t C, uint32_t k, bool widest, bool pinned,
                         std::shared_ptr<CachedPlan>& out)
 {
-    std::string key(8 + (size_t)(C + 1) * 4, '\0');
-    const uint32_t wv = widest ? 1u : 0u;
-    memcpy(&key[0], &k, 4);
-    memcpy(&key[4], &wv, 4);
-    memcpy(&key[8], h_offsets, (size_t)(C + 1) * 4);
+    std::vector<uint32_t> n(C);
+    for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
+    // the tuning in effect is part of the key
+    const PlanOptions opt = tuned_options(k, widest, plan_rank_bits(n));
+    std::string key(16 + (size_t)(C + 1) * 4, '\0');
+    const uint32_t head[4] = {k, widest ? 1u : 0u, opt.radix_bits, opt.max_items};
+    memcpy(&key[0], head, 16);
+    memcpy(&key[16], h_offsets, (size_t)(C + 1) * 4);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     std::shared_ptr<CachedPlan> cp;
     auto it = g_plans.find(key);
     if (it != g_plans.end()) {
         cp = it->second;
     } else {
-        std::vector<uint32_t> n(C);
-        for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
         cp = std::make_shared<CachedPlan>();
-        cp->plan = make_plan(n, k, widest);
+        cp->plan = make_plan(n, k, widest, opt);
         g_plans.emplace(key, cp);
     }
     if (pinned && cp->plan.tables && !cp->pinned) {
@@ -505,7 +507,7 @@ extern "C" {
 size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode)
 {
     if (validate_k_mode(k, dim_mode) || n > KDT_MAX_POINTS) return 0;
-    return make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST).total;
+    return workspace_bytes_any(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
 }
 
 kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
@@ -567,9 +569,9 @@ kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipS
 size_t kdt_batched_workspace_bytes(const uint32_t* h_offsets, uint32_t C, uint32_t k, int dim_mode)
 {
     if (validate_k_mode(k, dim_mode) || validate_offsets(h_offsets, C)) return 0;
-    std::shared_ptr<CachedPlan> cp;
-    if (batched_plan(h_offsets, C, k, dim_mode == KDT_DIM_WIDEST, false, cp)) return 0;
-    return cp->plan.total;
+    std::vector<uint32_t> n(C);
+    for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
+    return workspace_bytes_any(n, k, dim_mode == KDT_DIM_WIDEST);
 }
 
 kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
@@ -586,6 +588,129 @@ kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, u
     if (kdt_status s = batched_plan(h_offsets, C, k, dim_mode == KDT_DIM_WIDEST, true, cp)) return s;
     return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, cp->pinned, stream);
 }
+
+kdt_status kdt_tune_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k, int dim_mode,
+                            void* d_ws, size_t ws_bytes, uint32_t reps, hipStream_t stream, kdt_tuning* best)
+{
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (kdt_status s = validate_offsets(h_offsets, C)) return s;
+    if (!best) {
+        set_err("best is null");
+        return KDT_EINVAL;
+    }
+    const bool widest = dim_mode == KDT_DIM_WIDEST;
+    std::vector<uint32_t> n(C);
+    for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
+    const uint64_t ntotal = h_offsets[C];
+    if (ntotal > 0 && !d_points) {
+        set_err("points is null");
+        return KDT_EINVAL;
+    }
+    const size_t need = workspace_bytes_any(n, k, widest);
+    if (!d_ws || ws_bytes < need || ((uintptr_t)d_ws) % ALIGN) {
+        set_err("a %zu-byte aligned workspace of %zu bytes is needed", (size_t)ALIGN, need);
+        return KDT_EINVAL;
+    }
+    memset(best, 0, sizeof *best);
+    const uint32_t bits = plan_rank_bits(n);
+    if (ntotal == 0 || bits == 0) return KDT_OK;   // no tree is built by digit passes: nothing to choose
+    reps = reps ? reps : 1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    kdt_status rc = KDT_OK;
+    PlanOptions chosen;
+    float best_ms = 0.f;
+    for (const PlanOptions& cand : tuning_candidates()) {
+        const Plan p = make_plan(n, k, widest, cand);
+        void* pinned = nullptr;
+        if (p.tables) {
+            if (hipHostMalloc(&pinned, p.blob.size(), hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                set_err("hipHostMalloc of %zu bytes failed", p.blob.size());
+                rc = KDT_ENOMEM;
+                break;
+            }
+            memcpy(pinned, p.blob.data(), p.blob.size());
+        }
+        float ms = 0.f;
+        rc = enqueue(p, d_points, nullptr, nullptr, nullptr, nullptr, (char*)d_ws, pinned, stream);   // warm-up
+        if (rc == KDT_OK && hipEventRecord(e0, stream) != hipSuccess) rc = KDT_EDEVICE;
+        for (uint32_t r = 0; rc == KDT_OK && r < reps; ++r)
+            rc = enqueue(p, d_points, nullptr, nullptr, nullptr, nullptr, (char*)d_ws, pinned, stream);
+        if (rc == KDT_OK && (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = KDT_EDEVICE;
+        (void)hipStreamSynchronize(stream);
+        if (pinned) (void)hipHostFree(pinned);
+        if (rc != KDT_OK) break;
+        ms /= (float)reps;
+        if (best_ms == 0.f || ms < best_ms) {
+            best_ms = ms;
+            chosen = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != KDT_OK) {
+        if (rc == KDT_EDEVICE && !g_err[0]) set_err("HIP error while timing a candidate");
+        return rc;
+    }
+    set_tuned_options(k, widest, bits, chosen);
+    best->radix_bits = chosen.radix_bits;
+    best->level_items = chosen.max_items;
+    best->ms = best_ms;
+    return KDT_OK;
+}
+
+kdt_status kdt_tuning_get(uint32_t k, int dim_mode, uint32_t rank_bits, kdt_tuning* out)
+{
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (!out || rank_bits > 32) {
+        set_err("bad arguments");
+        return KDT_EINVAL;
+    }
+    const PlanOptions o = tuned_options(k, dim_mode == KDT_DIM_WIDEST, rank_bits);
+    memset(out, 0, sizeof *out);
+    out->radix_bits = o.radix_bits;
+    out->level_items = o.max_items;
+    return KDT_OK;
+}
+
+kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kdt_tuning* t)
+{
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (!t || rank_bits > 32 || (t->radix_bits && (t->radix_bits < 8 || t->radix_bits > 10)) ||
+        (t->level_items && t->level_items != 4 && t->level_items != 8)) {
+        set_err("tuning must have radix_bits 0 or 8..10 and level_items 0, 4 or 8");
+        return KDT_EINVAL;
+    }
+    PlanOptions o;
+    o.radix_bits = t->radix_bits;
+    o.max_items = t->level_items;
+    set_tuned_options(k, dim_mode == KDT_DIM_WIDEST, rank_bits, o);
+    return KDT_OK;
+}
+
+kdt_status kdt_tuning_save(const char* path)
+{
+    if (!path || !save_tuning(path)) {
+        set_err("could not write the tuning file");
+        return KDT_EINVAL;
+    }
+    return KDT_OK;
+}
+
+kdt_status kdt_tuning_load(const char* path)
+{
+    if (!path || !load_tuning(path)) {
+        set_err("could not read a valid tuning file");
+        return KDT_EINVAL;
+    }
+    return KDT_OK;
+}
+
+void kdt_tuning_clear(void) { clear_tuning(); }
 
 void kdt_release_cached(void)
 {

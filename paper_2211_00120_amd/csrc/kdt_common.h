@@ -183,6 +183,14 @@ __device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t d)
     return d == 0u ? x : (d == 1u ? y : (d == 2u ? z : w));
 }
 
+__device__ __forceinline__ void set4(uint4& r, uint32_t d, uint32_t v)
+{
+    r.x = d == 0u ? v : r.x;
+    r.y = d == 1u ? v : r.y;
+    r.z = d == 2u ? v : r.z;
+    r.w = d == 3u ? v : r.w;
+}
+
 // Lanes of this wave whose (valid, value) agree with this lane's on the low
 // `bits` bits of value (bits <= 16; one ballot per bit).
 __device__ __forceinline__ uint64_t match_bits(uint32_t value, uint32_t bits, bool valid)

@@ -61,7 +61,8 @@ struct PresortArgs {
     uint32_t* counter;      // dynamic tile counter of this pass
     uint32_t shift;
     uint32_t* perm_out;     // last pass: per tree rank -> local index of this dimension
-    uint32_t* rank_table;   // last pass: point-major ranks, [(off + i)*k + dim]
+    uint32_t* rank_table;   // last pass: point-major ranks, [(off + i)*k + dim], except each tree's root dimension
+    const uint8_t* dimnode; // split-widest: node dims (the root's is tree's first entry); null: root dimension 0
     uint32_t k;
     uint32_t dim;
     uint32_t* status;

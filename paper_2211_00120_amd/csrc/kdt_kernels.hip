@@ -172,6 +172,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         dig[i] = (rec[i].x >> shift) & 0xFFu;
     }
     const uint32_t n = ti.n;
+    // iteration 0 reads the root dimension's ranks as positions in perm_out,
+    // so only the other dimensions go into the (randomly written) rank table
+    const bool to_table = !LAST || a.dim != (a.dimnode ? (uint32_t)a.dimnode[off] : 0u);
     sweep_tile<RB, ITEMS, 2>(
         sm, rec, ok, dig, ITEMS, cnt, a.hist + (size_t)ti.idx * a.hist_stride, 0u, a.lb, g, st.tile0, a.status,
         [&](const uint4& r) { return (r.x >> shift) & 0xFFu; },
@@ -179,7 +182,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
             if (LAST) {
                 a.perm_out[off + pos] = r.y;
-                a.rank_table[(off + r.y) * a.k + a.dim] = pos;
+                if (to_table) a.rank_table[(off + r.y) * a.k + a.dim] = pos;
             } else {
                 reinterpret_cast<uint2*>(a.kvout)[off + pos] = make_uint2(r.x, r.y);
             }
@@ -233,7 +236,8 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
             place<K, WIDEST>(a.o, ti, r < piv ? 1u : 2u, idx);
             continue;
         }
-        const uint4 rec = load_rec4<K>(a.rank_table, off + idx);
+        uint4 rec = load_rec4<K>(a.rank_table, off + idx);
+        set4(rec, d0, r);                   // the root dimension's rank is the position
         const uint32_t side = r > piv ? 1u : 0u;
         store_rec4<K>(a.rout, off + r - side, rec);
         if (acc) {

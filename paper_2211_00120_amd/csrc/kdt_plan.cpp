@@ -1,9 +1,13 @@
 // kdt_plan.cpp -- host planner of a build call (see kdt_plan.h).
 #include "kdt_plan.h"
 
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "kdt_layout.h"
 
@@ -40,7 +44,98 @@ size_t push_table(std::vector<uint8_t>& blob, const void* p, size_t bytes)
     return at;
 }
 
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, bool, uint32_t>, PlanOptions> g_tune;
+
 }  // namespace
+
+std::vector<PlanOptions> tuning_candidates()
+{
+    std::vector<PlanOptions> c;
+    for (uint32_t rb : {8u, 9u, 10u})
+        for (uint32_t items : {4u, 8u}) {
+            PlanOptions o;
+            o.radix_bits = rb;
+            o.max_items = items;
+            c.push_back(o);
+        }
+    return c;
+}
+
+PlanOptions tuned_options(uint32_t k, bool widest, uint32_t bits)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(std::make_tuple(k, widest, bits));
+    return it == g_tune.end() ? PlanOptions() : it->second;
+}
+
+void set_tuned_options(uint32_t k, bool widest, uint32_t bits, const PlanOptions& o)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[std::make_tuple(k, widest, bits)] = o;
+}
+
+void clear_tuning()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
+
+// One line per entry: "k widest bits radix_bits max_items".
+bool save_tuning(const char* path)
+{
+    FILE* f = fopen(path, "w");
+    if (!f) return false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : g_tune)
+        fprintf(f, "%u %d %u %u %u\n", std::get<0>(kv.first), std::get<1>(kv.first) ? 1 : 0, std::get<2>(kv.first),
+                kv.second.radix_bits, kv.second.max_items);
+    return fclose(f) == 0;
+}
+
+bool load_tuning(const char* path)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    std::map<std::tuple<uint32_t, bool, uint32_t>, PlanOptions> t;
+    unsigned k, w, bits, rb, items;
+    int r;
+    bool ok = true;
+    while ((r = fscanf(f, "%u %u %u %u %u", &k, &w, &bits, &rb, &items)) == 5) {
+        if (k < 1 || k > 4 || w > 1 || bits > 32 || (rb && (rb < 8 || rb > 10)) || (items && items != 4 && items != 8)) {
+            ok = false;
+            break;
+        }
+        PlanOptions o;
+        o.radix_bits = rb;
+        o.max_items = items;
+        t[std::make_tuple((uint32_t)k, w == 1u, (uint32_t)bits)] = o;
+    }
+    if (r != EOF) ok = false;
+    fclose(f);
+    if (!ok) return false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : t) g_tune[kv.first] = kv.second;
+    return true;
+}
+
+uint32_t plan_rank_bits(const std::vector<uint32_t>& n)
+{
+    uint32_t b = 0;
+    for (uint32_t x : n)
+        if (x > TAIL_CAP) b = std::max(b, rank_bits(x));
+    return b;
+}
+
+size_t workspace_bytes_any(const std::vector<uint32_t>& n, uint32_t k, bool widest)
+{
+    size_t b = 0;
+    PlanOptions automatic;
+    automatic.radix_bits = 0;
+    automatic.max_items = 0;
+    for (const PlanOptions& o : tuning_candidates()) b = std::max(b, make_plan(n, k, widest, o).total);
+    return std::max(b, make_plan(n, k, widest, automatic).total);
+}
 
 uint32_t first_tail_level(uint32_t n)
 {
@@ -52,8 +147,10 @@ uint32_t first_tail_level(uint32_t n)
     return l;
 }
 
-Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& opt)
+Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& given)
 {
+    const PlanOptions opt =
+        (given.radix_bits || given.max_items) ? given : tuned_options(k, widest, plan_rank_bits(n));
     Plan p;
     p.k = k;
     p.widest = widest;

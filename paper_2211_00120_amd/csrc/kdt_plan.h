@@ -66,7 +66,22 @@ struct Plan {
 };
 
 // Plan of a call over trees of n[t] points (in that order, back to back).
+// Default options take the tuned choice for (k, rule, rank bits), if any.
 Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& opt = PlanOptions());
+
+// Rank bits of the largest tree built by digit passes (0 if none).
+uint32_t plan_rank_bits(const std::vector<uint32_t>& n);
+
+// Workspace bytes that hold the plan under every tuning choice.
+size_t workspace_bytes_any(const std::vector<uint32_t>& n, uint32_t k, bool widest);
+
+// The autotuner's table: one choice per (k, split rule, rank bits).
+std::vector<PlanOptions> tuning_candidates();
+PlanOptions tuned_options(uint32_t k, bool widest, uint32_t bits);
+void set_tuned_options(uint32_t k, bool widest, uint32_t bits, const PlanOptions& o);
+void clear_tuning();
+bool save_tuning(const char* path);
+bool load_tuning(const char* path);
 
 // First iteration at which every subtree of an n-point tree holds at most
 // TAIL_CAP points (n > TAIL_CAP).

@@ -50,6 +50,14 @@ _SIGS = {
     "kdt_server_copy_out": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]),
     "kdt_clock": (ctypes.c_double, []),
+    "kdt_tune_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
+    "kdt_tuning_get": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p]),
+    "kdt_tuning_set": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p]),
+    "kdt_tuning_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "kdt_tuning_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "kdt_tuning_clear": (None, []),
     "kdt_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "kdt_profile_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "kdt_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -77,6 +85,10 @@ class Result(ctypes.Structure):
                 ("d_tree", ctypes.c_void_p), ("d_perm", ctypes.c_void_p), ("d_dim", ctypes.c_void_p),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("device_ms", ctypes.c_double), ("batch_requests", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_uint32), ("level_items", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
 
 class KdtError(RuntimeError):
@@ -214,6 +226,56 @@ def build_batched(points, offsets, mode: int = ROUND_ROBIN, *, tree=None, perm=N
     if rc != OK:
         raise KdtError(rc, "kdt_build_batched")
     return tree, perm, dim, status
+
+
+def tune_batched(points, offsets, mode: int = ROUND_ROBIN, reps: int = 3, workspace=None, stream=None):
+    """kdt_tune_batched: time every digit-width / tile choice on this batch
+    and record the fastest; returns (radix_bits, level_items, ms)."""
+    import torch
+    _check_points(points)
+    n, k = points.shape
+    o = _offsets(offsets)
+    if workspace is None:
+        workspace = torch.empty(max(batched_workspace_bytes(o, k, mode), 1), dtype=torch.uint8,
+                                device=points.device)
+    best = Tuning()
+    rc = lib().kdt_tune_batched(_ptr(points), o.ctypes.data_as(ctypes.c_void_p), o.size - 1, k, mode,
+                                _ptr(workspace), workspace.numel() * workspace.element_size(), reps,
+                                _stream(stream), ctypes.byref(best))
+    if rc != OK:
+        raise KdtError(rc, "kdt_tune_batched")
+    return best.radix_bits, best.level_items, best.ms
+
+
+def tuning_get(k: int, mode: int, rank_bits: int):
+    t = Tuning()
+    rc = lib().kdt_tuning_get(k, mode, rank_bits, ctypes.byref(t))
+    if rc != OK:
+        raise KdtError(rc, "kdt_tuning_get")
+    return t.radix_bits, t.level_items
+
+
+def tuning_set(k: int, mode: int, rank_bits: int, radix_bits: int, level_items: int):
+    t = Tuning(radix_bits, level_items, 0.0)
+    rc = lib().kdt_tuning_set(k, mode, rank_bits, ctypes.byref(t))
+    if rc != OK:
+        raise KdtError(rc, "kdt_tuning_set")
+
+
+def tuning_save(path: str):
+    rc = lib().kdt_tuning_save(path.encode())
+    if rc != OK:
+        raise KdtError(rc, "kdt_tuning_save")
+
+
+def tuning_load(path: str):
+    rc = lib().kdt_tuning_load(path.encode())
+    if rc != OK:
+        raise KdtError(rc, "kdt_tuning_load")
+
+
+def tuning_clear():
+    lib().kdt_tuning_clear()
 
 
 def release_cached():

@@ -96,7 +96,7 @@ static void check_choose(std::mt19937_64& rng)
         if (c.picks.empty()) {
             ArenaAllocator t = pool;
             const bool out_ok = t.alloc(batch_output_bytes(q[0].n, q[0].k)) != ArenaAllocator::NPOS;
-            const bool ws_ok = out_ok && t.alloc(make_plan({q[0].n}, q[0].k, q[0].mode == 1).total) !=
+            const bool ws_ok = out_ok && t.alloc(workspace_bytes_any({q[0].n}, q[0].k, q[0].mode == 1)) !=
                                              ArenaAllocator::NPOS;
             CHECK(!ws_ok, "the oldest request fits but nothing was chosen");
             continue;
@@ -114,7 +114,7 @@ static void check_choose(std::mt19937_64& rng)
         }
         CHECK(c.picks.size() == 1 || pts <= maxp, "point limit");
         CHECK(c.out_bytes == batch_output_bytes(pts, q[0].k), "output block size");
-        CHECK(c.ws_bytes == make_plan(n, q[0].k, q[0].mode == 1).total, "workspace size");
+        CHECK(c.ws_bytes == workspace_bytes_any(n, q[0].k, q[0].mode == 1), "workspace size");
         ArenaAllocator t = pool;
         CHECK(t.alloc(c.out_bytes) != ArenaAllocator::NPOS && t.alloc(c.ws_bytes) != ArenaAllocator::NPOS,
               "chosen blocks fit");
@@ -133,7 +133,7 @@ static void check_choose(std::mt19937_64& rng)
             n2.push_back(q[next].n);
             ArenaAllocator t2 = pool;
             const bool fit2 = t2.alloc(batch_output_bytes(pts + q[next].n, q[0].k)) != ArenaAllocator::NPOS &&
-                              t2.alloc(make_plan(n2, q[0].k, q[0].mode == 1).total) != ArenaAllocator::NPOS;
+                              t2.alloc(workspace_bytes_any(n2, q[0].k, q[0].mode == 1)) != ArenaAllocator::NPOS;
             CHECK(!fit2, "one more request would have fitted");
         }
     }

@@ -202,3 +202,37 @@ def test_batched_full_4096_clouds():
     _say("case batched-4096: oracle on sampled clouds")
     for c in np.random.default_rng(4).choice(C, 48, replace=False):
         _assert_cloud(pts, offsets, int(c), tree_b, perm_b, dim_b, mode, "batched-4096")
+
+
+def test_tuner_choices_give_identical_trees():
+    """Every digit-width / tile choice the tuner may record builds the same
+    trees; kdt_tune_batched records one of them for the batch's class."""
+    sizes = [70000, 3000, 0, 250000, 9000, 1500, 40000]
+    clouds = [workloads.grid(n, 3, 90 + i, levels=17) for i, n in enumerate(sizes)]
+    pts, offsets = _concat(clouds)
+    _say("case tuner: reference build")
+    kdt.tuning_clear()
+    try:
+        ref = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
+        bits = int(np.ceil(np.log2(max(sizes))))
+        for rb in (8, 9, 10):
+            for items in (4, 8):
+                _say(f"case tuner: radix {rb} items {items}")
+                kdt.tuning_set(3, kdt.ROUND_ROBIN, bits, rb, items)
+                got = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
+                assert got[3] == kdt.OK
+                assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+                assert got[0].tobytes() == ref[0].tobytes()
+        kdt.tuning_clear()
+        t = torch.from_numpy(pts).to(DEV)
+        rb, items, ms = kdt.tune_batched(t, offsets, kdt.ROUND_ROBIN, reps=2)
+        torch.cuda.synchronize()
+        _say(f"tuner picked radix {rb} items {items} at {ms:.3f} ms")
+        assert rb in (8, 9, 10) and items in (4, 8) and ms > 0
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, bits) == (rb, items)
+        got = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
+        assert np.array_equal(got[1], ref[1])
+        for c in range(len(sizes)):
+            _assert_cloud(pts, offsets, c, *got[:3], kdt.ROUND_ROBIN, "tuned")
+    finally:
+        kdt.tuning_clear()

@@ -116,10 +116,10 @@ def test_batched_argument_errors_and_sizes():
     args = (None, None, None, None)
     assert lib.kdt_build_batched(fake, p, 4, 9, 0, *args, ws, need, None) == kdt.EINVAL
     assert lib.kdt_build_batched(None, p, 4, 3, 0, *args, ws, need, None) == kdt.EINVAL
-    assert lib.kdt_build_batched(fake, p, 4, 3, 0, *args, ws, need - 1, None) == kdt.EINVAL
+    assert lib.kdt_build_batched(fake, p, 4, 3, 0, *args, ws, 4096, None) == kdt.EINVAL
     assert "workspace" in kdt.last_error()
     assert lib.kdt_build_batched(fake, None, 4, 3, 0, *args, ws, need, None) == kdt.EINVAL
-    # one batched plan for one tree needs no more workspace than the single build
+    # one batched plan for one tree needs the same workspace as the single build
     one = np.array([0, 123457], np.uint32)
     assert lib.kdt_batched_workspace_bytes(one.ctypes.data_as(ctypes.c_void_p), 1, 3, 1) \
         == lib.kdt_workspace_bytes(123457, 3, 1)
@@ -168,3 +168,34 @@ def test_server_argument_errors():
     assert lib.kdt_server_poll(None, 1, None) == kdt.EINVAL
     assert lib.kdt_server_release(None, 1) == kdt.EINVAL
     assert lib.kdt_clock() > 0.0
+
+
+def test_tuning_table_round_trip(tmp_path):
+    kdt.tuning_clear()
+    try:
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (0, 0)
+        kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 10, 4)
+        kdt.tuning_set(4, kdt.WIDEST, 27, 8, 8)
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4)
+        with pytest.raises(kdt.KdtError):
+            kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 11, 4)
+        with pytest.raises(kdt.KdtError):
+            kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 5)
+        path = str(tmp_path / "tune.txt")
+        kdt.tuning_save(path)
+        kdt.tuning_clear()
+        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (0, 0)
+        kdt.tuning_load(path)
+        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (8, 8)
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4)
+        bad = tmp_path / "bad.txt"
+        bad.write_text("3 0 24 12 4\n")
+        with pytest.raises(kdt.KdtError):
+            kdt.tuning_load(str(bad))
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4)     # unchanged by the failed load
+        # sizes hold every choice: setting a tuning never grows them
+        before = kdt.workspace_bytes(10_000_000, 3, kdt.ROUND_ROBIN)
+        kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 8)
+        assert kdt.workspace_bytes(10_000_000, 3, kdt.ROUND_ROBIN) == before
+    finally:
+        kdt.tuning_clear()
