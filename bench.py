@@ -182,6 +182,10 @@ def run_batched(args, data, mode, cfg):
         kdt.build_batched(d_pts, offsets, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws,
                           stream=stream)
 
+    if args.autotune:
+        rb, items, tms = kdt.tune_batched(d_pts, offsets, mode, reps=2, workspace=ws, stream=stream)
+        cfg["tuned"] = {"radix_bits": rb, "level_items": items}
+        print(f"# autotune: radix {rb} items {items} ({tms:.3f} ms)", file=sys.stderr, flush=True)
     # per-kernel breakdown from profiled eager builds on the side stream
     with torch.cuda.stream(stream):
         for _ in range(max(args.warmup, 1)):
@@ -452,6 +456,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--autotune", action="store_true",
+                    help="before warm-up, let kdt_tune_batched pick the digit width and tile size for this input")
     ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
     ap.add_argument("--inflight", type=int, default=4, help="serving: batches on the device at once")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -516,29 +522,40 @@ def main():
     def step():
         kdt.build_ws(d_pts, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws, stream=stream)
 
+    if args.autotune:
+        import numpy as np
+        rb, items, tms = kdt.tune_batched(d_pts, np.array([0, n], np.uint32), mode, reps=3, workspace=ws)
+        cfg["tuned"] = {"radix_bits": rb, "level_items": items}
+        print(f"# autotune: radix {rb} items {items} ({tms:.3f} ms)", file=sys.stderr, flush=True)
+
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     print(f"# warmup done: n={n} k={k} mode={mode}", file=sys.stderr, flush=True)
 
-    if not args.no_profile:
-        kdt.profile_enable(True)
-        kdt.profile_collect()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = {}
-    if not args.no_profile:
-        prof = kdt.profile_collect()
-        kdt.profile_enable(False)
     st = int(status.item())
     print(f"# timed {args.steps} steps in {elapsed:.3f} s, status {st}", file=sys.stderr, flush=True)
-
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed / 1e6
+
+    # the same K steps again with a pair of HIP events around every kernel
+    # on the build's stream (per-kernel durations for the roofline); the
+    # events add a few microseconds between kernels, so `value` comes from
+    # the pass above
+    prof = {}
+    if not args.no_profile:
+        kdt.profile_enable(True)
+        kdt.profile_collect()
+        for _ in range(args.steps):
+            step()
+        prof = kdt.profile_collect()
+        kdt.profile_enable(False)
 
     roofline, kernels = kernel_table(prof, args.steps)
     if roofline:

@@ -31,9 +31,12 @@ constexpr uint32_t SWEEP_STAGE = 2048;
 
 // Predecessor windows of the look-back: a short first window (the common
 // case is a nearby inclusive prefix), then wider ones.
-constexpr int LB_FIRST = 4;
+#ifndef KDT_LB_FIRST
+#define KDT_LB_FIRST 4
+#endif
+constexpr int LB_FIRST = KDT_LB_FIRST;
 #ifndef KDT_LB_WINDOW
-#define KDT_LB_WINDOW 16
+#define KDT_LB_WINDOW 4
 #endif
 constexpr int LB_WINDOW = KDT_LB_WINDOW;
 
@@ -43,7 +46,7 @@ struct SweepSmem {
     uint16_t wh[SWEEP_WAVES * NB];   // per-wave digit counters, then per-wave exclusive offsets
     uint32_t dstart[NB];             // tile-local start of each digit run
     uint32_t gbase[NB];              // global position of the run minus dstart
-    uint32_t sh[SWEEP_WAVES];
+    uint32_t sh[2 * SWEEP_WAVES];
     uint32_t tile;
     uint32_t stage[RW][SWEEP_STAGE]; // one round of records in sorted tile order
 };
@@ -62,6 +65,30 @@ __device__ __forceinline__ uint32_t sweep_excl_scan(uint32_t v, uint32_t* sh)
         if (i < w) base += sh[i];
     __syncthreads();
     return base + inc - v;
+}
+
+// Exclusive scans of two values per thread at once (same two barriers).
+__device__ __forceinline__ void sweep_excl_scan2(uint32_t a, uint32_t b, uint32_t* sh, uint32_t& ea, uint32_t& eb)
+{
+    const int lane = (int)lane_id();
+    const int w = (int)(threadIdx.x >> 6);
+    const uint32_t ia = wave_incl_scan(a);
+    const uint32_t ib = wave_incl_scan(b);
+    if (lane == 63) {
+        sh[w] = ia;
+        sh[SWEEP_WAVES + w] = ib;
+    }
+    __syncthreads();
+    uint32_t ba = 0, bb = 0;
+#pragma unroll
+    for (int i = 0; i < SWEEP_WAVES; ++i)
+        if (i < w) {
+            ba += sh[i];
+            bb += sh[SWEEP_WAVES + i];
+        }
+    __syncthreads();
+    ea = ba + ia - a;
+    eb = bb + ib - b;
 }
 
 // Stable wave multisplit over RB-bit digits of the first `active` items.
@@ -177,8 +204,8 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW>& sm, const uint4 (&
 #pragma unroll
         for (uint32_t b = 0; b < BPT; ++b) lb_store(&lb[(size_t)g * NB + t0 + b], (first ? LB_INC : LB_AGG) | c[b]);
     }
-    uint32_t cex = sweep_excl_scan(csum, sm.sh);
-    uint32_t hex = sweep_excl_scan(hsum, sm.sh);
+    uint32_t cex, hex;
+    sweep_excl_scan2(csum, hsum, sm.sh, cex, hex);
     if (has) {
 #pragma unroll
         for (uint32_t b = 0; b < BPT; ++b) {

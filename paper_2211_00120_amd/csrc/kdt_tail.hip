@@ -69,23 +69,56 @@ __device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, c
     }
 }
 
-// Digit offsets of one LDS sort pass: wh[w*RADIX + digit] holds wave w's
-// count of each digit; it becomes wave w's exclusive offset inside the
-// digit's run, and dstart[digit] the run's start.  Contains barriers.
+constexpr uint32_t TAIL_SORT_BINS = 512;       // LDS sort digits of up to 9 bits
+
+// Digit offsets of one LDS sort pass over NB digit values: wh[w*NB + digit]
+// holds wave w's count of each digit; it becomes wave w's exclusive offset
+// inside the digit's run, and dstart[digit] the run's start.  Contains
+// barriers.
+template <uint32_t NB>
 __device__ __forceinline__ void tail_digit_offsets(uint16_t* wh, uint32_t* dstart, uint32_t* sh)
 {
     const uint32_t t = threadIdx.x;
     uint32_t run = 0;
-    if (t < RADIX) {
+    if (t < NB) {
 #pragma unroll
         for (int ww = 0; ww < TAIL_THREADS / 64; ++ww) {
-            const uint32_t x = wh[ww * RADIX + t];
-            wh[ww * RADIX + t] = (uint16_t)run;
+            const uint32_t x = wh[ww * NB + t];
+            wh[ww * NB + t] = (uint16_t)run;
             run += x;
         }
     }
     const uint32_t ex = sweep_excl_scan(run, sh);
-    if (t < RADIX) dstart[t] = ex;
+    if (t < NB) dstart[t] = ex;
+}
+
+// One stable LSD pass of the group's LDS sort: it[] (key above bit 12, slot
+// below) ordered by the digit (it >> sft) & mask, mask < TAIL_SORT_BINS.
+template <int ITEMS>
+__device__ __forceinline__ void tail_sort_pass(uint64_t (&it)[ITEMS], const bool (&ok)[ITEMS], uint32_t sft,
+                                               uint32_t mask, uint64_t* x, uint16_t* wh, uint32_t* dstart,
+                                               uint32_t* sh)
+{
+    constexpr uint32_t NB = TAIL_SORT_BINS;
+    constexpr uint32_t CW = 64u * ITEMS;
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    uint32_t dig[ITEMS], rnk[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(it[i] >> sft) & mask;
+    wave_multisplit16<9, ITEMS>(dig, ok, rnk, wh + w * NB, ITEMS);
+    __syncthreads();
+    tail_digit_offsets<NB>(wh, dstart, sh);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (ok[i]) x[dstart[dig[i]] + wh[w * NB + dig[i]] + rnk[i]] = it[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+        if (ok[i]) it[i] = x[p];
+    }
+    __syncthreads();
 }
 
 template <int K, bool WIDEST>
@@ -102,11 +135,13 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     __shared__ uint16_t seg[C];
     __shared__ uint16_t tmp[C];
     __shared__ union {
-        uint64_t x[C];                             // sort exchange
+        struct {
+            uint64_t x[C];                         // sort exchange
+            uint16_t wh[NW * TAIL_SORT_BINS];      // per-wave digit counters
+            uint32_t dstart[TAIL_SORT_BINS];
+        } sort;
         uint16_t cnt[NW][C];                       // per-(wave, segment) counters of an iteration
     } ub;
-    __shared__ uint16_t wh[NW * RADIX];
-    __shared__ uint32_t dstart[RADIX];
     __shared__ uint32_t sh[NW];
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
     __shared__ uint8_t ndim[NODES];
@@ -227,7 +262,9 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     }
     __syncthreads();
 
-    // ---- ord_d: the group sorted by rank_d (stable LSD over 8-bit digits) ----
+    // ---- ord_d: the group sorted by rank_d (stable LSD radix in LDS) ----
+    // fewest passes over the B key bits with digits of at most 9 bits
+    const uint32_t nsb = ((B + 7u) / 8u == (B + 8u) / 9u) ? 8u : 9u;
     for (uint32_t d = 0; d < (uint32_t)K; ++d) {
         if (d == free_dim) {
             for (uint32_t p = threadIdx.x; p < m; p += TAIL_THREADS) ord[d][p] = (uint16_t)p;
@@ -239,25 +276,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
             it[i] = ((uint64_t)pick4(rec[i], d) << 12) | e;
         }
-        for (uint32_t sft = 12; sft < 12 + B; sft += DIGIT_BITS) {
-            uint32_t dig[ITEMS], rnk[ITEMS];
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(it[i] >> sft) & 0xFFu;
-            wave_multisplit16<8, ITEMS>(dig, ok, rnk, wh + w * RADIX, ITEMS);
-            __syncthreads();
-            tail_digit_offsets(wh, dstart, sh);
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i)
-                if (ok[i]) ub.x[dstart[dig[i]] + wh[w * RADIX + dig[i]] + rnk[i]] = it[i];
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                if (ok[i]) it[i] = ub.x[p];
-            }
-            __syncthreads();
-        }
+        for (uint32_t sft = 12; sft < 12 + B; sft += nsb)
+            tail_sort_pass<ITEMS>(it, ok, sft, (1u << nsb) - 1u, ub.sort.x, ub.sort.wh, ub.sort.dstart, sh);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
@@ -281,24 +301,44 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
         __syncthreads();
         // position of each point inside its segment in the order of the
         // segment's split dimension
+        // (the loads and the lane matching of a wave's items are independent;
+        // only the counter updates run item by item, in list order)
         for (uint32_t d = 0; d < (uint32_t)K; ++d) {
             if (!WIDEST && d != l % (uint32_t)K) continue;
+            uint32_t e[ITEMS], q[ITEMS];
+            bool valid[ITEMS];
+            uint64_t peers[ITEMS];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                uint32_t e = 0, q = DONE;
-                if (p < m) {
-                    e = ord[d][p];
-                    q = seg[e];
+                e[i] = p < m ? (uint32_t)ord[d][p] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+                q[i] = p < m ? (uint32_t)seg[e[i]] : DONE;
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                valid[i] = q[i] != DONE;
+                if (WIDEST && valid[i]) valid[i] = segdim[cur][q[i]] == d;
+                peers[i] = __ballot(valid[i]);
+            }
+            for (uint32_t b = 0; b < gbits; ++b) {
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const bool bit = (q[i] >> b) & 1u;
+                    const uint64_t bal = __ballot(bit);
+                    peers[i] &= bit ? bal : ~bal;
                 }
-                bool valid = q != DONE;
-                if (WIDEST && valid) valid = segdim[cur][q] == d;
-                const uint64_t peers = match_bits(q, gbits, valid);
-                const uint32_t below = count_below(peers);
+            }
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t below = count_below(peers[i]);
                 uint32_t base = 0;
-                if (valid) base = ub.cnt[w][q];
-                if (valid && below == 0) ub.cnt[w][q] = (uint16_t)(base + (uint32_t)__popcll(peers));
-                if (valid) tmp[e] = (uint16_t)((w << 12) | (base + below));
+                if (valid[i]) base = ub.cnt[w][q[i]];
+                if (valid[i] && below == 0) ub.cnt[w][q[i]] = (uint16_t)(base + (uint32_t)__popcll(peers[i]));
+                if (valid[i]) tmp[e[i]] = (uint16_t)((w << 12) | (base + below));
             }
         }
         __syncthreads();
