@@ -40,6 +40,19 @@ constexpr int LB_FIRST = KDT_LB_FIRST;
 #endif
 constexpr int LB_WINDOW = KDT_LB_WINDOW;
 
+// Element type of the write-out stage for records of RW words: one LDS
+// access per record (uint4 also for 3 words).
+template <int RW> struct StageOf { using T = uint4; };
+template <> struct StageOf<2> { using T = uint2; };
+template <> struct StageOf<1> { using T = uint32_t; };
+
+__device__ __forceinline__ void stage_put(uint4& s, const uint4& r) { s = r; }
+__device__ __forceinline__ void stage_put(uint2& s, const uint4& r) { s = make_uint2(r.x, r.y); }
+__device__ __forceinline__ void stage_put(uint32_t& s, const uint4& r) { s = r.x; }
+__device__ __forceinline__ uint4 stage_get(const uint4& s) { return s; }
+__device__ __forceinline__ uint4 stage_get(const uint2& s) { return make_uint4(s.x, s.y, 0u, 0u); }
+__device__ __forceinline__ uint4 stage_get(const uint32_t& s) { return make_uint4(s, 0u, 0u, 0u); }
+
 template <int RB, int RW>
 struct SweepSmem {
     static constexpr uint32_t NB = 1u << RB;
@@ -48,7 +61,7 @@ struct SweepSmem {
     uint32_t gbase[NB];              // global position of the run minus dstart
     uint32_t sh[2 * SWEEP_WAVES];
     uint32_t tile;
-    uint32_t stage[RW][SWEEP_STAGE]; // one round of records in sorted tile order
+    typename StageOf<RW>::T stage[SWEEP_STAGE];   // one round of records in sorted tile order
 };
 
 // Exclusive scan of one value per thread over SWEEP_THREADS threads.
@@ -231,20 +244,12 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW>& sm, const uint4 (&
         for (int i = 0; i < ITEMS; ++i) {
             if (i >= active) break;
             const uint32_t o = dst[i] - base;
-            if (o < SWEEP_STAGE) {
-                sm.stage[0][o] = rec[i].x;
-                if constexpr (RW > 1) sm.stage[1][o] = rec[i].y;
-                if constexpr (RW > 2) sm.stage[2][o] = rec[i].z;
-                if constexpr (RW > 3) sm.stage[3][o] = rec[i].w;
-            }
+            if (o < SWEEP_STAGE) stage_put(sm.stage[o], rec[i]);
         }
         __syncthreads();
         const uint32_t m = min(SWEEP_STAGE, cnt - base);
         for (uint32_t j = threadIdx.x; j < m; j += SWEEP_THREADS) {
-            uint4 r = make_uint4(sm.stage[0][j], 0u, 0u, 0u);
-            if constexpr (RW > 1) r.y = sm.stage[1][j];
-            if constexpr (RW > 2) r.z = sm.stage[2][j];
-            if constexpr (RW > 3) r.w = sm.stage[3][j];
+            const uint4 r = stage_get(sm.stage[j]);
             const uint32_t d = digit_of(r);
             store(base + j, sm.gbase[d] + base + j, r);
         }
