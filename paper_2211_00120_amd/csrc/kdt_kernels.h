@@ -95,7 +95,7 @@ struct LevelPassArgs {
     uint32_t* rout;         // next pass's input, or (last pass) next iteration's records
     uint32_t* hist;         // histogram region; share.hist / share.hist_next are word offsets in it
     uint32_t passes, pass, shift, radix_bits;
-    uint32_t items;         // records per thread in this launch's tiles (tile = 512 * items)
+    uint32_t items;         // records per thread in this launch's tiles (tile = SWEEP_THREADS * items)
     uint32_t* lb;
     uint32_t* lb_zero;
     uint32_t lb_zero_n;

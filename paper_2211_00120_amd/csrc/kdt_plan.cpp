@@ -15,11 +15,11 @@ namespace kdt {
 
 namespace {
 
-// Records per thread of an iteration's sort tiles (tile = 512 * items): the
+// Records per thread of an iteration's sort tiles (tile = SWEEP_THREADS * items): the
 // largest tile that the iteration's biggest subtree still fills.
 uint32_t level_items(uint32_t big, uint32_t cap)
 {
-    const uint32_t items = big >= 4096u ? 8u : 4u;
+    const uint32_t items = big >= (uint32_t)SWEEP_THREADS * 8u ? 8u : 4u;
     return items < cap ? items : cap;
 }
 
@@ -223,7 +223,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
             const Level v = make_level(n[t], l);
             TreeStep s = step(t, l, ll.tiles);
             s.hist = ll.hist_words;
-            ll.tiles += tiles_level(v, 512u * ll.items).tiles;
+            ll.tiles += tiles_level(v, (uint32_t)SWEEP_THREADS * ll.items).tiles;
             ll.hist_words += v.nseg * p.P * NB;
             ll.steps.push_back(s);
             TreeStep h = step(t, l, ll.hist_tiles);

@@ -15,12 +15,18 @@ constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digit passes over a rank of at mos
 constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
 constexpr uint32_t PREP_TILE = 4096;       // points per workgroup of prep / iteration 0
 
-// Tile shapes (items per thread of a 512-thread workgroup); tuning knobs.
+// Threads of the onesweep workgroups (presort and level passes).
+#ifndef KDT_SWEEP_THREADS
+#define KDT_SWEEP_THREADS 512
+#endif
+constexpr int SWEEP_THREADS = KDT_SWEEP_THREADS;
+
+// Tile shapes (items per thread of a SWEEP_THREADS workgroup); tuning knobs.
 #ifndef KDT_PRESORT_ITEMS
 #define KDT_PRESORT_ITEMS 8
 #endif
 constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
-constexpr uint32_t PRESORT_TILE = 512u * PRESORT_ITEMS;
+constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
 constexpr uint32_t HIST_TILE = 16384;      // chunk of the split-widest histogram kernel
 constexpr int TAIL_THREADS = 512;          // subtree tail: 512 threads x 4 slots = up to 2048 points
 constexpr int TAIL_ITEMS = 4;

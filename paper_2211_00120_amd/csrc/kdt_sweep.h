@@ -22,10 +22,10 @@
 #include <stdint.h>
 
 #include "kdt_device.h"
+#include "kdt_shares.h"
 
 namespace kdt {
 
-constexpr int SWEEP_THREADS = 512;
 constexpr int SWEEP_WAVES = SWEEP_THREADS / 64;
 constexpr uint32_t SWEEP_STAGE = 2048;
 
@@ -64,7 +64,9 @@ struct SweepSmem {
     typename StageOf<RW>::T stage[SWEEP_STAGE];   // one round of records in sorted tile order
 };
 
-// Exclusive scan of one value per thread over SWEEP_THREADS threads.
+// Exclusive scan of one value per thread over a workgroup of NWV waves
+// (sh: NWV words of LDS).
+template <int NWV = SWEEP_WAVES>
 __device__ __forceinline__ uint32_t sweep_excl_scan(uint32_t v, uint32_t* sh)
 {
     const int lane = (int)lane_id();
@@ -74,7 +76,7 @@ __device__ __forceinline__ uint32_t sweep_excl_scan(uint32_t v, uint32_t* sh)
     __syncthreads();
     uint32_t base = 0;
 #pragma unroll
-    for (int i = 0; i < SWEEP_WAVES; ++i)
+    for (int i = 0; i < NWV; ++i)
         if (i < w) base += sh[i];
     __syncthreads();
     return base + inc - v;

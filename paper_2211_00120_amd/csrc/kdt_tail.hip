@@ -88,7 +88,7 @@ __device__ __forceinline__ void tail_digit_offsets(uint16_t* wh, uint32_t* dstar
             run += x;
         }
     }
-    const uint32_t ex = sweep_excl_scan(run, sh);
+    const uint32_t ex = sweep_excl_scan<TAIL_THREADS / 64>(run, sh);
     if (t < NB) dstart[t] = ex;
 }
 

@@ -143,7 +143,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
             const Level v = make_level(n[t], l);
             CHECK(s.tree == t && s.level == l && s.tile0 == tiles, "level %u share of tree %u", l, t);
             CHECK(h.tree == t && h.tile0 == htiles && h.hist == s.hist, "hist share of tree %u", t);
-            tiles += tiles_level(v, 512u * ll.items).tiles;
+            tiles += tiles_level(v, (uint32_t)SWEEP_THREADS * ll.items).tiles;
             htiles += tiles_level(v, HIST_TILE).tiles;
             const uint64_t lo = (l & 1u) * (uint64_t)p.hist_words, hi = lo + p.hist_words;
             const uint64_t words = (uint64_t)v.nseg * p.P * NB;
