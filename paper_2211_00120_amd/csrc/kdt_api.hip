@@ -7,9 +7,11 @@
 //     (k_tail from the points: keys, per-dimension orders and every
 //     iteration in LDS);
 //   * larger trees go through init, prep, [root dims], k presorts x 4
-//     passes, iteration 0, then iterations 1.. as segmented onesweep passes
-//     while some subtree is larger than TAIL_CAP, then one tail launch that
-//     runs each tree's remaining iterations, each tree from its own level.
+//     passes, iteration 0, then iterations 1.. while some subtree is larger
+//     than TAIL_CAP (each: radix select of every subtree's pivot key, then
+//     one segmented onesweep split pass that applies the tag update), then
+//     one tail launch that runs each tree's remaining iterations, each tree
+//     from its own level.
 //
 // Every launch covers all trees that have work at that step, so the launch
 // count of a batch is that of its largest tree.  With a single share the
@@ -80,10 +82,10 @@ kdt_status check_launch(const char* what)
 // While enabled, every kernel enqueued by a build is bracketed by two
 // hipEvents on the build's stream and tagged with its kind and algorithmic
 // bytes (the bytes the step must move by definition).
-enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_HIST, KIND_PASS, KIND_TAIL,
+enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PART, KIND_TAIL,
             KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
-                                            "k_level0", "k_level_hist", "k_level_pass", "k_tail",
+                                            "k_level0", "k_level_select", "k_level_part", "k_tail",
                                             "k_tail_whole", "share_tables", "k_word"};
 
 struct ProfRec {
@@ -242,11 +244,16 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     // first one, pass q clears the one of pass q+1
     const std::vector<uint32_t>& pw = p.pass_words;
     auto next_words = [&](uint32_t q) { return q + 1 < pw.size() ? pw[q + 1] : 0u; };
-    const uint32_t hist1_words = p.levels.empty() ? 0u : p.levels[0].hist_words;
+    // histogram thirds 1 and 2 (iterations 1 and 2) start cleared; the split
+    // of iteration l clears the third of iteration l+2
+    const uint32_t hist12_words = p.levels.empty() ? 0u : p.hist_words * 2u;
+    // split keys of iteration l live in skey[(l-1) & 1]: the presort keys
+    // (free after the presorts) and the rank table (free after iteration 0)
+    uint32_t* skey[2] = {keys, ranks};
 
     if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, [&] {
             launch_init(dstatus, counters, hist_rank, nlarge_trees * k * 4 * RADIX_HOST, lb[0],
-                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist1_words, o.bbox,
+                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, o.bbox,
                         widest ? nlarge_trees : 0u, st);
         }))
         return s;
@@ -317,68 +324,73 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         // iteration 0 writes the records of iteration 1 into rec[0]
         int cur = 0;
         {
+            const bool keys1 = !p.levels.empty() && !p.levels[0].sorted;
             Level0Args a{};
             a.sh = shares(p, p.level0, p.t_level0, ws);
             a.perms = perms;
             a.rank_table = ranks;
             a.rout = rec[cur];
-            a.hist = (!widest && !p.levels.empty()) ? hist : nullptr;
+            a.kout = skey[0];
+            a.hist = hist;
+            a.keys_next = keys1 ? 1u : 0u;
             a.ntotal = ntotal;
             a.passes = p.P;
             a.radix_bits = p.RB;
             a.o = o;
-            if (kdt_status s = run_kernel(st, KIND_LEVEL0, nlarge * (4.0 + 8.0 * K),
+            if (kdt_status s = run_kernel(st, KIND_LEVEL0, nlarge * (4.0 + 8.0 * K + (keys1 ? 4.0 : 0.0)),
                                           [&] { launch_level0((int)k, a, p.prep_tiles, widest, st); }))
                 return s;
         }
 
-        // iterations 1 .. as segmented digit passes
+        // iterations 1 .. : pivot selects, then the split
         for (size_t li = 0; li < p.levels.size(); ++li) {
             const LevelLaunch& ll = p.levels[li];
             const uint32_t l = ll.level;
             double live = 0;
             for (const TreeStep& s : ll.steps) live += p.trees[s.tree].n - full_nodes(l);
-            if (widest) {
-                LevelHistArgs ha{};
-                ha.sh = shares(p, ll.hsteps, p.t_hist[li], ws);
-                ha.rin = rec[cur];
-                ha.hist = hist;
-                ha.passes = p.P;
-                ha.radix_bits = p.RB;
-                ha.o = o;
-                if (kdt_status s = run_kernel(st, KIND_HIST, live * 4.0 * K,
-                                              [&] { launch_level_hist((int)k, ha, ll.hist_tiles, st); }))
-                    return s;
+            if (!ll.sorted) {
+                for (int j = (int)p.P - 2; j >= 0; --j) {
+                    LevelSelectArgs sa{};
+                    sa.sh = shares(p, ll.ssteps, p.t_select[li], ws);
+                    sa.kin = skey[(l - 1u) & 1u];
+                    sa.hist = hist;
+                    sa.passes = p.P;
+                    sa.digit = (uint32_t)j;
+                    sa.radix_bits = p.RB;
+                    sa.status = dstatus;
+                    if (kdt_status s = run_kernel(st, KIND_SELECT, live * 4.0,
+                                                  [&] { launch_level_select(sa, ll.select_tiles, st); }))
+                        return s;
+                }
             }
-            const uint32_t next_hist_words = li + 1 < p.levels.size() ? p.levels[li + 1].hist_words : 0u;
-            for (uint32_t ps = 0; ps < p.P; ++ps, ++q) {
-                const bool last = ps + 1 == p.P;
-                LevelPassArgs a{};
-                a.sh = shares(p, ll.steps, p.t_level[li], ws);
-                a.rin = rec[cur];
-                a.rout = rec[cur ^ 1];
-                a.hist = hist;
-                a.passes = p.P;
-                a.pass = ps;
-                a.shift = p.RB * ps;
-                a.radix_bits = p.RB;
-                a.items = ll.items;
-                a.lb = lb[q & 1];
-                a.lb_zero = lb[(q + 1) & 1];
-                a.lb_zero_n = next_words(q);
-                // pass 0 clears the next iteration's histogram half (P >= 2,
-                // so that happens a launch before anything accumulates there)
-                a.zero2 = (ps == 0 && next_hist_words) ? hist + ((l + 1u) & 1u) * p.hist_words : nullptr;
-                a.zero2_n = ps == 0 ? next_hist_words : 0u;
-                a.counter = counters + q;
-                a.k = k;
-                a.acc_next = (last && !widest && next_hist_words) ? 1u : 0u;
-                a.o = o;
-                if (kdt_status s = run_kernel(st, KIND_PASS, live * 8.0 * K,
-                                              [&] { launch_level_pass((int)k, a, ll.tiles, last, widest, st); }))
-                    return s;
-                cur ^= 1;
-            }
+            const bool keys_next = li + 1 < p.levels.size() && !p.levels[li + 1].sorted;
+            const uint32_t zero_words = li + 2 < p.levels.size() ? p.levels[li + 2].hist_words : 0u;
+            LevelPartArgs a{};
+            a.sh = shares(p, ll.steps, p.t_level[li], ws);
+            a.rin = rec[cur];
+            a.rout = rec[cur ^ 1];
+            a.kout = skey[l & 1u];
+            a.hist = hist;
+            a.perms = perms;
+            a.ntotal = ntotal;
+            a.passes = p.P;
+            a.radix_bits = p.RB;
+            a.items = ll.items;
+            a.sorted = ll.sorted ? 1u : 0u;
+            a.keys_next = keys_next ? 1u : 0u;
+            a.lb = lb[q & 1];
+            a.lb_zero = lb[(q + 1) & 1];
+            a.lb_zero_n = next_words(q);
+            a.zero2 = zero_words ? hist + ((l + 2u) % 3u) * p.hist_words : nullptr;
+            a.zero2_n = zero_words;
+            a.counter = counters + q;
+            a.k = k;
+            a.o = o;
+            if (kdt_status s = run_kernel(st, KIND_PART, live * (8.0 * K + (keys_next ? 4.0 : 0.0)),
+                                          [&] { launch_level_part((int)k, a, ll.tiles, widest, st); }))
+                return s;
+            cur ^= 1;
+            ++q;
         }
 
         // every large tree's remaining iterations, each from its own level

@@ -104,37 +104,47 @@ __device__ __forceinline__ float pickf(const float4& p, uint32_t d)
 }
 
 // Split-widest (Sec. 6): the domain of a child of subtree s is s's domain
-// clipped by s's plane (left child: hi = plane, right child: lo = plane); the
-// child's split dimension is its domain's widest extent.  s is the i-th
-// subtree of its level in tree ti, box_cur[box_off + i] its domain; the
-// children's domains go to box_next[box_off + 2i (+1)] (when box_next is
-// set) and their dimensions to dimnode.  plane is the pivot's coordinate in
-// s's split dimension ds.
+// bc (lo[0..3], hi[4..7]) clipped by s's plane (left child c = 0: hi =
+// plane, right child c = 1: lo = plane); the child's split dimension is its
+// domain's widest extent.  plane is the pivot's coordinate in s's split
+// dimension ds.
+template <int K>
+__device__ __forceinline__ void split_box(const float* bc, float plane, uint32_t ds, uint32_t c, float (&l2)[K],
+                                          float (&h2)[K])
+{
+#pragma unroll
+    for (int d = 0; d < K; ++d) {
+        l2[d] = bc[d];
+        h2[d] = bc[4 + d];
+        if ((uint32_t)d == ds) {
+            if (c == 0u) h2[d] = fminf(h2[d], plane);
+            else l2[d] = fmaxf(l2[d], plane);
+        }
+    }
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t child_dim(const float* bc, float plane, uint32_t ds, uint32_t c)
+{
+    float l2[K], h2[K];
+    split_box<K>(bc, plane, ds, c, l2, h2);
+    return widest_dim<K>(l2, h2);
+}
+
+// Writes the children's dimensions of subtree s (the i-th of its level in
+// tree ti, domain box_cur[box_off + i]) to dimnode and, when box_next is
+// set, their domains to box_next[box_off + 2i (+1)].
 template <int K>
 __device__ void widest_children(const Outs& o, const TreeInfo& ti, uint32_t s, uint32_t i, float plane,
                                 uint32_t ds, const float* box_cur, float* box_next)
 {
-    float lo[K], hi[K];
     const float* bc = box_cur + ((size_t)ti.box_off + i) * 8;
-#pragma unroll
-    for (int d = 0; d < K; ++d) {
-        lo[d] = bc[d];
-        hi[d] = bc[4 + d];
-    }
 #pragma unroll
     for (uint32_t c = 0; c < 2u; ++c) {
         const uint32_t child = 2u * s + 1u + c;
         if (child >= ti.n) continue;
         float l2[K], h2[K];
-#pragma unroll
-        for (int d = 0; d < K; ++d) {
-            l2[d] = lo[d];
-            h2[d] = hi[d];
-            if ((uint32_t)d == ds) {
-                if (c == 0u) h2[d] = fminf(hi[d], plane);
-                else l2[d] = fmaxf(lo[d], plane);
-            }
-        }
+        split_box<K>(bc, plane, ds, c, l2, h2);
         o.dimnode[(size_t)ti.off + child] = (uint8_t)widest_dim<K>(l2, h2);
         if (box_next) {
             float* bn = box_next + ((size_t)ti.box_off + 2u * i + c) * 8;

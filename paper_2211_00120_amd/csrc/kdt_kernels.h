@@ -73,37 +73,50 @@ struct Level0Args {
     const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
     const uint32_t* rank_table;
     uint32_t* rout;         // iteration-1 records
-    uint32_t* hist;         // base of the iteration-1 histograms (share.hist_next offsets), nullable
+    uint32_t* kout;         // iteration-1 split keys (share.hist_next != NO_HIST and keys_next)
+    uint32_t* hist;         // base of the iteration-1 histograms (share.hist_next offsets)
+    uint32_t keys_next;     // iteration 1 selects its pivots from keys and histograms
     uint32_t ntotal;
     uint32_t passes;
     uint32_t radix_bits;
     Outs o;
 };
 
-struct LevelHistArgs {
+// Pivot selection of iteration l, one digit: the digit histogram, per
+// subtree, of the split keys whose higher digits equal the pivot's (known
+// from the histograms of the higher digits).
+struct LevelSelectArgs {
     Shares sh;              // shares of one iteration, tiles of HIST_TILE
-    const uint32_t* rin;
-    uint32_t* hist;         // base; share.hist offsets
-    uint32_t passes;
+    const uint32_t* kin;    // split key (rank in the subtree's split dimension) per live position
+    uint32_t* hist;         // histogram region; share.hist word offsets
+    uint32_t passes;        // digits per key (the top one is counted when the keys are written)
+    uint32_t digit;         // digit counted by this launch (0 = lowest)
     uint32_t radix_bits;
-    Outs o;
+    uint32_t* status;
 };
 
-struct LevelPassArgs {
+// The update of iteration l: a stable three-way split of every subtree's
+// segment around its pivot (smaller key, the pivot, larger key), which is
+// the sorted order of Sec. 3.1 restricted to what the tag update reads.
+struct LevelPartArgs {
     Shares sh;              // shares of one iteration, tiles of 512*items
     const uint32_t* rin;
-    uint32_t* rout;         // next pass's input, or (last pass) next iteration's records
+    uint32_t* rout;         // next iteration's records
+    uint32_t* kout;         // next iteration's split keys (keys_next)
     uint32_t* hist;         // histogram region; share.hist / share.hist_next are word offsets in it
-    uint32_t passes, pass, shift, radix_bits;
+    const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
+    uint32_t ntotal;
+    uint32_t passes, radix_bits;
     uint32_t items;         // records per thread in this launch's tiles (tile = SWEEP_THREADS * items)
+    uint32_t sorted;        // every segment is in split-key order (the pivot is at its left size)
+    uint32_t keys_next;     // write the next iteration's split keys and top-digit histograms
     uint32_t* lb;
     uint32_t* lb_zero;
     uint32_t lb_zero_n;
-    uint32_t* zero2;        // buffer to clear (next iteration's histograms)
+    uint32_t* zero2;        // buffer to clear (histograms of the iteration after next)
     uint32_t zero2_n;
     uint32_t* counter;
     uint32_t k;             // dimension count (round robin split dimension = level mod k)
-    uint32_t acc_next;      // last pass: accumulate next-iteration histograms (round robin)
     Outs o;
 };
 
@@ -122,8 +135,8 @@ void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStrea
 void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st);
 void launch_presort_pass(const PresortArgs& a, bool first, bool last, uint32_t tiles, hipStream_t st);
 void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st);
-void launch_level_hist(int k, const LevelHistArgs& a, uint32_t tiles, hipStream_t st);
-void launch_level_pass(int k, const LevelPassArgs& a, uint32_t tiles, bool last, bool widest, hipStream_t st);
+void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t st);
+void launch_level_part(int k, const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_tail(int k, const TailArgs& a, uint32_t groups, bool widest, hipStream_t st);
 
 }  // namespace kdt

@@ -15,10 +15,13 @@
 //  level 0     the presort of the root's dimension already is the iteration-0
 //              sort (all tags are 0), so iteration 0 is only the tag update:
 //              place the root at the pivot ss(1), write the rest compacted.
-//  level l     the live points are grouped by subtree (Obs. 3.2), so the sort
-//              by (tag, coordinate) only has to order each subtree's segment
-//              by the rank of its split dimension (kdt_level.h); its last
-//              digit pass applies the tag update of Sec. 3.2.
+//  level l     the live points are grouped by subtree (Obs. 3.2) and every
+//              subtree's segment is still in the root dimension's order.  The
+//              tag update only asks where each point falls relative to its
+//              subtree's pivot, so the sort by (tag, coordinate) reduces to a
+//              radix select of the pivot's key (k_level_select, digit
+//              histograms per subtree) and one stable three-way split around
+//              it that applies the update (kdt_level.h).
 //  tail        once every subtree fits one workgroup, the remaining
 //              iterations run in LDS (kdt_tail.hip).
 //
@@ -198,28 +201,46 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 // of rank r.  The pivot is ss(1) (Sec. 3.2, Sec. 5); the root is placed, the
 // others keep their order and are written compacted (left subtree then right
 // subtree).  With N <= 3 the children are leaves and are placed directly.
-// Optionally accumulates the digit histograms of iteration 1 (round robin).
+// With keys_next, also writes each survivor's split key of iteration 1 (its
+// rank in its subtree's split dimension) and the top-digit histogram of
+// every iteration-1 subtree.
 template <int K, bool WIDEST>
 __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
 {
-    __shared__ uint32_t nh[2 * MAX_LEVEL_PASSES * MAX_BINS];
+    __shared__ uint32_t nh[2 * MAX_BINS];
+    __shared__ uint32_t cdim[2];
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, blockIdx.x, st, ti);
     const uint32_t P = a.passes;
     const uint32_t RBv = a.radix_bits;
     const uint32_t NB = 1u << RBv;
-    const bool acc = a.hist != nullptr && st.hist_next != 0xFFFFFFFFu;
+    const uint32_t top = RBv * (P - 1u);
+    const bool acc = a.keys_next != 0u && st.hist_next != 0xFFFFFFFFu;
     if (acc)
-        for (uint32_t x = threadIdx.x; x < 2u * P * NB; x += BLOCK) nh[x] = 0u;
-    __syncthreads();
+        for (uint32_t x = threadIdx.x; x < 2u * NB; x += BLOCK) nh[x] = 0u;
     const uint32_t n = ti.n;
     const size_t off = ti.off;
     const uint32_t L = num_levels(n);
     const uint32_t d0 = WIDEST ? (uint32_t)a.o.dimnode[off] : 0u;
     const uint32_t* perm_d0 = a.perms + (size_t)d0 * a.ntotal + off;
     const uint32_t piv = (L >= 2) ? seg_pivot(make_level(n, 0), 0) : 0u;
-    const uint32_t dn = (K == 1) ? 0u : 1u % (uint32_t)K;
+    if (threadIdx.x == 0) {
+        // split dimensions of the root's children
+        uint32_t c0 = (K == 1) ? 0u : 1u % (uint32_t)K, c1 = c0;
+        if (WIDEST && acc) {
+            uint32_t idx = perm_d0[piv];
+            if (!in_bounds(idx, n, a.o.status)) idx = 0;
+            const float plane = a.o.pts[(off + idx) * K + d0];
+            const float* bc = a.o.box[0] + (size_t)ti.box_off * 8;
+            c0 = child_dim<K>(bc, plane, d0, 0u);
+            c1 = child_dim<K>(bc, plane, d0, 1u);
+        }
+        cdim[0] = c0;
+        cdim[1] = c1;
+    }
+    __syncthreads();
+    const uint32_t cd0 = uniform(cdim[0]), cd1 = uniform(cdim[1]);
     const uint32_t start = (blockIdx.x - st.tile0) * PREP_TILE;
     const uint32_t end = min(start + PREP_TILE, n);
     for (uint32_t r = start + threadIdx.x; r < end; r += BLOCK) {
@@ -241,33 +262,39 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
         const uint32_t side = r > piv ? 1u : 0u;
         store_rec4<K>(a.rout, off + r - side, rec);
         if (acc) {
-            const uint32_t u = pick4(rec, dn);
-            for (uint32_t p = 0; p < P; ++p)
-                atomicAdd(&nh[(side * P + p) * NB + ((u >> (RBv * p)) & (NB - 1u))], 1u);
+            const uint32_t kv = pick4(rec, side ? cd1 : cd0);
+            a.kout[off + r - side] = kv;
+            atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
         }
     }
     if (acc) {
         __syncthreads();
-        uint32_t* dst = a.hist + st.hist_next;
-        for (uint32_t x = threadIdx.x; x < 2u * P * NB; x += BLOCK)
-            if (nh[x]) atomicAdd(&dst[x], nh[x]);
+        // iteration-1 subtrees 0 and 1, top digit
+        for (uint32_t x = threadIdx.x; x < 2u * NB; x += BLOCK) {
+            const uint32_t c = x / NB;
+            if (nh[x]) atomicAdd(&a.hist[st.hist_next + ((size_t)c * P + P - 1u) * NB + (x - c * NB)], nh[x]);
+        }
     }
 }
 
-// ------------------------------------------------- split-widest histograms
+// --------------------------------------------------------- pivot selection
 
-// Digit histograms of iteration l for split-widest (the split dimension of a
-// subtree is only known once its parent's pivot is fixed).  Workgroups cover
-// segment-aligned chunks of each tree's live array.
-template <int K>
-__global__ void __launch_bounds__(BLOCK) k_level_hist(LevelHistArgs a)
+// One digit of the radix select of every subtree's pivot key in iteration l
+// (see LevelSelectArgs).  Workgroups take segment-aligned chunks of HIST_TILE
+// keys.  The pivot of the i-th subtree is its key of rank ss(2s+1) (its left
+// size); the digits above `digit` are read off the histograms of the
+// earlier launches, and this launch counts the `digit` values of the keys
+// that agree with them.
+__global__ void __launch_bounds__(SWEEP_THREADS) k_level_select(LevelSelectArgs a)
 {
-    __shared__ uint32_t h[MAX_LEVEL_PASSES * MAX_BINS];
-    const uint32_t P = a.passes;
+    __shared__ uint32_t lh[MAX_BINS];
+    __shared__ uint32_t sh[2 * SWEEP_WAVES];
+    __shared__ uint32_t sel[2];
     const uint32_t RBv = a.radix_bits;
     const uint32_t NB = 1u << RBv;
-    for (uint32_t x = threadIdx.x; x < P * NB; x += BLOCK) h[x] = 0u;
-    __syncthreads();
+    const uint32_t P = a.passes;
+    const uint32_t j = a.digit;
+    for (uint32_t x = threadIdx.x; x < NB; x += SWEEP_THREADS) lh[x] = 0u;
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, blockIdx.x, st, ti);
@@ -279,15 +306,23 @@ __global__ void __launch_bounds__(BLOCK) k_level_hist(LevelHistArgs a)
     const uint32_t sz = tiles_seg_size(tl, seg);
     const uint32_t start = u * HIST_TILE;
     const uint32_t cnt = min(HIST_TILE, sz - start);
-    const uint32_t d = a.o.dimnode[(size_t)ti.off + v.Fl + seg];
-    for (uint32_t j = threadIdx.x; j < cnt; j += BLOCK) {
-        const uint32_t r = a.rin[((size_t)ti.off + soff + start + j) * K + d];
-        for (uint32_t p = 0; p < P; ++p) atomicAdd(&h[p * NB + ((r >> (RBv * p)) & (NB - 1u))], 1u);
+    uint32_t* h = a.hist + st.hist + (size_t)seg * P * NB;
+    uint32_t kk = seg_left_size(v, seg);
+    uint32_t prefix = 0;
+    // digits above j (P >= 2 and j <= P-2: at least one; each search ends
+    // with a barrier, which also orders the clearing of lh)
+    for (uint32_t jj = P - 1u; jj > j; --jj)
+        prefix = (prefix << RBv) | find_bucket(h + (size_t)jj * NB, NB, kk, sh, sel, a.status);
+    const uint32_t hs = RBv * (j + 1u), lo = RBv * j;
+    const uint32_t* kin = a.kin + (size_t)ti.off + soff + start;
+    for (uint32_t x = threadIdx.x; x < cnt; x += SWEEP_THREADS) {
+        const uint32_t key = kin[x];
+        if ((key >> hs) == prefix) atomicAdd(&lh[(key >> lo) & (NB - 1u)], 1u);
     }
     __syncthreads();
-    uint32_t* dst = a.hist + st.hist + (size_t)seg * P * NB;
-    for (uint32_t x = threadIdx.x; x < P * NB; x += BLOCK)
-        if (h[x]) atomicAdd(&dst[x], h[x]);
+    uint32_t* dst = h + (size_t)j * NB;
+    for (uint32_t x = threadIdx.x; x < NB; x += SWEEP_THREADS)
+        if (lh[x]) atomicAdd(&dst[x], lh[x]);
 }
 
 __global__ void k_set_word(uint32_t* dst, uint32_t v)
@@ -370,26 +405,21 @@ void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipS
     }
 }
 
-void launch_level_hist(int k, const LevelHistArgs& a, uint32_t tiles, hipStream_t st)
+void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t st)
 {
-    switch (k) {
-    case 1: k_level_hist<1><<<tiles, BLOCK, 0, st>>>(a); break;
-    case 2: k_level_hist<2><<<tiles, BLOCK, 0, st>>>(a); break;
-    case 3: k_level_hist<3><<<tiles, BLOCK, 0, st>>>(a); break;
-    default: k_level_hist<4><<<tiles, BLOCK, 0, st>>>(a); break;
-    }
+    k_level_select<<<tiles, SWEEP_THREADS, 0, st>>>(a);
 }
 
 template <int K>
-void launch_level_pass_k(const LevelPassArgs& a, uint32_t tiles, bool last, bool widest, hipStream_t st);
+void launch_level_part_k(const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 
-void launch_level_pass(int k, const LevelPassArgs& a, uint32_t tiles, bool last, bool widest, hipStream_t st)
+void launch_level_part(int k, const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st)
 {
     switch (k) {
-    case 1: launch_level_pass_k<1>(a, tiles, last, widest, st); break;
-    case 2: launch_level_pass_k<2>(a, tiles, last, widest, st); break;
-    case 3: launch_level_pass_k<3>(a, tiles, last, widest, st); break;
-    default: launch_level_pass_k<4>(a, tiles, last, widest, st); break;
+    case 1: launch_level_part_k<1>(a, tiles, widest, st); break;
+    case 2: launch_level_part_k<2>(a, tiles, widest, st); break;
+    case 3: launch_level_part_k<3>(a, tiles, widest, st); break;
+    default: launch_level_part_k<4>(a, tiles, widest, st); break;
     }
 }
 

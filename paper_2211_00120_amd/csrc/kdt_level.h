@@ -1,6 +1,18 @@
-// kdt_level.h -- the segmented digit pass of one iteration's sort, with the
-// tag update fused into its last pass.  Instantiated per dimension count in
-// kdt_level_k{1,2,3,4}.hip (compiled in parallel).
+// kdt_level.h -- the update of one iteration run as digit passes: a stable
+// three-way split of every subtree segment around its pivot, with the tag
+// update of Sec. 3.2 fused into its scatter.  Instantiated per dimension
+// count in kdt_level_k{1,2,3,4}.hip (compiled in parallel).
+//
+// The tag update reads only where each point lands relative to its
+// subtree's pivot ss(2s+1): before it (new tag 2s+1), at it (node s is
+// fixed), after it (2s+2).  Once the pivot's key is known, that is one
+// comparison per point, and a stable split by it leaves the two children in
+// their parent's order -- so every segment keeps the order of iteration 0,
+// the root dimension's sorted order.  The pivot's key is the key of rank
+// ss(2s+1) in the segment; k_level_select finds it digit by digit from
+// per-segment digit histograms (radix select), and where the segment is
+// already in split-key order (round robin, split dimension = the root's),
+// it is simply the key at that position.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,20 +26,18 @@
 
 namespace kdt {
 
-// One stable digit pass of the per-segment sort of iteration l, ordering each
-// subtree's points by the rank of its split dimension (RB-bit digits).  Tiles
-// never straddle a segment; global offsets are segment offset + digit prefix
-// inside the segment (from the histogram) + look-back over the segment's
-// earlier tiles.  LAST fuses the tag update of Sec. 3.2 into the scatter and,
-// for round robin, accumulates the next iteration's digit histograms.
-template <int K, bool LAST, bool WIDEST, int RB, int ITEMS>
-__global__ void __launch_bounds__(SWEEP_THREADS) k_level_pass(LevelPassArgs a)
+// Digit of the split pass: 0 smaller key, 1 the pivot, 2 larger key.
+constexpr int PART_RB = 2;
+
+template <int K, bool WIDEST, int ITEMS>
+__global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
 {
-    constexpr uint32_t NB = 1u << RB;
-    constexpr uint32_t MASK = NB - 1u;
     constexpr uint32_t T = SWEEP_THREADS * (uint32_t)ITEMS;
-    __shared__ SweepSmem<RB, K> sm;
-    __shared__ uint32_t nh[LAST ? 2 * MAX_LEVEL_PASSES * NB : 1];
+    __shared__ SweepSmem<PART_RB, K> sm;
+    __shared__ uint32_t nh[2 * MAX_BINS];   // top-digit histograms of the two children
+    __shared__ uint32_t segc[4];            // the segment's count of each split digit
+    __shared__ uint32_t ctl[2];             // the children's split dimensions
+    __shared__ uint32_t sel[2];
 
     if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -47,13 +57,53 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_pass(LevelPassArgs a)
     const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[off + v.Fl + seg] : st.level % a.k;
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint32_t live = v.n - v.Fl;
-    const uint32_t shift = a.shift;
-    const uint32_t* seg_hist = a.hist + st.hist + ((size_t)seg * a.passes + a.pass) * NB;
-    const uint32_t NP = a.passes;
-    const bool acc = LAST && a.acc_next && st.hist_next != 0xFFFFFFFFu;
-    if (acc) {
-        for (uint32_t x = threadIdx.x; x < 2u * NP * NB; x += SWEEP_THREADS) nh[x] = 0u;
+    const uint32_t RBv = a.radix_bits;
+    const uint32_t NB = 1u << RBv;
+    const uint32_t P = a.passes;
+    const uint32_t top = RBv * (P - 1u);
+    const uint32_t ls = seg_left_size(v, seg);        // ss(2s+1): rank of the pivot in the segment
+    const uint32_t s = v.Fl + seg;
+    const bool keys = a.keys_next != 0u && st.hist_next != 0xFFFFFFFFu;
+    if (keys) {
+        for (uint32_t x = threadIdx.x; x < 2u * NB; x += SWEEP_THREADS) nh[x] = 0u;
     }
+
+    // the pivot's key (its rank in dimension d)
+    uint32_t p = 0;
+    if (a.sorted) {
+        p = pick4(load_rec4<K>(a.rin, off + soff + ls), d);
+    } else {
+        const uint32_t* h = a.hist + st.hist + (size_t)seg * P * NB;
+        uint32_t kk = ls;
+        for (int jj = (int)P - 1; jj >= 0; --jj)
+            p = (p << RBv) | find_bucket(h + (size_t)jj * NB, NB, kk, sm.sh, sel, a.o.status);
+    }
+    p = uniform(p);
+    // the pivot's point fixes node s (the segment's first tile places it)
+    // and, for split-widest, the children's dimensions
+    if (threadIdx.x == 0) {
+        uint32_t idx = 0;
+        if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
+        if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
+        uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;
+        if (WIDEST) {
+            const float plane = a.o.pts[(off + idx) * K + d];
+            const float* bc = a.o.box[st.level & 1u] + ((size_t)ti.box_off + seg) * 8;
+            c0 = child_dim<K>(bc, plane, d, 0u);
+            c1 = child_dim<K>(bc, plane, d, 1u);
+            if (u == 0) widest_children<K>(a.o, ti, s, seg, plane, d, a.o.box[st.level & 1u],
+                                           a.o.box[(st.level + 1u) & 1u]);
+        }
+        if (u == 0) place<K, WIDEST>(a.o, ti, s, idx);
+        ctl[0] = c0;
+        ctl[1] = c1;
+        segc[0] = ls;
+        segc[1] = 1u;
+        segc[2] = ssz - ls - 1u;
+        segc[3] = 0u;
+    }
+    __syncthreads();
+    const uint32_t cd0 = uniform(ctl[0]), cd1 = uniform(ctl[1]);
 
     uint4 rec[ITEMS];
     uint32_t dig[ITEMS];
@@ -63,84 +113,54 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_pass(LevelPassArgs a)
         const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
         ok[i] = j < cnt;
         rec[i] = ok[i] ? load_rec4<K>(a.rin, off + soff + start + j) : make_uint4(0u, 0u, 0u, 0u);
-        dig[i] = (pick4(rec[i], d) >> shift) & MASK;
+        const uint32_t x = pick4(rec[i], d);
+        dig[i] = x < p ? 0u : (x == p ? 1u : 2u);
     }
-    auto digit_of = [&](const uint4& r) { return (pick4(r, d) >> shift) & MASK; };
-    if (!LAST) {
-        sweep_tile<RB, ITEMS, K>(sm, rec, ok, dig, ITEMS, cnt, seg_hist, soff, a.lb, g, g - u, a.o.status, digit_of,
-                                 [&](uint32_t, uint32_t pos, const uint4& r) {
-                                     if (in_bounds(pos, live, a.o.status)) store_rec4<K>(a.rout, off + pos, r);
-                                 });
-        zero_range(a.lb_zero, a.lb_zero_n);
-        zero_range(a.zero2, a.zero2_n);
-        return;
-    }
-    // tag update (Sec. 3.2) for subtree s = F(l) + seg: the sorted segment is
-    // [soff, soff + ssz); the pivot is the entry at soff + ss(2s+1).
-    const uint32_t piv = seg_pivot(v, seg);
-    const uint32_t s = v.Fl + seg;
-    const uint32_t dn = (st.level + 1u) % a.k;
-    sweep_tile<RB, ITEMS, K>(
-        sm, rec, ok, dig, ITEMS, cnt, seg_hist, soff, a.lb, g, g - u, a.o.status, digit_of,
+    auto digit_of = [&](const uint4& r) {
+        const uint32_t x = pick4(r, d);
+        return x < p ? 0u : (x == p ? 1u : 2u);
+    };
+    const uint32_t piv = soff + ls;
+    sweep_tile<PART_RB, ITEMS, K>(
+        sm, rec, ok, dig, ITEMS, cnt, segc, soff, a.lb, g, g - u, a.o.status, digit_of,
         [&](uint32_t, uint32_t pos, const uint4& r) {
-            if (pos == piv) {
-                if (!in_bounds(r.x, ti.n, a.o.status)) return;
-                const uint32_t idx = a.o.perm0[off + r.x];
-                place<K, WIDEST>(a.o, ti, s, idx);
-                if (WIDEST)
-                    widest_children<K>(a.o, ti, s, seg, a.o.pts[(off + idx) * K + d], d, a.o.box[st.level & 1u],
-                                       a.o.box[(st.level + 1u) & 1u]);
-                return;
-            }
+            if (pos == piv) return;                 // node s, placed above
             const uint32_t side = pos > piv ? 1u : 0u;
-            const uint32_t nxt = pos - seg - side;
+            const uint32_t nxt = pos - seg - side;  // live position in iteration l+1
             if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - v.nseg, a.o.status)) return;
             store_rec4<K>(a.rout, off + nxt, r);
-            if (acc) {
-                const uint32_t vv = pick4(r, dn);
-                for (uint32_t p = 0; p < NP; ++p)
-                    atomicAdd(&nh[(side * NP + p) * NB + ((vv >> (RB * p)) & MASK)], 1u);
+            if (keys) {
+                const uint32_t kv = pick4(r, side ? cd1 : cd0);
+                a.kout[off + nxt] = kv;
+                atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
             }
         });
-    if (acc) {
-        // sweep_tile ends with a barrier, so nh is complete; children 2seg and
-        // 2seg+1 of the next iteration are adjacent
-        uint32_t* dst = a.hist + st.hist_next + (size_t)(2u * seg) * NP * NB;
-        for (uint32_t x = threadIdx.x; x < 2u * NP * NB; x += SWEEP_THREADS)
-            if (nh[x]) atomicAdd(&dst[x], nh[x]);
+    if (keys) {
+        // sweep_tile ends with a barrier, so nh is complete; children 2seg
+        // and 2seg+1 are segments of iteration l+1
+        for (uint32_t x = threadIdx.x; x < 2u * NB; x += SWEEP_THREADS) {
+            const uint32_t c = x / NB;
+            if (nh[x])
+                atomicAdd(&a.hist[st.hist_next + ((size_t)(2u * seg + c) * P + P - 1u) * NB + (x - c * NB)], nh[x]);
+        }
     }
     zero_range(a.lb_zero, a.lb_zero_n);
     zero_range(a.zero2, a.zero2_n);
 }
 
-template <int K, int RB, int ITEMS>
-static void level_pass_kri(const LevelPassArgs& a, uint32_t tiles, bool last, bool widest, hipStream_t st)
+template <int K, int ITEMS>
+static void level_part_ki(const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st)
 {
-    if (last) {
-        if (widest) k_level_pass<K, true, true, RB, ITEMS><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-        else k_level_pass<K, true, false, RB, ITEMS><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-    } else {
-        if (widest) k_level_pass<K, false, true, RB, ITEMS><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-        else k_level_pass<K, false, false, RB, ITEMS><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-    }
-}
-
-template <int K, int RB>
-static void level_pass_kr(const LevelPassArgs& a, uint32_t tiles, bool last, bool widest, hipStream_t st)
-{
-    switch (a.items) {
-    case 4: level_pass_kri<K, RB, 4>(a, tiles, last, widest, st); break;
-    default: level_pass_kri<K, RB, 8>(a, tiles, last, widest, st); break;
-    }
+    if (widest) k_level_part<K, true, ITEMS><<<tiles, SWEEP_THREADS, 0, st>>>(a);
+    else k_level_part<K, false, ITEMS><<<tiles, SWEEP_THREADS, 0, st>>>(a);
 }
 
 template <int K>
-void launch_level_pass_k(const LevelPassArgs& a, uint32_t tiles, bool last, bool widest, hipStream_t st)
+void launch_level_part_k(const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st)
 {
-    switch (a.radix_bits) {
-    case 8: level_pass_kr<K, 8>(a, tiles, last, widest, st); break;
-    case 9: level_pass_kr<K, 9>(a, tiles, last, widest, st); break;
-    default: level_pass_kr<K, 10>(a, tiles, last, widest, st); break;
+    switch (a.items) {
+    case 4: level_part_ki<K, 4>(a, tiles, widest, st); break;
+    default: level_part_ki<K, 8>(a, tiles, widest, st); break;
     }
 }
 

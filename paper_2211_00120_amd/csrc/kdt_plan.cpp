@@ -15,7 +15,7 @@ namespace kdt {
 
 namespace {
 
-// Records per thread of an iteration's sort tiles (tile = SWEEP_THREADS * items): the
+// Records per thread of an iteration's split tiles (tile = SWEEP_THREADS * items): the
 // largest tile that the iteration's biggest subtree still fills.
 uint32_t level_items(uint32_t big, uint32_t cap)
 {
@@ -175,7 +175,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         }
     }
 
-    // digit width of the level sorts: fewest passes over the largest rank
+    // digit width of the pivot selects: fewest digits over the largest rank
     // with 8..10-bit digits, then the narrowest digit that keeps that count
     // (a tree of more than TAIL_CAP points has ranks of >= 12 bits, so P >= 2)
     for (uint32_t t : p.large) p.B = std::max(p.B, rank_bits(n[t]));
@@ -210,10 +210,13 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         p.roots.push_back(step(t, 0u, 0u));
     }
 
-    // iterations 1 .. run as digit passes (tree t takes part while l < l0[t])
+    // iterations 1 .. run as digit passes (tree t takes part while l < l0[t]);
+    // every segment stays in the root dimension's order, which for round
+    // robin is dimension 0
     for (uint32_t l = 1; l < maxl; ++l) {
         LevelLaunch ll;
         ll.level = l;
+        ll.sorted = !widest && l % k == 0;
         uint32_t big = 0;
         for (uint32_t t : p.large)
             if (l < l0[t]) big = std::max(big, seg_size(make_level(n[t], l), 0));
@@ -226,19 +229,19 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
             ll.tiles += tiles_level(v, (uint32_t)SWEEP_THREADS * ll.items).tiles;
             ll.hist_words += v.nseg * p.P * NB;
             ll.steps.push_back(s);
-            TreeStep h = step(t, l, ll.hist_tiles);
-            ll.hist_tiles += tiles_level(v, HIST_TILE).tiles;
-            ll.hsteps.push_back(h);
+            TreeStep h = step(t, l, ll.select_tiles);
+            ll.select_tiles += tiles_level(v, HIST_TILE).tiles;
+            ll.ssteps.push_back(h);
         }
         p.hist_words = std::max(p.hist_words, ll.hist_words);
         p.levels.push_back(std::move(ll));
     }
-    // iteration l's histograms live in half (l & 1) of the histogram region
+    // iteration l's histograms live in third (l mod 3) of the histogram region
     for (LevelLaunch& ll : p.levels) {
-        const uint32_t base = (ll.level & 1u) * p.hist_words;
+        const uint32_t base = (ll.level % 3u) * p.hist_words;
         for (size_t i = 0; i < ll.steps.size(); ++i) {
             ll.steps[i].hist += base;
-            ll.hsteps[i].hist = ll.steps[i].hist;
+            ll.ssteps[i].hist = ll.steps[i].hist;
         }
     }
     // each share's histogram offset for the next iteration
@@ -252,14 +255,14 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         for (TreeStep& s : p.levels[li].steps) s.hist_next = next_hist(li + 1, s.tree);
     for (TreeStep& s : p.level0) s.hist_next = next_hist(0, s.tree);
 
-    // the tail of every large tree from its own first tail iteration; the
-    // level sorts flip the record buffer once per pass
+    // the tail of every large tree from its own first tail iteration; each
+    // iteration's split flips the record buffer
     for (uint32_t t : p.large) {
         const Level v = make_level(n[t], l0[t]);
         const uint32_t G = std::max(1u, std::min({TAIL_CAP / seg_size(v, 0), v.nseg, 2u}));
         TreeStep s = step(t, l0[t], p.tail_groups);
         s.G = G;
-        s.buf = ((l0[t] - 1u) * p.P) & 1u;
+        s.buf = (l0[t] - 1u) & 1u;
         p.tail.push_back(s);
         p.tail_groups += ceil_div(v.nseg, G);
     }
@@ -267,8 +270,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     // look-back words per pass, in the order the passes run
     if (!p.large.empty())
         for (uint32_t q = 0; q < 4u * k; ++q) p.pass_words.push_back(p.presort_tiles * RADIX_HOST);
-    for (const LevelLaunch& ll : p.levels)
-        for (uint32_t q = 0; q < p.P; ++q) p.pass_words.push_back(ll.tiles * NB);
+    for (const LevelLaunch& ll : p.levels) p.pass_words.push_back(ll.tiles * PART_BINS);
     for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
 
     // share tables
@@ -282,7 +284,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.tables = p.small.size() > 1 || p.large.size() > 1;
     for (const LevelLaunch& ll : p.levels) {
         p.t_level.push_back(push_table(p.blob, ll.steps.data(), ll.steps.size() * sizeof(TreeStep)));
-        p.t_hist.push_back(push_table(p.blob, ll.hsteps.data(), ll.hsteps.size() * sizeof(TreeStep)));
+        p.t_select.push_back(push_table(p.blob, ll.ssteps.data(), ll.ssteps.size() * sizeof(TreeStep)));
     }
 
     // workspace
@@ -296,7 +298,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_status = take(64);
     p.o_counters = take(MAX_PASSES * 4);
     p.o_hist_rank = take((size_t)p.large.size() * k * 4 * RADIX_HOST * 4);
-    p.o_hist = take((size_t)p.hist_words * 2 * 4);
+    p.o_hist = take((size_t)p.hist_words * 3 * 4);
     p.o_lb[0] = take((size_t)p.lb_words * 4);
     p.o_lb[1] = take((size_t)p.lb_words * 4);
     p.o_keys = take(N * k * 4);

@@ -3,8 +3,9 @@
 // A call builds a list of independent trees.  The plan fixes, from the tree
 // sizes, k and the split rule alone: which trees are built whole by one
 // workgroup, the launch sequence of the others (prep, presorts, iteration
-// 0, the iterations run as segmented digit passes, the tail), every launch's
-// share table, the digit width of the level sorts and the workspace layout.
+// 0, the iterations run as pivot selects and splits, the tail), every
+// launch's share table, the digit width of the pivot selects and the
+// workspace layout.
 #pragma once
 
 #include <stddef.h>
@@ -22,23 +23,27 @@ constexpr uint32_t NO_HIST = 0xFFFFFFFFu;
 
 // Choices the planner otherwise makes itself (0 = automatic).
 struct PlanOptions {
-    uint32_t radix_bits = 0;   // digit width of the level sorts: 8, 9 or 10
-    uint32_t max_items = 0;    // cap on records per thread of the level-sort tiles: 4 or 8
+    uint32_t radix_bits = 0;   // digit width of the pivot selects: 8, 9 or 10
+    uint32_t max_items = 0;    // cap on records per thread of the split tiles: 4 or 8
 };
 
 // One iteration run as digit passes over every tree that still has subtrees
-// larger than TAIL_CAP.
+// larger than TAIL_CAP: P-1 pivot-select launches (none when `sorted`), then
+// the split.
 struct LevelLaunch {
     uint32_t level = 0;
-    uint32_t items = 4;              // records per thread of its sort tiles
-    uint32_t tiles = 0;              // sort tiles
-    uint32_t hist_tiles = 0;         // split-widest histogram tiles
+    uint32_t items = 4;              // records per thread of its split tiles
+    uint32_t tiles = 0;              // split tiles
+    uint32_t select_tiles = 0;       // pivot-select tiles
     uint32_t hist_words = 0;         // words of its digit histograms
-    std::vector<TreeStep> steps;     // sort shares
-    std::vector<TreeStep> hsteps;    // split-widest histogram shares (tiles of HIST_TILE)
+    bool sorted = false;             // round robin at the root's dimension: segments are in key order
+    std::vector<TreeStep> steps;     // split shares
+    std::vector<TreeStep> ssteps;    // pivot-select shares (tiles of HIST_TILE)
 };
 
 // Everything about one call that depends only on the tree sizes, k and mode.
+// Iteration l's digit histograms live in third (l mod 3) of the histogram
+// region, so that the split of iteration l can clear the third of l + 2.
 struct Plan {
     uint32_t k = 0;
     bool widest = false;
@@ -46,18 +51,18 @@ struct Plan {
     std::vector<TreeInfo> trees;     // every tree of the call
     std::vector<uint32_t> large;     // trees built by digit passes
     std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
-    uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / passes of the level sorts
+    uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / digits of the pivot selects
     std::vector<TreeStep> prep, presort, level0, tail, roots;
     uint32_t prep_tiles = 0, presort_tiles = 0, tail_groups = 0;
     std::vector<LevelLaunch> levels; // iterations 1.. run as passes
-    uint32_t hist_words = 0;         // per parity half of the histogram region
+    uint32_t hist_words = 0;         // per third of the histogram region
     uint32_t lb_words = 0;           // per look-back buffer
     uint32_t box_entries = 0;        // per split-widest domain buffer
     std::vector<uint32_t> pass_words;// look-back words of every onesweep pass, in order
     bool tables = false;             // some launch reads a device share table
     std::vector<uint8_t> blob;       // the share tables, as uploaded
     size_t t_trees = 0, t_small = 0, t_prep = 0, t_presort = 0, t_level0 = 0, t_tail = 0, t_roots = 0;
-    std::vector<size_t> t_level, t_hist;
+    std::vector<size_t> t_level, t_select;
     // workspace offsets (bytes)
     size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,
            o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_tables = 0,

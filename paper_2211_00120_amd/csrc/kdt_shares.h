@@ -11,8 +11,9 @@ constexpr uint32_t KDT_STATUS_INTERNAL = 0x100; // an internal bound or wait che
 
 constexpr uint32_t RADIX_HOST = 256;
 constexpr uint32_t MAX_PASSES = 256;       // onesweep passes per build (tile counters)
-constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digit passes over a rank of at most 30 bits (8..10-bit digits)
+constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digits of a rank of at most 30 bits (8..10-bit digits)
 constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
+constexpr uint32_t PART_BINS = 4;          // digit values of the split passes (smaller, pivot, larger)
 constexpr uint32_t PREP_TILE = 4096;       // points per workgroup of prep / iteration 0
 
 // Threads of the onesweep workgroups (presort and level passes).
@@ -27,7 +28,7 @@ constexpr int SWEEP_THREADS = KDT_SWEEP_THREADS;
 #endif
 constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
 constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
-constexpr uint32_t HIST_TILE = 16384;      // chunk of the split-widest histogram kernel
+constexpr uint32_t HIST_TILE = 16384;      // keys per workgroup of the pivot selects
 constexpr int TAIL_THREADS = 512;          // subtree tail: 512 threads x 4 slots = up to 2048 points
 constexpr int TAIL_ITEMS = 4;
 constexpr uint32_t TAIL_CAP = (uint32_t)TAIL_THREADS * TAIL_ITEMS;

@@ -106,6 +106,54 @@ __device__ __forceinline__ void sweep_excl_scan2(uint32_t a, uint32_t b, uint32_
     eb = bb + ib - b;
 }
 
+// Pivot search in one digit histogram h (NB counts) of a segment: the digit
+// value whose run holds the key of rank kk (0-based) among the counted keys;
+// kk becomes its rank inside that run.  Workgroup-wide: every thread passes
+// the same kk and gets the same result.  sh: 2*SWEEP_WAVES words and sel: 2
+// words of LDS.  A histogram that holds fewer than kk + 1 keys flags an
+// internal error and yields digit 0.  Contains barriers; ends with one.
+constexpr uint32_t FIND_BPT = (MAX_BINS + SWEEP_THREADS - 1) / SWEEP_THREADS;
+
+__device__ __forceinline__ uint32_t find_bucket(const uint32_t* h, uint32_t NB, uint32_t& kk, uint32_t* sh,
+                                                uint32_t* sel, uint32_t* status)
+{
+    const uint32_t bpt = (NB + SWEEP_THREADS - 1u) / SWEEP_THREADS;
+    const uint32_t t0 = threadIdx.x * bpt;
+    uint32_t c[FIND_BPT];
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < FIND_BPT; ++b) {
+        c[b] = (b < bpt && t0 + b < NB) ? h[t0 + b] : 0u;
+        sum += c[b];
+    }
+    if (threadIdx.x == 0) sel[0] = 0xFFFFFFFFu;
+    // the scan's barriers order the sentinel before the hit's write below
+    const uint32_t ex = sweep_excl_scan(sum, sh);
+    if (kk >= ex && kk - ex < sum) {
+        uint32_t run = ex;
+#pragma unroll
+        for (uint32_t b = 0; b < FIND_BPT; ++b) {
+            if (kk - run < c[b]) {
+                sel[0] = t0 + b;
+                sel[1] = kk - run;
+                break;
+            }
+            run += c[b];
+        }
+    }
+    __syncthreads();
+    uint32_t bk = sel[0];
+    uint32_t rest = sel[1];
+    __syncthreads();
+    if (bk == 0xFFFFFFFFu) {
+        if (threadIdx.x == 0) atomicOr(status, 0x100u);
+        bk = 0u;
+        rest = 0u;
+    }
+    kk = uniform(rest);
+    return uniform(bk);
+}
+
 // Stable wave multisplit over RB-bit digits of the first `active` items.
 template <int RB, int ITEMS>
 __device__ __forceinline__ void wave_multisplit16(const uint32_t (&digit)[ITEMS], const bool (&valid)[ITEMS],

@@ -20,8 +20,8 @@
 //     segment 2q or 2q+1 of the next iteration; at l = L-2 the children are
 //     leaves and are placed directly.
 //
-// The input order of a subtree is its parent's sorted order, so the parent's
-// dimension needs no sort (round robin: dimension (l0-1) mod k).
+// The iterations before l0 split every segment stably, so a subtree's input
+// is in the root dimension's order, and that dimension needs no sort.
 //
 // A whole tree of at most TAIL_CAP points is built the same way straight
 // from its points (from_points): the per-dimension orders come from a stable
@@ -252,14 +252,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
         for (int d = 0; d < 8; ++d) rootbox[q][d] = bx[d];
         segdim[0][q] = o.dimnode[off + v0.Fl + i0 + q];
     }
-    // dimension whose order the input already has (within every segment)
+    // dimension whose order the input already has (within every segment):
+    // the root's
     uint32_t free_dim = 0xFFFFFFFFu;
-    if (!FP) {
-        if (!WIDEST) free_dim = (l0 + (uint32_t)K - 1u) % (uint32_t)K;
-        // the parent's dimension (a group of two subtrees starts at an even
-        // i0, so both are children of the same parent)
-        else free_dim = o.dimnode[off + ((v0.Fl + i0 - 1u) >> 1)];
-    }
+    if (!FP) free_dim = WIDEST ? (uint32_t)o.dimnode[off] : 0u;
     __syncthreads();
 
     // ---- ord_d: the group sorted by rank_d (stable LSD radix in LDS) ----

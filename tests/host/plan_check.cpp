@@ -129,6 +129,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         const LevelLaunch& ll = p.levels[li];
         const uint32_t l = (uint32_t)li + 1;
         CHECK(ll.level == l && (ll.items == 4 || ll.items == 8), "level %u", l);
+        CHECK(ll.sorted == (!widest && l % k == 0), "level %u sorted flag", l);
         if (opt.max_items) CHECK(ll.items <= opt.max_items, "items cap");
         std::vector<std::pair<uint64_t, uint64_t>> hist;
         uint32_t tiles = 0, htiles = 0;
@@ -138,14 +139,14 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
             CHECK(si < ll.steps.size(), "level %u misses tree %u", l, t);
             if (si >= ll.steps.size()) break;
             const TreeStep& s = ll.steps[si];
-            const TreeStep& h = ll.hsteps[si];
+            const TreeStep& h = ll.ssteps[si];
             ++si;
             const Level v = make_level(n[t], l);
             CHECK(s.tree == t && s.level == l && s.tile0 == tiles, "level %u share of tree %u", l, t);
-            CHECK(h.tree == t && h.tile0 == htiles && h.hist == s.hist, "hist share of tree %u", t);
+            CHECK(h.tree == t && h.tile0 == htiles && h.hist == s.hist, "select share of tree %u", t);
             tiles += tiles_level(v, (uint32_t)SWEEP_THREADS * ll.items).tiles;
             htiles += tiles_level(v, HIST_TILE).tiles;
-            const uint64_t lo = (l & 1u) * (uint64_t)p.hist_words, hi = lo + p.hist_words;
+            const uint64_t lo = (l % 3u) * (uint64_t)p.hist_words, hi = lo + p.hist_words;
             const uint64_t words = (uint64_t)v.nseg * p.P * NB;
             CHECK(s.hist >= lo && s.hist + words <= hi, "hist range of tree %u at level %u", t, l);
             hist.push_back({s.hist, s.hist + words});
@@ -161,8 +162,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
             }
         }
         CHECK(disjoint(hist), "histogram ranges overlap at level %u", l);
-        CHECK(si == ll.steps.size() && ll.hsteps.size() == si, "level %u share count", l);
-        CHECK(tiles == ll.tiles && htiles == ll.hist_tiles, "level %u tile totals", l);
+        CHECK(si == ll.steps.size() && ll.ssteps.size() == si, "level %u share count", l);
+        CHECK(tiles == ll.tiles && htiles == ll.select_tiles, "level %u tile totals", l);
         uint32_t hw = 0;
         for (const TreeStep& s : ll.steps) hw += make_level(n[s.tree], l).nseg * p.P * NB;
         CHECK(hw == ll.hist_words && hw <= p.hist_words, "level %u hist words", l);
@@ -184,20 +185,22 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         const Level v = make_level(n[t], l0[t]);
         CHECK(s.tree == t && s.level == l0[t] && s.tile0 == groups, "tail share of tree %u", t);
         CHECK(s.G >= 1 && s.G <= 2 && (uint64_t)s.G * biggest_subtree(n[t], l0[t]) <= TAIL_CAP, "tail G of %u", t);
-        CHECK(s.buf == (((l0[t] - 1u) * p.P) & 1u), "tail buffer of tree %u", t);
+        CHECK(s.buf == ((l0[t] - 1u) & 1u), "tail buffer of tree %u", t);
         groups += (v.nseg + s.G - 1) / s.G;
     }
     CHECK(groups == p.tail_groups, "tail groups");
     // look-back words
-    const size_t npass = (p.large.empty() ? 0 : 4u * k) + p.levels.size() * p.P;
+    const size_t npass = (p.large.empty() ? 0 : 4u * k) + p.levels.size();
     CHECK(p.pass_words.size() == npass && npass <= MAX_PASSES, "pass count");
+    for (size_t li = 0; li < p.levels.size(); ++li)
+        CHECK(p.pass_words[4u * k + li] == p.levels[li].tiles * PART_BINS, "split look-back words of level %zu", li);
     for (uint32_t w : p.pass_words) CHECK(w <= p.lb_words, "look-back words");
     // workspace regions: aligned, in order, disjoint
     const size_t N = p.ntotal;
     struct R { size_t off, bytes; const char* name; } regs[] = {
         {p.o_status, 64, "status"}, {p.o_counters, MAX_PASSES * 4, "counters"},
         {p.o_hist_rank, p.large.size() * k * 4 * RADIX_HOST * 4, "hist_rank"},
-        {p.o_hist, (size_t)p.hist_words * 8, "hist"}, {p.o_lb[0], (size_t)p.lb_words * 4, "lb0"},
+        {p.o_hist, (size_t)p.hist_words * 12, "hist"}, {p.o_lb[0], (size_t)p.lb_words * 4, "lb0"},
         {p.o_lb[1], (size_t)p.lb_words * 4, "lb1"}, {p.o_keys, N * k * 4, "keys"}, {p.o_perms, N * k * 4, "perms"},
         {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, p.rec_words * 8, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
         {p.o_dimnode, N, "dimnode"}, {p.o_box[0], (size_t)p.box_entries * 32, "box0"},
@@ -220,8 +223,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     for (size_t li = 0; li < p.levels.size(); ++li) {
         CHECK(same(p.t_level[li], p.levels[li].steps.data(), p.levels[li].steps.size() * sizeof(TreeStep)),
               "level table %zu", li);
-        CHECK(same(p.t_hist[li], p.levels[li].hsteps.data(), p.levels[li].hsteps.size() * sizeof(TreeStep)),
-              "hist table %zu", li);
+        CHECK(same(p.t_select[li], p.levels[li].ssteps.data(), p.levels[li].ssteps.size() * sizeof(TreeStep)),
+              "select table %zu", li);
     }
     CHECK(p.tables == (p.small.size() > 1 || p.large.size() > 1), "table flag");
     check_steps_tile(p.small, (uint32_t)p.small.size(), "small");
