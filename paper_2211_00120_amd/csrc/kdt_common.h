@@ -45,7 +45,7 @@ __device__ __forceinline__ void find_share(const Shares& sh, uint32_t g, TreeSte
     st.tile0 = uniform(s.tile0);
     st.hist = uniform(s.hist);
     st.hist_next = uniform(s.hist_next);
-    st.G = uniform(s.G);
+    st.pair0 = uniform(s.pair0);
     st.buf = uniform(s.buf);
     ti.off = uniform(t.off);
     ti.n = uniform(t.n);

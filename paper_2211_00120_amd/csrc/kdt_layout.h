@@ -161,4 +161,13 @@ KDT_HD void tile_locate(const SegTiles& t, uint32_t g, uint32_t& seg, uint32_t& 
     u = q - j * t.ts;
 }
 
+// Workgroups of the tail over the nseg subtrees of one tree's first tail
+// iteration: subtrees [0, pair0) one each, the later ones two each.
+KDT_HD uint32_t tail_group_count(uint32_t nseg, uint32_t pair0) { return pair0 + (nseg - pair0 + 1u) / 2u; }
+KDT_HD void tail_group_range(uint32_t gi, uint32_t pair0, uint32_t nseg, uint32_t& i0, uint32_t& i1)
+{
+    i0 = gi < pair0 ? gi : pair0 + 2u * (gi - pair0);
+    i1 = umin(i0 + (gi < pair0 ? 1u : 2u), nseg);
+}
+
 }  // namespace kdt

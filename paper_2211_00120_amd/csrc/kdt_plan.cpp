@@ -31,7 +31,7 @@ TreeStep step(uint32_t tree, uint32_t level, uint32_t tile0)
     s.tile0 = tile0;
     s.hist = 0;
     s.hist_next = NO_HIST;
-    s.G = 0;
+    s.pair0 = 0;
     s.buf = 0;
     return s;
 }
@@ -167,7 +167,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         if (n[t] == 0) continue;
         if (n[t] <= TAIL_CAP) {
             TreeStep s = step(t, 0u, (uint32_t)p.small.size());
-            s.G = 1;
+            s.pair0 = 1;
             p.small.push_back(s);
         } else {
             p.trees[t].idx = (uint32_t)p.large.size();
@@ -257,14 +257,21 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
 
     // the tail of every large tree from its own first tail iteration; each
     // iteration's split flips the record buffer
+    // (subtree sizes never grow with the index, so the subtrees that fit
+    // two to a workgroup are a suffix)
     for (uint32_t t : p.large) {
         const Level v = make_level(n[t], l0[t]);
-        const uint32_t G = std::max(1u, std::min({TAIL_CAP / seg_size(v, 0), v.nseg, 2u}));
+        // sizes: 2W-1 below a = R/W, then one of W-1 + R%W, then W-1
+        const uint32_t half = TAIL_CAP / 2u, a = v.R / v.W;
+        uint32_t pair0 = v.nseg;
+        if (seg_size(v, 0) <= half) pair0 = 0;
+        else if (a < v.nseg && seg_size(v, a) <= half) pair0 = a;
+        else if (a + 1u < v.nseg && seg_size(v, a + 1u) <= half) pair0 = a + 1u;
         TreeStep s = step(t, l0[t], p.tail_groups);
-        s.G = G;
+        s.pair0 = pair0;
         s.buf = (l0[t] - 1u) & 1u;
         p.tail.push_back(s);
-        p.tail_groups += ceil_div(v.nseg, G);
+        p.tail_groups += tail_group_count(v.nseg, pair0);
     }
 
     // look-back words per pass, in the order the passes run

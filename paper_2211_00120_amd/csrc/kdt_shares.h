@@ -48,7 +48,7 @@ struct TreeStep {
     uint32_t tile0;      // first tile (tail: first workgroup) of this share
     uint32_t hist;       // word offset of the share's digit histograms for this iteration
     uint32_t hist_next;  // word offset of its histograms for the next iteration (~0u: none)
-    uint32_t G;          // tail: level-l0 subtrees per workgroup
+    uint32_t pair0;      // tail: level-l0 subtrees [0, pair0) take one workgroup each, the later ones two
     uint32_t buf;        // tail: record buffer (0/1) that holds the tree's level-l0 records
 };
 

@@ -158,8 +158,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     const Level v0 = make_level(ti.n, FP ? 0u : stp.level);
     const uint32_t l0 = v0.l;
     const uint32_t L = v0.L;
-    const uint32_t i0 = (blockIdx.x - stp.tile0) * stp.G;
-    const uint32_t i1 = min(i0 + stp.G, v0.nseg);
+    uint32_t i0, i1;
+    tail_group_range(blockIdx.x - stp.tile0, stp.pair0, v0.nseg, i0, i1);
     const uint32_t gc = i1 - i0;
     const uint32_t live0 = v0.n - v0.Fl;
     const uint32_t off0 = FP ? 0u : seg_offset(v0, i0);

@@ -44,6 +44,22 @@ static uint64_t biggest_subtree(uint64_t n, uint32_t l)
     return best;
 }
 
+// sizes of the subtrees of level l, in level order
+static std::vector<uint64_t> subtree_sizes(uint64_t n, uint32_t l)
+{
+    std::vector<uint64_t> out;
+    const uint64_t first = (1ull << l) - 1;
+    for (uint64_t s = first; s < 2 * first + 1 && s < n; ++s) {
+        uint64_t c = 0;
+        for (uint64_t lo = s, w = 1; lo < n; lo = 2 * lo + 1, w *= 2) {
+            const uint64_t hi = lo + w;
+            c += (hi < n ? hi : n) - lo;
+        }
+        out.push_back(c);
+    }
+    return out;
+}
+
 static bool disjoint(std::vector<std::pair<uint64_t, uint64_t>> r)
 {
     std::sort(r.begin(), r.end());
@@ -77,7 +93,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     std::vector<int> role(T, 0);
     for (size_t i = 0; i < p.small.size(); ++i) {
         const TreeStep& s = p.small[i];
-        CHECK(s.tile0 == i && s.G == 1 && n[s.tree] >= 1 && n[s.tree] <= TAIL_CAP, "small %zu", i);
+        CHECK(s.tile0 == i && s.pair0 == 1 && n[s.tree] >= 1 && n[s.tree] <= TAIL_CAP, "small %zu", i);
         role[s.tree] |= 1;
     }
     for (size_t i = 0; i < p.large.size(); ++i) {
@@ -184,9 +200,27 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         const uint32_t t = p.large[i];
         const Level v = make_level(n[t], l0[t]);
         CHECK(s.tree == t && s.level == l0[t] && s.tile0 == groups, "tail share of tree %u", t);
-        CHECK(s.G >= 1 && s.G <= 2 && (uint64_t)s.G * biggest_subtree(n[t], l0[t]) <= TAIL_CAP, "tail G of %u", t);
+        CHECK(s.pair0 <= v.nseg, "tail pair0 of %u", t);
         CHECK(s.buf == ((l0[t] - 1u) & 1u), "tail buffer of tree %u", t);
-        groups += (v.nseg + s.G - 1) / s.G;
+        // every workgroup's subtrees fit TAIL_CAP (sizes counted on the
+        // tree), every subtree is in exactly one group, and no lone subtree
+        // before pair0 could have shared a workgroup
+        const uint32_t ng = tail_group_count(v.nseg, s.pair0);
+        std::vector<uint64_t> sizes = subtree_sizes(n[t], l0[t]);
+        uint32_t covered = 0;
+        for (uint32_t gi = 0; gi < ng; ++gi) {
+            uint32_t i0, i1;
+            tail_group_range(gi, s.pair0, v.nseg, i0, i1);
+            CHECK(i0 == covered && i1 > i0 && i1 - i0 <= 2, "tail group %u of tree %u", gi, t);
+            uint64_t pts = 0;
+            for (uint32_t i = i0; i < i1 && i < sizes.size(); ++i) pts += sizes[i];
+            CHECK(pts <= TAIL_CAP, "tail group %u of tree %u holds %llu points", gi, t, (unsigned long long)pts);
+            covered = i1;
+        }
+        CHECK(covered == v.nseg, "tail groups of tree %u cover its subtrees", t);
+        for (uint32_t i = 0; i < s.pair0 && i < sizes.size(); ++i)
+            CHECK(sizes[i] > TAIL_CAP / 2, "subtree %u of tree %u could pair", i, t);
+        groups += ng;
     }
     CHECK(groups == p.tail_groups, "tail groups");
     // look-back words
