@@ -306,6 +306,15 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_select(LevelSelectArgs 
     const uint32_t sz = tiles_seg_size(tl, seg);
     const uint32_t start = u * HIST_TILE;
     const uint32_t cnt = min(HIST_TILE, sz - start);
+    // the chunk's keys first, so that their loads overlap the digit search
+    constexpr uint32_t KPT = HIST_TILE / SWEEP_THREADS;
+    const uint32_t* kin = a.kin + (size_t)ti.off + soff + start;
+    uint32_t key[KPT];
+#pragma unroll
+    for (uint32_t i = 0; i < KPT; ++i) {
+        const uint32_t x = i * SWEEP_THREADS + threadIdx.x;
+        key[i] = x < cnt ? kin[x] : 0u;
+    }
     uint32_t* h = a.hist + st.hist + (size_t)seg * P * NB;
     uint32_t kk = seg_left_size(v, seg);
     uint32_t prefix = 0;
@@ -314,10 +323,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_select(LevelSelectArgs 
     for (uint32_t jj = P - 1u; jj > j; --jj)
         prefix = (prefix << RBv) | find_bucket(h + (size_t)jj * NB, NB, kk, sh, sel, a.status);
     const uint32_t hs = RBv * (j + 1u), lo = RBv * j;
-    const uint32_t* kin = a.kin + (size_t)ti.off + soff + start;
-    for (uint32_t x = threadIdx.x; x < cnt; x += SWEEP_THREADS) {
-        const uint32_t key = kin[x];
-        if ((key >> hs) == prefix) atomicAdd(&lh[(key >> lo) & (NB - 1u)], 1u);
+#pragma unroll
+    for (uint32_t i = 0; i < KPT; ++i) {
+        const uint32_t x = i * SWEEP_THREADS + threadIdx.x;
+        if (x < cnt && (key[i] >> hs) == prefix) atomicAdd(&lh[(key[i] >> lo) & (NB - 1u)], 1u);
     }
     __syncthreads();
     uint32_t* dst = h + (size_t)j * NB;

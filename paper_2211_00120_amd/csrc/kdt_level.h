@@ -68,6 +68,16 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         for (uint32_t x = threadIdx.x; x < 2u * NB; x += SWEEP_THREADS) nh[x] = 0u;
     }
 
+    // the tile's records first, so that their loads overlap the pivot search
+    uint4 rec[ITEMS];
+    bool ok[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+        ok[i] = j < cnt;
+        rec[i] = ok[i] ? load_rec4<K>(a.rin, off + soff + start + j) : make_uint4(0u, 0u, 0u, 0u);
+    }
+
     // the pivot's key (its rank in dimension d)
     uint32_t p = 0;
     if (a.sorted) {
@@ -80,7 +90,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
     }
     p = uniform(p);
     // the pivot's point fixes node s (the segment's first tile places it)
-    // and, for split-widest, the children's dimensions
+    // and, for split-widest, the children's dimensions; sweep_tile's
+    // barriers publish ctl and segc before they are read
     if (threadIdx.x == 0) {
         uint32_t idx = 0;
         if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
@@ -102,17 +113,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         segc[2] = ssz - ls - 1u;
         segc[3] = 0u;
     }
-    __syncthreads();
-    const uint32_t cd0 = uniform(ctl[0]), cd1 = uniform(ctl[1]);
 
-    uint4 rec[ITEMS];
     uint32_t dig[ITEMS];
-    bool ok[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
-        ok[i] = j < cnt;
-        rec[i] = ok[i] ? load_rec4<K>(a.rin, off + soff + start + j) : make_uint4(0u, 0u, 0u, 0u);
         const uint32_t x = pick4(rec[i], d);
         dig[i] = x < p ? 0u : (x == p ? 1u : 2u);
     }
@@ -130,7 +134,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
             if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - v.nseg, a.o.status)) return;
             store_rec4<K>(a.rout, off + nxt, r);
             if (keys) {
-                const uint32_t kv = pick4(r, side ? cd1 : cd0);
+                const uint32_t kv = pick4(r, ctl[side]);
                 a.kout[off + nxt] = kv;
                 atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
             }
