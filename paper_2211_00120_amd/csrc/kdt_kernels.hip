@@ -320,8 +320,13 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_select(LevelSelectArgs 
     uint32_t prefix = 0;
     // digits above j (P >= 2 and j <= P-2: at least one; each search ends
     // with a barrier, which also orders the clearing of lh)
-    for (uint32_t jj = P - 1u; jj > j; --jj)
-        prefix = (prefix << RBv) | find_bucket(h + (size_t)jj * NB, NB, kk, sh, sel, a.status);
+    uint32_t c[MAX_LEVEL_PASSES][FIND_BPT];
+#pragma unroll
+    for (uint32_t jj = 0; jj < MAX_LEVEL_PASSES; ++jj)
+        if (jj > j && jj < P) load_bins(h + (size_t)jj * NB, NB, c[jj]);
+#pragma unroll
+    for (int jj = (int)MAX_LEVEL_PASSES - 1; jj >= 0; --jj)
+        if ((uint32_t)jj > j && (uint32_t)jj < P) prefix = (prefix << RBv) | find_bucket(c[jj], NB, kk, sh, sel, a.status);
     const uint32_t hs = RBv * (j + 1u), lo = RBv * j;
 #pragma unroll
     for (uint32_t i = 0; i < KPT; ++i) {

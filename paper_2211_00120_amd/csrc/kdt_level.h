@@ -84,9 +84,14 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         p = pick4(load_rec4<K>(a.rin, off + soff + ls), d);
     } else {
         const uint32_t* h = a.hist + st.hist + (size_t)seg * P * NB;
+        uint32_t c[MAX_LEVEL_PASSES][FIND_BPT];
+#pragma unroll
+        for (uint32_t jj = 0; jj < MAX_LEVEL_PASSES; ++jj)
+            if (jj < P) load_bins(h + (size_t)jj * NB, NB, c[jj]);
         uint32_t kk = ls;
-        for (int jj = (int)P - 1; jj >= 0; --jj)
-            p = (p << RBv) | find_bucket(h + (size_t)jj * NB, NB, kk, sm.sh, sel, a.o.status);
+#pragma unroll
+        for (int jj = (int)MAX_LEVEL_PASSES - 1; jj >= 0; --jj)
+            if ((uint32_t)jj < P) p = (p << RBv) | find_bucket(c[jj], NB, kk, sm.sh, sel, a.o.status);
     }
     p = uniform(p);
     // the pivot's point fixes node s (the segment's first tile places it)
@@ -94,8 +99,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
     // barriers publish ctl and segc before they are read
     if (threadIdx.x == 0) {
         uint32_t idx = 0;
-        if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
-        if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
+        if (WIDEST || u == 0) {
+            if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
+            if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
+        }
         uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;
         if (WIDEST) {
             const float plane = a.o.pts[(off + idx) * K + d];

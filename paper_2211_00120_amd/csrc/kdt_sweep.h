@@ -106,26 +106,32 @@ __device__ __forceinline__ void sweep_excl_scan2(uint32_t a, uint32_t b, uint32_
     eb = bb + ib - b;
 }
 
-// Pivot search in one digit histogram h (NB counts) of a segment: the digit
+// Pivot search in one digit histogram of a segment (NB counts): the digit
 // value whose run holds the key of rank kk (0-based) among the counted keys;
-// kk becomes its rank inside that run.  Workgroup-wide: every thread passes
-// the same kk and gets the same result.  sh: 2*SWEEP_WAVES words and sel: 2
+// kk becomes its rank inside that run.  Each thread passes its FIND_BPT
+// consecutive counts (load_bins), so that the loads of several digits can be
+// issued before the first search.  Workgroup-wide: every thread passes the
+// same kk and gets the same result.  sh: 2*SWEEP_WAVES words and sel: 2
 // words of LDS.  A histogram that holds fewer than kk + 1 keys flags an
 // internal error and yields digit 0.  Contains barriers; ends with one.
 constexpr uint32_t FIND_BPT = (MAX_BINS + SWEEP_THREADS - 1) / SWEEP_THREADS;
 
-__device__ __forceinline__ uint32_t find_bucket(const uint32_t* h, uint32_t NB, uint32_t& kk, uint32_t* sh,
-                                                uint32_t* sel, uint32_t* status)
+__device__ __forceinline__ void load_bins(const uint32_t* h, uint32_t NB, uint32_t (&c)[FIND_BPT])
 {
     const uint32_t bpt = (NB + SWEEP_THREADS - 1u) / SWEEP_THREADS;
     const uint32_t t0 = threadIdx.x * bpt;
-    uint32_t c[FIND_BPT];
+#pragma unroll
+    for (uint32_t b = 0; b < FIND_BPT; ++b) c[b] = (b < bpt && t0 + b < NB) ? h[t0 + b] : 0u;
+}
+
+__device__ __forceinline__ uint32_t find_bucket(const uint32_t (&c)[FIND_BPT], uint32_t NB, uint32_t& kk,
+                                                uint32_t* sh, uint32_t* sel, uint32_t* status)
+{
+    const uint32_t bpt = (NB + SWEEP_THREADS - 1u) / SWEEP_THREADS;
+    const uint32_t t0 = threadIdx.x * bpt;
     uint32_t sum = 0;
 #pragma unroll
-    for (uint32_t b = 0; b < FIND_BPT; ++b) {
-        c[b] = (b < bpt && t0 + b < NB) ? h[t0 + b] : 0u;
-        sum += c[b];
-    }
+    for (uint32_t b = 0; b < FIND_BPT; ++b) sum += c[b];
     if (threadIdx.x == 0) sel[0] = 0xFFFFFFFFu;
     // the scan's barriers order the sentinel before the hit's write below
     const uint32_t ex = sweep_excl_scan(sum, sh);

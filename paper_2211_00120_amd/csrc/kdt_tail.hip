@@ -178,40 +178,58 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     bool ok[ITEMS];
     bool bad = false;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-        ok[i] = e < m;
-        rec[i] = make_uint4(0u, 0u, 0u, 0u);
-        idx[i] = 0u;
-        pc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (FP) {
-            if (ok[i]) {
-                idx[i] = e;
-                pc[i] = load_point<K>(o.pts, off + e);
-                const float cf[4] = {pc[i].x, pc[i].y, pc[i].z, pc[i].w};
-                uint32_t kk[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-                for (int d = 0; d < K; ++d) {
-                    const uint32_t bits = __float_as_uint(cf[d]);
-                    bad |= nonfinite(bits);
-                    kk[d] = orderable(bits);
-                }
-                rec[i] = make_uint4(kk[0], kk[1], kk[2], kk[3]);
-            }
-            seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
-        } else {
-            if (ok[i]) rec[i] = load_rec4<K>(a.rin[stp.buf & 1u], off + off0 + e);
-            seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
-        }
-    }
-    if (!FP) {
+    for (int i = 0; i < ITEMS; ++i) ok[i] = w * CW + (uint32_t)i * 64u + lane < m;
+    if (FP) {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
-            if (ok[i] && in_bounds(rec[i].x, ti.n, o.status)) idx[i] = o.perm0[off + rec[i].x];
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            idx[i] = e;
+            pc[i] = ok[i] ? load_point<K>(o.pts, off + e) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) pc[i] = ok[i] ? load_point<K>(o.pts, off + idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            const float cf[4] = {pc[i].x, pc[i].y, pc[i].z, pc[i].w};
+            uint32_t kk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int d = 0; d < K; ++d) {
+                const uint32_t bits = __float_as_uint(cf[d]);
+                bad |= ok[i] && nonfinite(bits);
+                kk[d] = orderable(bits);
+            }
+            rec[i] = ok[i] ? make_uint4(kk[0], kk[1], kk[2], kk[3]) : make_uint4(0u, 0u, 0u, 0u);
+            seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
+        }
     } else {
+        // the records, then each slot's index (rank 0 -> index) and point: the
+        // loads of each kind go out together, and the gathers complete while
+        // the group sorts
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            rec[i] = ok[i] ? load_rec4<K>(a.rin[stp.buf & 1u], off + off0 + e) : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
+        }
+        bool oob = false;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool in = rec[i].x < ti.n;
+            oob |= ok[i] && !in;
+            idx[i] = (ok[i] && in) ? o.perm0[off + rec[i].x] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool in = idx[i] < ti.n;
+            oob |= ok[i] && !in;
+            pc[i] = (ok[i] && in) ? load_point<K>(o.pts, off + idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (__any(oob) && lane == 0) atomicOr(o.status, KDT_STATUS_INTERNAL);
+    }
+    if (FP) {
         if (__any(bad) && lane == 0) atomicOr(o.status, KDT_STATUS_NONFINITE);
         if (WIDEST) {
             // scene box of the tree (as orderable keys, then floats)
