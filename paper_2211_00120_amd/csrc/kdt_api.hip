@@ -253,8 +253,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
 
     if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, [&] {
             launch_init(dstatus, counters, hist_rank, nlarge_trees * k * 4 * RADIX_HOST, lb[0],
-                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, o.bbox,
-                        widest ? nlarge_trees : 0u, st);
+                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, o.bbox, nlarge_trees, st);
         }))
         return s;
 
@@ -291,7 +290,16 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
 
         // presort: per dimension, 4 stable digit passes of (key, index); the
         // (key, index) ping-pong lives in the record region (2 * rec_words >=
-        // 4 * ntotal words), which is free until iteration 0
+        // 4 * ntotal words), which is free until iteration 0.  A pass whose
+        // digit is the same in all keys of a tree is skipped for that tree;
+        // for the profile's byte counts, the key summaries are read back
+        // (profiling builds only)
+        std::vector<uint32_t> keysum;
+        if (g_prof.on) {
+            keysum.resize((size_t)nlarge_trees * KEYSUM_WORDS);
+            HIP_TRY(hipMemcpyAsync(keysum.data(), o.bbox, keysum.size() * 4, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
         uint32_t q = 0;
         uint32_t* kv[2] = {recbase, recbase + 2 * (size_t)ntotal};
         for (uint32_t d = 0; d < k; ++d) {
@@ -299,24 +307,35 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 PresortArgs a{};
                 a.sh = shares(p, p.presort, p.t_presort, ws);
                 a.kin = keys + (size_t)d * ntotal;
-                a.kvin = ps == 0 ? nullptr : kv[(ps - 1) & 1];
-                a.kvout = kv[ps & 1];
+                a.kv[0] = kv[0];
+                a.kv[1] = kv[1];
+                a.keysum = o.bbox;
+                a.pass = ps;
                 a.hist = hist_rank + (d * 4 + ps) * RADIX_HOST;
                 a.hist_stride = k * 4 * RADIX_HOST;
                 a.lb = lb[q & 1];
                 a.lb_zero = lb[(q + 1) & 1];
                 a.lb_zero_n = next_words(q);
                 a.counter = counters + q;
-                a.shift = 8 * ps;
                 a.perm_out = perms + (size_t)d * ntotal;
                 a.rank_table = ranks;
                 a.dimnode = widest ? o.dimnode : nullptr;
                 a.k = k;
                 a.dim = d;
                 a.status = dstatus;
-                if (kdt_status s = run_kernel(st, KIND_PRESORT, nlarge * (ps == 0 ? 12.0 : 16.0), [&] {
-                        launch_presort_pass(a, ps == 0, ps == 3, p.presort_tiles, st);
-                    }))
+                double bytes = 0;
+                if (g_prof.on) {
+                    for (uint32_t i = 0; i < nlarge_trees; ++i) {
+                        const uint32_t vary = keysum[i * KEYSUM_WORDS + 8 + d] ^ keysum[i * KEYSUM_WORDS + 12 + d];
+                        auto runs = [&](uint32_t qq) { return ((vary >> (8 * qq)) & 0xFFu) != 0u; };
+                        if (ps < 3 && !runs(ps)) continue;
+                        bool first = true;
+                        for (uint32_t qq = 0; qq < ps; ++qq) first = first && !runs(qq);
+                        bytes += p.trees[p.large[i]].n * (first ? 12.0 : 16.0);
+                    }
+                }
+                if (kdt_status s = run_kernel(st, KIND_PRESORT, bytes,
+                                              [&] { launch_presort_pass(a, ps == 3, p.presort_tiles, st); }))
                     return s;
             }
         }

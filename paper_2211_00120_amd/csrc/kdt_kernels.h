@@ -37,7 +37,7 @@ struct Outs {
     const uint32_t* perm0;  // per tree: rank in dimension 0 -> local index
     uint32_t* status;       // device status word
     float* box[2];          // split-widest domains of live subtrees, [level & 1][(box_off + i)*8 + (0..3 lo, 4..7 hi)]
-    uint32_t* bbox;         // per tree: scene box as orderable keys [idx*8 + (0..3 min, 4..7 max)]
+    uint32_t* bbox;         // per tree: key summary [idx*KEYSUM_WORDS + ...] (scene box, bits that vary)
 };
 
 struct PrepArgs {
@@ -48,18 +48,23 @@ struct PrepArgs {
     Outs o;
 };
 
+// Pass `pass` (digit 8*pass) of one dimension's presort.  A pass whose
+// digit is the same in every key of a tree (from the key summary) is skipped
+// for that tree; each tree's passes read the output of its last pass that
+// ran (or prep's keys, before any) and write the other (key, index) buffer.
+// The last pass always runs.
 struct PresortArgs {
     Shares sh;              // one share per tree, tiles of PRESORT_TILE points
-    const uint32_t* kin;    // first pass: prep's keys of this dimension (value = local index)
-    const uint32_t* kvin;   // later passes: (key, local index) pairs, interleaved
-    uint32_t* kvout;
+    const uint32_t* kin;    // prep's keys of this dimension (value = local index)
+    uint32_t* kv[2];        // (key, local index) pairs, interleaved
+    const uint32_t* keysum; // per tree key summaries
+    uint32_t pass;
     const uint32_t* hist;   // per tree histograms of this dimension and pass: hist + idx*hist_stride
     uint32_t hist_stride;
     uint32_t* lb;           // look-back words of this pass
     uint32_t* lb_zero;      // look-back words to clear for the next pass
     uint32_t lb_zero_n;
     uint32_t* counter;      // dynamic tile counter of this pass
-    uint32_t shift;
     uint32_t* perm_out;     // last pass: per tree rank -> local index of this dimension
     uint32_t* rank_table;   // last pass: point-major ranks, [(off + i)*k + dim], except each tree's root dimension
     const uint8_t* dimnode; // split-widest: node dims (the root's is tree's first entry); null: root dimension 0
@@ -133,7 +138,7 @@ void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1
                  uint32_t* z3, uint32_t n3, uint32_t* bbox, uint32_t nbox, hipStream_t st);
 void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st);
-void launch_presort_pass(const PresortArgs& a, bool first, bool last, uint32_t tiles, hipStream_t st);
+void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st);
 void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t st);
 void launch_level_part(int k, const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st);

@@ -52,30 +52,37 @@ __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* coun
     zero_range(z2, n2);
     zero_range(z3, n3);
     // per-tree scene boxes as running (min, max) of orderable keys
-    for (uint32_t x = gid; x < nbox * 8u; x += gridDim.x * BLOCK) bbox[x] = (x & 4u) ? 0u : 0xFFFFFFFFu;
+    // per-tree key summaries: running minima and ANDs start all ones, maxima
+    // and ORs all zeros
+    for (uint32_t x = gid; x < nbox * KEYSUM_WORDS; x += gridDim.x * BLOCK) bbox[x] = (x & 4u) ? 0u : 0xFFFFFFFFu;
 }
 
 // --------------------------------------------------------------------- prep
 
-// One tile of one tree: uint32 keys (SoA), non-finite flag, the tree's scene
-// box (as orderable keys) and the 4 digit histograms of every dimension's
-// presort.
+// One tile of one tree: uint32 keys (SoA), non-finite flag, the tree's key
+// summary (scene box for split-widest; the bits that are not the same in
+// every key) and the 4 digit histograms of every dimension's presort.
 template <int K, bool WIDEST>
 __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
 {
     __shared__ uint32_t sh[K * 4 * RADIX];
-    __shared__ uint32_t s_lo[K], s_hi[K];
+    __shared__ uint32_t s_sum[KEYSUM_WORDS];
     for (uint32_t x = threadIdx.x; x < K * 4 * RADIX; x += BLOCK) sh[x] = 0u;
-    if (threadIdx.x < K) { s_lo[threadIdx.x] = 0xFFFFFFFFu; s_hi[threadIdx.x] = 0u; }
+    if (threadIdx.x < KEYSUM_WORDS) s_sum[threadIdx.x] = (threadIdx.x & 4u) ? 0u : 0xFFFFFFFFu;
     __syncthreads();
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, blockIdx.x, st, ti);
     const uint32_t start = (blockIdx.x - st.tile0) * PREP_TILE;
     const uint32_t end = min(start + PREP_TILE, ti.n);
-    uint32_t lo[K], hi[K];
+    uint32_t lo[K], hi[K], kand[K], kor[K];
 #pragma unroll
-    for (int d = 0; d < K; ++d) { lo[d] = 0xFFFFFFFFu; hi[d] = 0u; }
+    for (int d = 0; d < K; ++d) {
+        lo[d] = 0xFFFFFFFFu;
+        hi[d] = 0u;
+        kand[d] = 0xFFFFFFFFu;
+        kor[d] = 0u;
+    }
     bool bad = false;
     for (uint32_t i = start + threadIdx.x; i < end; i += BLOCK) {
         const size_t gi = (size_t)ti.off + i;
@@ -86,25 +93,35 @@ __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
             const uint32_t u = orderable(b);
             a.keys[(size_t)d * a.ntotal + gi] = u;
             if (WIDEST) { lo[d] = min(lo[d], u); hi[d] = max(hi[d], u); }
+            kand[d] &= u;
+            kor[d] |= u;
 #pragma unroll
             for (int p = 0; p < 4; ++p) atomicAdd(&sh[(d * 4 + p) * RADIX + ((u >> (8 * p)) & 0xFFu)], 1u);
         }
     }
     if (__any(bad) && lane_id() == 0) atomicOr(a.o.status, KDT_STATUS_NONFINITE);
-    if (WIDEST) {
 #pragma unroll
-        for (int d = 0; d < K; ++d) {
-            atomicMin(&s_lo[d], lo[d]);
-            atomicMax(&s_hi[d], hi[d]);
+    for (int d = 0; d < K; ++d) {
+        if (WIDEST) {
+            atomicMin(&s_sum[d], lo[d]);
+            atomicMax(&s_sum[4 + d], hi[d]);
         }
+        atomicAnd(&s_sum[8 + d], kand[d]);
+        atomicOr(&s_sum[12 + d], kor[d]);
     }
     __syncthreads();
     uint32_t* hist = a.hist + (size_t)ti.idx * K * 4 * RADIX;
     for (uint32_t x = threadIdx.x; x < K * 4 * RADIX; x += BLOCK)
         if (sh[x]) atomicAdd(&hist[x], sh[x]);
-    if (WIDEST && threadIdx.x < K) {
-        atomicMin(&a.o.bbox[ti.idx * 8 + threadIdx.x], s_lo[threadIdx.x]);
-        atomicMax(&a.o.bbox[ti.idx * 8 + 4 + threadIdx.x], s_hi[threadIdx.x]);
+    if (threadIdx.x < (uint32_t)K) {
+        uint32_t* sum = a.o.bbox + (size_t)ti.idx * KEYSUM_WORDS;
+        const uint32_t d = threadIdx.x;
+        if (WIDEST) {
+            atomicMin(&sum[d], s_sum[d]);
+            atomicMax(&sum[4 + d], s_sum[4 + d]);
+        }
+        atomicAnd(&sum[8 + d], s_sum[8 + d]);
+        atomicOr(&sum[12 + d], s_sum[12 + d]);
     }
 }
 
@@ -119,8 +136,8 @@ __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
     float lo[K], hi[K];
 #pragma unroll
     for (int d = 0; d < K; ++d) {
-        lo[d] = from_orderable(o.bbox[ti.idx * 8 + d]);
-        hi[d] = from_orderable(o.bbox[ti.idx * 8 + 4 + d]);
+        lo[d] = from_orderable(o.bbox[(size_t)ti.idx * KEYSUM_WORDS + d]);
+        hi[d] = from_orderable(o.bbox[(size_t)ti.idx * KEYSUM_WORDS + 4 + d]);
         o.box[0][(size_t)ti.box_off * 8 + d] = lo[d];
         o.box[0][(size_t)ti.box_off * 8 + 4 + d] = hi[d];
     }
@@ -130,11 +147,12 @@ __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
 // ------------------------------------------------------------ presort passes
 
 // One stable LSD digit pass of the (key, index) sort of one dimension, every
-// tree a segment of its own.  FIRST reads the keys of prep and takes the
-// local index as value; LAST writes the sorted indices (rank -> index) and
-// scatters each index's rank into the point-major rank table.  Pairs are
-// stored interleaved (uint2).
-template <bool FIRST, bool LAST>
+// tree a segment of its own.  A tree's first pass that runs reads the keys
+// of prep and takes the local index as value; LAST writes the sorted indices
+// (rank -> index) and scatters each index's rank into the point-major rank
+// table.  Pairs are stored interleaved (uint2).  Passes whose digit is the
+// same in every key of the tree are skipped (see PresortArgs).
+template <bool LAST>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 {
     constexpr int ITEMS = PRESORT_ITEMS;
@@ -148,10 +166,23 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, g, st, ti);
+    // digits of this dimension that are not the same in every key of the tree
+    const uint32_t* sum = a.keysum + (size_t)ti.idx * KEYSUM_WORDS;
+    const uint32_t vary = uniform(sum[8 + a.dim] ^ sum[12 + a.dim]);
+    const uint32_t q = a.pass;
+    if (!LAST && ((vary >> (8u * q)) & 0xFFu) == 0u) {
+        zero_range(a.lb_zero, a.lb_zero_n);
+        return;
+    }
+    uint32_t ran = 0;                       // passes of this tree that ran before this one
+    for (uint32_t qq = 0; qq < q; ++qq) ran += ((vary >> (8u * qq)) & 0xFFu) != 0u;
+    const bool first = ran == 0u;
+    const uint32_t* kvin = a.kv[(ran + 1u) & 1u];
+    uint32_t* kvout = a.kv[ran & 1u];
     const uint32_t start = (g - st.tile0) * T;
     const uint32_t cnt = min(T, ti.n - start);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t shift = a.shift;
+    const uint32_t shift = 8u * q;
     const size_t off = ti.off;
 
     uint4 rec[ITEMS];
@@ -163,11 +194,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         ok[i] = j < cnt;
         rec[i] = make_uint4(0u, 0u, 0u, 0u);
         if (ok[i]) {
-            if (FIRST) {
+            if (first) {
                 rec[i].x = a.kin[off + start + j];
                 rec[i].y = start + j;
             } else {
-                const uint2 kv = reinterpret_cast<const uint2*>(a.kvin)[off + start + j];
+                const uint2 kv = reinterpret_cast<const uint2*>(kvin)[off + start + j];
                 rec[i].x = kv.x;
                 rec[i].y = kv.y;
             }
@@ -187,7 +218,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
                 a.perm_out[off + pos] = r.y;
                 if (to_table) a.rank_table[(off + r.y) * a.k + a.dim] = pos;
             } else {
-                reinterpret_cast<uint2*>(a.kvout)[off + pos] = make_uint2(r.x, r.y);
+                reinterpret_cast<uint2*>(kvout)[off + pos] = make_uint2(r.x, r.y);
             }
         });
     // clear the next pass's look-back words (nothing waits on these stores)
@@ -359,7 +390,7 @@ void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1
     uint32_t big = n1 > n2 ? n1 : n2;
     big = big > n3 ? big : n3;
     big = big > MAX_PASSES ? big : MAX_PASSES;
-    big = big > nbox * 8u ? big : nbox * 8u;
+    big = big > nbox * KEYSUM_WORDS ? big : nbox * KEYSUM_WORDS;
     uint32_t grid = ceil_div(big, BLOCK);
     if (grid > 2048) grid = 2048;
     if (grid == 0) grid = 1;
@@ -394,12 +425,10 @@ void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hi
     }
 }
 
-void launch_presort_pass(const PresortArgs& a, bool first, bool last, uint32_t tiles, hipStream_t st)
+void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st)
 {
-    if (first && last) k_presort_pass<true, true><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-    else if (first) k_presort_pass<true, false><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-    else if (last) k_presort_pass<false, true><<<tiles, SWEEP_THREADS, 0, st>>>(a);
-    else k_presort_pass<false, false><<<tiles, SWEEP_THREADS, 0, st>>>(a);
+    if (last) k_presort_pass<true><<<tiles, SWEEP_THREADS, 0, st>>>(a);
+    else k_presort_pass<false><<<tiles, SWEEP_THREADS, 0, st>>>(a);
 }
 
 template <int K>

@@ -171,7 +171,7 @@ void launch_level_part_k(const LevelPartArgs& a, uint32_t tiles, bool widest, hi
 {
     switch (a.items) {
     case 4: level_part_ki<K, 4>(a, tiles, widest, st); break;
-    default: level_part_ki<K, 8>(a, tiles, widest, st); break;
+    default: level_part_ki<K, PART_ITEMS>(a, tiles, widest, st); break;
     }
 }
 

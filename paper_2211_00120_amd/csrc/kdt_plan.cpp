@@ -19,8 +19,8 @@ namespace {
 // largest tile that the iteration's biggest subtree still fills.
 uint32_t level_items(uint32_t big, uint32_t cap)
 {
-    const uint32_t items = big >= (uint32_t)SWEEP_THREADS * 8u ? 8u : 4u;
-    return items < cap ? items : cap;
+    const uint32_t large = cap >= 8u ? (uint32_t)PART_ITEMS : 4u;
+    return big >= (uint32_t)SWEEP_THREADS * large ? large : 4u;
 }
 
 TreeStep step(uint32_t tree, uint32_t level, uint32_t tile0)
@@ -317,7 +317,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_dimnode = take(N);
     p.o_box[0] = take((size_t)p.box_entries * 8 * 4);
     p.o_box[1] = take((size_t)p.box_entries * 8 * 4);
-    p.o_bbox = take((size_t)p.large.size() * 8 * 4);
+    p.o_bbox = take((size_t)p.large.size() * KEYSUM_WORDS * 4);
     p.o_tables = take(p.tables ? p.blob.size() : 0);
     p.total = o;
     return p;

@@ -15,6 +15,9 @@ constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digits of a rank of at most 30 bit
 constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
 constexpr uint32_t PART_BINS = 4;          // digit values of the split passes (smaller, pivot, larger)
 constexpr uint32_t PREP_TILE = 4096;       // points per workgroup of prep / iteration 0
+// Per-tree key summary words, as orderable keys: [0..3] per-dimension minimum,
+// [4..7] maximum, [8..11] bitwise AND, [12..15] bitwise OR.
+constexpr uint32_t KEYSUM_WORDS = 16;
 
 // Threads of the onesweep workgroups (presort and level passes).
 #ifndef KDT_SWEEP_THREADS
@@ -24,10 +27,15 @@ constexpr int SWEEP_THREADS = KDT_SWEEP_THREADS;
 
 // Tile shapes (items per thread of a SWEEP_THREADS workgroup); tuning knobs.
 #ifndef KDT_PRESORT_ITEMS
-#define KDT_PRESORT_ITEMS 8
+#define KDT_PRESORT_ITEMS 12
 #endif
 constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
 constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
+// Records per thread of the large split tiles (the small ones take 4).
+#ifndef KDT_PART_ITEMS
+#define KDT_PART_ITEMS 8
+#endif
+constexpr int PART_ITEMS = KDT_PART_ITEMS;
 constexpr uint32_t HIST_TILE = 16384;      // keys per workgroup of the pivot selects
 constexpr int TAIL_THREADS = 512;          // subtree tail: 512 threads x 4 slots = up to 2048 points
 constexpr int TAIL_ITEMS = 4;

@@ -144,7 +144,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     for (size_t li = 0; li < p.levels.size(); ++li) {
         const LevelLaunch& ll = p.levels[li];
         const uint32_t l = (uint32_t)li + 1;
-        CHECK(ll.level == l && (ll.items == 4 || ll.items == 8), "level %u", l);
+        CHECK(ll.level == l && (ll.items == 4 || ll.items == (uint32_t)PART_ITEMS), "level %u", l);
         CHECK(ll.sorted == (!widest && l % k == 0), "level %u sorted flag", l);
         if (opt.max_items) CHECK(ll.items <= opt.max_items, "items cap");
         std::vector<std::pair<uint64_t, uint64_t>> hist;
@@ -238,7 +238,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         {p.o_lb[1], (size_t)p.lb_words * 4, "lb1"}, {p.o_keys, N * k * 4, "keys"}, {p.o_perms, N * k * 4, "perms"},
         {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, p.rec_words * 8, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
         {p.o_dimnode, N, "dimnode"}, {p.o_box[0], (size_t)p.box_entries * 32, "box0"},
-        {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * 32, "bbox"},
+        {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * KEYSUM_WORDS * 4, "keysum"},
         {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}};
     size_t end = 0;
     for (const R& r : regs) {

@@ -87,6 +87,29 @@ def test_batched_single_cloud_equals_single_build(mode):
     _assert_cloud(pts, offsets, 0, tree, perm, dim, mode, "one-cloud")
 
 
+def test_batched_constant_digit_passes():
+    """Clouds whose keys leave different presort digits constant (powers of
+    four, 1 + m * 2^-15, a constant coordinate) beside uniform clouds: each
+    cloud skips its own passes and still equals the oracle's build."""
+    r = np.random.default_rng(33)
+    clouds = []
+    for i, n in enumerate([70000, 3000, 150000, 9000, 40000, 2500]):
+        c = r.random((n, 3), dtype=np.float32)
+        if i % 3 == 0:
+            c[:, 0] = np.float32(4.0) ** r.integers(-6, 7, n).astype(np.float32)
+        if i % 3 == 1:
+            c[:, 1] = np.float32(1.0) + r.integers(0, 256, n).astype(np.float32) * np.float32(2.0 ** -15)
+            c[:, 2] = np.float32(-3.5)
+        clouds.append(c)
+    pts, offsets = _concat(clouds)
+    for mode in (kdt.ROUND_ROBIN, kdt.WIDEST):
+        _say(f"case batched-digit-patterns mode={mode}")
+        tree, perm, dim, status = _run_batched(pts, offsets, mode)
+        assert status == kdt.OK
+        for c in range(len(clouds)):
+            _assert_cloud(pts, offsets, c, tree, perm, dim, mode, "digit-patterns")
+
+
 def test_batched_only_small_clouds():
     clouds = [workloads.uniform(n, 3, 50 + n) for n in (1, 5, 64, 700, 2048, 1999, 3)]
     pts, offsets = _concat(clouds)

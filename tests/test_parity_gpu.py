@@ -98,6 +98,27 @@ def test_identical_points(mode):
     _assert_same(pts, mode, "identical")
 
 
+def _digit_pattern_points(n, seed):
+    """Four coordinates whose order-preserving keys differ in chosen bytes
+    only: powers of four (only the top byte varies), 1 + m * 2^-15 (only
+    byte 1 varies), a constant, and uniform values (every byte varies), so
+    that the presort skips different digit passes in each dimension."""
+    r = np.random.default_rng(seed)
+    pts = np.empty((n, 4), np.float32)
+    pts[:, 0] = np.float32(4.0) ** r.integers(-6, 7, n).astype(np.float32)
+    pts[:, 1] = np.float32(1.0) + r.integers(0, 256, n).astype(np.float32) * np.float32(2.0 ** -15)
+    pts[:, 2] = np.float32(0.75)
+    pts[:, 3] = r.random(n, dtype=np.float32)
+    return pts
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_constant_digit_passes(mode):
+    pts = _digit_pattern_points(100003, 31)
+    for cols in ([0, 1, 2, 3], [2, 0, 1], [1, 2]):
+        _assert_same(np.ascontiguousarray(pts[:, cols]), mode, f"digit-pattern-{cols}")
+
+
 def test_k1_widest_and_rr_equal():
     pts = workloads.grid(7777, 1, 5, levels=50)
     _assert_same(pts, kdt.ROUND_ROBIN, "k1-rr")
