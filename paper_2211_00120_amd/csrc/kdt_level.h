@@ -33,7 +33,7 @@ template <int K, bool WIDEST, int ITEMS>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
 {
     constexpr uint32_t T = SWEEP_THREADS * (uint32_t)ITEMS;
-    __shared__ SweepSmem<PART_RB, K> sm;
+    __shared__ SweepSmem<PART_RB, K, false> sm;
     __shared__ uint32_t nh[2 * MAX_BINS];   // top-digit histograms of the two children
     __shared__ uint32_t segc[4];            // the segment's count of each split digit
     __shared__ uint32_t ctl[2];             // the children's split dimensions
@@ -132,20 +132,21 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         return x < p ? 0u : (x == p ? 1u : 2u);
     };
     const uint32_t piv = soff + ls;
-    sweep_tile<PART_RB, ITEMS, K>(
-        sm, rec, ok, dig, ITEMS, cnt, segc, soff, a.lb, g, g - u, a.o.status, digit_of,
-        [&](uint32_t, uint32_t pos, const uint4& r) {
-            if (pos == piv) return;                 // node s, placed above
-            const uint32_t side = pos > piv ? 1u : 0u;
-            const uint32_t nxt = pos - seg - side;  // live position in iteration l+1
-            if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - v.nseg, a.o.status)) return;
-            store_rec4<K>(a.rout, off + nxt, r);
-            if (keys) {
-                const uint32_t kv = pick4(r, ctl[side]);
-                a.kout[off + nxt] = kv;
-                atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
-            }
-        });
+    auto store = [&](uint32_t, uint32_t pos, const uint4& r) {
+        if (pos == piv) return;                 // node s, placed above
+        const uint32_t side = pos > piv ? 1u : 0u;
+        const uint32_t nxt = pos - seg - side;  // live position in iteration l+1
+        if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - v.nseg, a.o.status)) return;
+        store_rec4<K>(a.rout, off + nxt, r);
+        if (keys) {
+            const uint32_t kv = pick4(r, ctl[side]);
+            a.kout[off + nxt] = kv;
+            atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+        }
+    };
+    sweep_tile<PART_RB, ITEMS, K, decltype(digit_of), decltype(store), false>(
+        sm, rec, ok, dig, ITEMS, cnt, segc, soff, a.lb, g, g - u, a.o.status, digit_of, store);
+
     if (keys) {
         // sweep_tile ends with a barrier, so nh is complete; children 2seg
         // and 2seg+1 are segments of iteration l+1

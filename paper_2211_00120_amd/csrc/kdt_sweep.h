@@ -53,7 +53,7 @@ __device__ __forceinline__ uint4 stage_get(const uint4& s) { return s; }
 __device__ __forceinline__ uint4 stage_get(const uint2& s) { return make_uint4(s.x, s.y, 0u, 0u); }
 __device__ __forceinline__ uint4 stage_get(const uint32_t& s) { return make_uint4(s, 0u, 0u, 0u); }
 
-template <int RB, int RW>
+template <int RB, int RW, bool STAGE = true>
 struct SweepSmem {
     static constexpr uint32_t NB = 1u << RB;
     uint16_t wh[SWEEP_WAVES * NB];   // per-wave digit counters, then per-wave exclusive offsets
@@ -61,7 +61,7 @@ struct SweepSmem {
     uint32_t gbase[NB];              // global position of the run minus dstart
     uint32_t sh[2 * SWEEP_WAVES];
     uint32_t tile;
-    typename StageOf<RW>::T stage[SWEEP_STAGE];   // one round of records in sorted tile order
+    typename StageOf<RW>::T stage[STAGE ? SWEEP_STAGE : 1];   // one round of records in sorted tile order
 };
 
 // Exclusive scan of one value per thread over a workgroup of NWV waves
@@ -231,9 +231,12 @@ __device__ __forceinline__ uint32_t lookback_bin(const uint32_t* lb, uint32_t NB
 // counts of the whole segment for this pass; seg_off: segment start; lb:
 // look-back words of this pass, tile g of a segment whose first tile is g0.
 // Calls store(j, pos, r) for every element, j being its tile-local sorted
-// index (consecutive threads get consecutive j) and pos its global position.
-template <int RB, int ITEMS, int RW, class Digit, class Store>
-__device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW>& sm, const uint4 (&rec)[ITEMS], const bool (&ok)[ITEMS],
+// index and pos its global position.  With STAGE (many digit values) the
+// records go out through LDS in sorted order, consecutive threads taking
+// consecutive j; without, each thread stores its own items.  Ends with a
+// barrier.
+template <int RB, int ITEMS, int RW, class Digit, class Store, bool STAGE = true>
+__device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const uint4 (&rec)[ITEMS], const bool (&ok)[ITEMS],
                                            const uint32_t (&dig)[ITEMS], int active, uint32_t cnt,
                                            const uint32_t* __restrict__ seg_hist, uint32_t seg_off, uint32_t* lb,
                                            uint32_t g, uint32_t g0, uint32_t* status, Digit digit_of, Store store)
@@ -293,6 +296,17 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW>& sm, const uint4 (&
     for (int i = 0; i < ITEMS; ++i) {
         dst[i] = 0xFFFFFFFFu;
         if (i < active && ok[i]) dst[i] = sm.dstart[dig[i]] + sm.wh[w * NB + dig[i]] + rnk[i];
+    }
+    if (!STAGE) {
+        // few digit values: each wave's stores of one item already form a
+        // few contiguous runs, so they go out straight from the registers
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i >= active) break;
+            if (ok[i]) store(dst[i], sm.gbase[dig[i]] + dst[i], rec[i]);
+        }
+        __syncthreads();
+        return;
     }
     // write-out in rounds of SWEEP_STAGE sorted positions
     for (uint32_t base = 0; base < cnt; base += SWEEP_STAGE) {
