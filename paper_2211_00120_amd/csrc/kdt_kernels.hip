@@ -62,12 +62,22 @@ __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* coun
 // One tile of one tree: uint32 keys (SoA), non-finite flag, the tree's key
 // summary (scene box for split-widest; the bits that are not the same in
 // every key) and the 4 digit histograms of every dimension's presort.
+#ifndef KDT_PREP_COPIES
+#define KDT_PREP_COPIES 2
+#endif
 template <int K, bool WIDEST>
 __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
 {
-    __shared__ uint32_t sh[K * 4 * RADIX];
+    // digit counters in PREP_COPIES copies, lane-interleaved: the high key
+    // bytes of typical data take few values, and lanes adding to one LDS
+    // word in one instruction are serialised.  A tile counts at most
+    // PREP_TILE < 2^16 keys, so two 16-bit counters share a word.
+    static_assert(PREP_TILE < 65536u, "16-bit digit counters");
+    constexpr uint32_t COPIES = KDT_PREP_COPIES;
+    constexpr uint32_t HW = K * 4 * RADIX;          // counters per copy
+    __shared__ uint32_t sh[COPIES * HW / 2];
     __shared__ uint32_t s_sum[KEYSUM_WORDS];
-    for (uint32_t x = threadIdx.x; x < K * 4 * RADIX; x += BLOCK) sh[x] = 0u;
+    for (uint32_t x = threadIdx.x; x < COPIES * HW / 2; x += BLOCK) sh[x] = 0u;
     if (threadIdx.x < KEYSUM_WORDS) s_sum[threadIdx.x] = (threadIdx.x & 4u) ? 0u : 0xFFFFFFFFu;
     __syncthreads();
     TreeStep st;
@@ -95,8 +105,12 @@ __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
             if (WIDEST) { lo[d] = min(lo[d], u); hi[d] = max(hi[d], u); }
             kand[d] &= u;
             kor[d] |= u;
+            uint32_t* shc = sh + (lane_id() & (COPIES - 1u)) * (HW / 2);
 #pragma unroll
-            for (int p = 0; p < 4; ++p) atomicAdd(&sh[(d * 4 + p) * RADIX + ((u >> (8 * p)) & 0xFFu)], 1u);
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t c = (d * 4 + p) * RADIX + ((u >> (8 * p)) & 0xFFu);
+                atomicAdd(&shc[c >> 1], 1u << (16u * (c & 1u)));
+            }
         }
     }
     if (__any(bad) && lane_id() == 0) atomicOr(a.o.status, KDT_STATUS_NONFINITE);
@@ -111,8 +125,12 @@ __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
     }
     __syncthreads();
     uint32_t* hist = a.hist + (size_t)ti.idx * K * 4 * RADIX;
-    for (uint32_t x = threadIdx.x; x < K * 4 * RADIX; x += BLOCK)
-        if (sh[x]) atomicAdd(&hist[x], sh[x]);
+    for (uint32_t x = threadIdx.x; x < HW; x += BLOCK) {
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t cp = 0; cp < COPIES; ++cp) c += (sh[cp * (HW / 2) + (x >> 1)] >> (16u * (x & 1u))) & 0xFFFFu;
+        if (c) atomicAdd(&hist[x], c);
+    }
     if (threadIdx.x < (uint32_t)K) {
         uint32_t* sum = a.o.bbox + (size_t)ti.idx * KEYSUM_WORDS;
         const uint32_t d = threadIdx.x;

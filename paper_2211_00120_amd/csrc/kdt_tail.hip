@@ -144,6 +144,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     } ub;
     __shared__ uint32_t sh[NW];
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
+    __shared__ uint16_t wl[WIDEST ? C : 1];        // split-widest: the iteration's walk list
+    __shared__ uint32_t lcnt[WIDEST ? K : 1][NW];  // split-widest: walk-list slots per (dimension, wave)
     __shared__ uint8_t ndim[NODES];
     __shared__ float nplane[NODES];
     __shared__ float rootbox[2][8];
@@ -314,28 +316,63 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
         }
         __syncthreads();
         // position of each point inside its segment in the order of the
-        // segment's split dimension
-        // (the loads and the lane matching of a wave's items are independent;
-        // only the counter updates run item by item, in list order)
-        for (uint32_t d = 0; d < (uint32_t)K; ++d) {
-            if (!WIDEST && d != l % (uint32_t)K) continue;
+        // segment's split dimension: a walk over a list in which each
+        // segment's points appear in that order -- ord_d itself for round
+        // robin; for split-widest, the concatenation over d of the slots of
+        // the segments split in d, each part in ord_d order
+        uint32_t M = m;
+        if (WIDEST) {
+            for (uint32_t d = 0; d < (uint32_t)K; ++d) {
+                uint32_t c = 0;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+                    const uint32_t e = p < m ? (uint32_t)ord[d][p] : 0u;
+                    const uint32_t q = p < m ? (uint32_t)seg[e] : DONE;
+                    c += (uint32_t)__popcll(__ballot(q != DONE && segdim[cur][q] == d));
+                }
+                if (lane == 0) lcnt[d][w] = c;
+            }
+            __syncthreads();
+            uint32_t base = 0;
+            M = 0;
+            for (uint32_t d = 0; d < (uint32_t)K; ++d)
+                for (uint32_t ww = 0; ww < (uint32_t)NW; ++ww) M += lcnt[d][ww];
+            for (uint32_t d = 0; d < (uint32_t)K; ++d) {
+                uint32_t b = base;
+                for (uint32_t ww = 0; ww < w; ++ww) b += lcnt[d][ww];
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
+                    const uint32_t e = p < m ? (uint32_t)ord[d][p] : 0u;
+                    const uint32_t q = p < m ? (uint32_t)seg[e] : DONE;
+                    const bool f = q != DONE && segdim[cur][q] == d;
+                    const uint64_t bal = __ballot(f);
+                    if (f) wl[b + count_below(bal)] = (uint16_t)e;
+                    b += (uint32_t)__popcll(bal);
+                }
+                for (uint32_t ww = 0; ww < (uint32_t)NW; ++ww) base += lcnt[d][ww];
+            }
+            __syncthreads();
+        }
+        {
+            const uint32_t d = l % (uint32_t)K;     // round robin's split dimension
             uint32_t e[ITEMS], q[ITEMS];
             bool valid[ITEMS];
             uint64_t peers[ITEMS];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                e[i] = p < m ? (uint32_t)ord[d][p] : 0u;
+                e[i] = p < M ? (uint32_t)(WIDEST ? wl[p] : ord[d][p]) : 0u;
             }
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                q[i] = p < m ? (uint32_t)seg[e[i]] : DONE;
+                q[i] = p < M ? (uint32_t)seg[e[i]] : DONE;
             }
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 valid[i] = q[i] != DONE;
-                if (WIDEST && valid[i]) valid[i] = segdim[cur][q[i]] == d;
                 peers[i] = __ballot(valid[i]);
             }
             for (uint32_t b = 0; b < gbits; ++b) {
@@ -382,31 +419,12 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
                 const uint32_t sn = vl.Fl + gq;
                 place_pt<K, WIDEST>(o, ti, sn, idx[i], pc[i]);
                 if (WIDEST) {
+                    // the node's dimension and plane; its children follow
+                    // below, one thread per segment
                     const uint32_t ds = segdim[cur][q];
-                    const float plane = pickf(pc[i], ds);
                     const uint32_t nidx = gc * ((1u << t) - 1u) + q;
                     ndim[nidx] = (uint8_t)ds;
-                    nplane[nidx] = plane;
-                    float lo[K], hi[K];
-                    local_box<K>(t, q, gc, rootbox, ndim, nplane, lo, hi);
-#pragma unroll
-                    for (uint32_t c = 0; c < 2u; ++c) {
-                        const uint32_t child = 2u * sn + 1u + c;
-                        if (child >= ti.n) continue;
-                        float l2[K], h2[K];
-#pragma unroll
-                        for (int dd = 0; dd < K; ++dd) {
-                            l2[dd] = lo[dd];
-                            h2[dd] = hi[dd];
-                            if ((uint32_t)dd == ds) {
-                                if (c == 0u) h2[dd] = fminf(hi[dd], plane);
-                                else l2[dd] = fmaxf(lo[dd], plane);
-                            }
-                        }
-                        const uint32_t cd = widest_dim<K>(l2, h2);
-                        o.dimnode[off + child] = (uint8_t)cd;
-                        if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
-                    }
+                    nplane[nidx] = pickf(pc[i], ds);
                 }
                 seg[e] = (uint16_t)DONE;
             } else {
@@ -420,6 +438,38 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             }
         }
         __syncthreads();
+        if (WIDEST) {
+            // each segment's children: domain = the segment's domain (root
+            // box clipped by its ancestors' planes) clipped by its own plane
+            for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) {
+                const uint32_t gq = (i0 << t) + q;
+                const uint32_t sn = vl.Fl + gq;
+                const uint32_t nidx = gc * ((1u << t) - 1u) + q;
+                const uint32_t ds = ndim[nidx];
+                const float plane = nplane[nidx];
+                float lo[K], hi[K];
+                local_box<K>(t, q, gc, rootbox, ndim, nplane, lo, hi);
+#pragma unroll
+                for (uint32_t c = 0; c < 2u; ++c) {
+                    const uint32_t child = 2u * sn + 1u + c;
+                    if (child >= ti.n) continue;
+                    float l2[K], h2[K];
+#pragma unroll
+                    for (int dd = 0; dd < K; ++dd) {
+                        l2[dd] = lo[dd];
+                        h2[dd] = hi[dd];
+                        if ((uint32_t)dd == ds) {
+                            if (c == 0u) h2[dd] = fminf(hi[dd], plane);
+                            else l2[dd] = fmaxf(lo[dd], plane);
+                        }
+                    }
+                    const uint32_t cd = widest_dim<K>(l2, h2);
+                    o.dimnode[off + child] = (uint8_t)cd;
+                    if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
+                }
+            }
+            // the next iteration reads segdim after its first barrier
+        }
         cur ^= 1u;
     }
 }
