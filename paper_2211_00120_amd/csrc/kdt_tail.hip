@@ -322,37 +322,41 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
         // the segments split in d, each part in ord_d order
         uint32_t M = m;
         if (WIDEST) {
-            for (uint32_t d = 0; d < (uint32_t)K; ++d) {
+            // one read of every (dimension, slot), kept for the write-out
+            uint32_t le[K][ITEMS];
+            uint64_t lb[K][ITEMS];
+#pragma unroll
+            for (int d = 0; d < K; ++d) {
                 uint32_t c = 0;
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
                     const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
                     const uint32_t e = p < m ? (uint32_t)ord[d][p] : 0u;
                     const uint32_t q = p < m ? (uint32_t)seg[e] : DONE;
-                    c += (uint32_t)__popcll(__ballot(q != DONE && segdim[cur][q] == d));
+                    le[d][i] = e;
+                    lb[d][i] = __ballot(q != DONE && segdim[cur][q] == (uint32_t)d);
+                    c += (uint32_t)__popcll(lb[d][i]);
                 }
                 if (lane == 0) lcnt[d][w] = c;
             }
             __syncthreads();
             uint32_t base = 0;
-            M = 0;
-            for (uint32_t d = 0; d < (uint32_t)K; ++d)
-                for (uint32_t ww = 0; ww < (uint32_t)NW; ++ww) M += lcnt[d][ww];
-            for (uint32_t d = 0; d < (uint32_t)K; ++d) {
+#pragma unroll
+            for (int d = 0; d < K; ++d) {
                 uint32_t b = base;
-                for (uint32_t ww = 0; ww < w; ++ww) b += lcnt[d][ww];
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    const uint32_t c = lcnt[d][ww];
+                    b += (uint32_t)ww < w ? c : 0u;
+                    base += c;
+                }
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
-                    const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                    const uint32_t e = p < m ? (uint32_t)ord[d][p] : 0u;
-                    const uint32_t q = p < m ? (uint32_t)seg[e] : DONE;
-                    const bool f = q != DONE && segdim[cur][q] == d;
-                    const uint64_t bal = __ballot(f);
-                    if (f) wl[b + count_below(bal)] = (uint16_t)e;
-                    b += (uint32_t)__popcll(bal);
+                    if ((lb[d][i] >> lane) & 1u) wl[b + count_below(lb[d][i])] = (uint16_t)le[d][i];
+                    b += (uint32_t)__popcll(lb[d][i]);
                 }
-                for (uint32_t ww = 0; ww < (uint32_t)NW; ++ww) base += lcnt[d][ww];
             }
+            M = base;
             __syncthreads();
         }
         {
