@@ -121,6 +121,113 @@ __device__ __forceinline__ void tail_sort_pass(uint64_t (&it)[ITEMS], const bool
     __syncthreads();
 }
 
+// Bucket sort of one dimension's keys of the group, for keys spread over
+// their range (ranks of a subtree's points are): bucket = (key - min) >>
+// shift, with at most TB_BUCKETS buckets; a key's slot inside its bucket
+// comes from an LDS atomic, and its place inside the bucket from counting
+// the bucket's smaller keys (equal keys by slot, i.e. input order).  Gives
+// up, leaving ord untouched, when a bucket holds more than TB_FILL keys.
+// All threads call it; it starts and ends with a barrier.
+constexpr uint32_t TB_BITS = 11;
+constexpr uint32_t TB_BUCKETS = 1u << TB_BITS;
+constexpr uint32_t TB_FILL = 32;
+
+template <int ITEMS>
+__device__ __forceinline__ bool tail_bucket_sort(const uint32_t (&key)[ITEMS], const bool (&ok)[ITEMS],
+                                                 uint16_t* ordd, uint32_t* bc, uint32_t* tk, uint16_t* ts,
+                                                 uint32_t* red, uint32_t* sh)
+{
+    constexpr int NW = TAIL_THREADS / 64;
+    constexpr uint32_t CW = 64u * ITEMS;
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (!ok[i]) continue;
+        lo = min(lo, key[i]);
+        hi = max(hi, key[i]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        red[0] = 0xFFFFFFFFu;
+        red[1] = 0u;
+        red[2] = 0u;
+    }
+    for (uint32_t x = threadIdx.x; x <= TB_BUCKETS; x += TAIL_THREADS) bc[x] = 0u;
+    __syncthreads();
+    if (lane == 0) {
+        atomicMin(&red[0], lo);
+        atomicMax(&red[1], hi);
+    }
+    __syncthreads();
+    const uint32_t kmin = red[0];
+    const uint32_t range = red[1] - kmin;
+    const uint32_t rbits = range ? 32u - (uint32_t)__builtin_clz(range) : 0u;
+    const uint32_t shift = rbits > TB_BITS ? rbits - TB_BITS : 0u;
+    uint32_t b[ITEMS], at[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        b[i] = ok[i] ? (key[i] - kmin) >> shift : 0u;
+        at[i] = ok[i] ? atomicAdd(&bc[b[i]], 1u) : 0u;
+    }
+    __syncthreads();
+    // bucket starts (exclusive scan, 4 buckets per thread) and the fullest bucket
+    constexpr uint32_t BPT = TB_BUCKETS / TAIL_THREADS;
+    const uint32_t t0 = threadIdx.x * BPT;
+    uint32_t c[BPT];
+    uint32_t sum = 0, mx = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < BPT; ++j) {
+        c[j] = bc[t0 + j];
+        sum += c[j];
+        mx = max(mx, c[j]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if (lane == 0) atomicMax(&red[2], mx);
+    const uint32_t ex = sweep_excl_scan<NW>(sum, sh);
+    uint32_t run = ex;
+#pragma unroll
+    for (uint32_t j = 0; j < BPT; ++j) {
+        bc[t0 + j] = run;
+        run += c[j];
+    }
+    if (threadIdx.x == TAIL_THREADS - 1) bc[TB_BUCKETS] = run;
+    __syncthreads();
+    if (red[2] > TB_FILL) {
+        __syncthreads();
+        return false;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+        if (!ok[i]) continue;
+        const uint32_t j = bc[b[i]] + at[i];
+        tk[j] = key[i];
+        ts[j] = (uint16_t)e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+        if (!ok[i]) continue;
+        const uint32_t st = bc[b[i]], en = bc[b[i] + 1u];
+        uint32_t r = 0;
+        for (uint32_t j = st; j < en; ++j) {
+            const uint32_t k2 = tk[j];
+            r += (k2 < key[i] || (k2 == key[i] && (uint32_t)ts[j] < e)) ? 1u : 0u;
+        }
+        ordd[st + r] = (uint16_t)e;
+    }
+    __syncthreads();
+    return true;
+}
+
 template <int K, bool WIDEST>
 __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 {
@@ -140,9 +247,15 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             uint16_t wh[NW * TAIL_SORT_BINS];      // per-wave digit counters
             uint32_t dstart[TAIL_SORT_BINS];
         } sort;
+        struct {
+            uint32_t bc[TB_BUCKETS + 1];           // bucket counts, then starts
+            uint32_t tk[C];                        // keys in bucket order
+            uint16_t ts[C];                        // their slots
+        } bsort;
         uint16_t cnt[NW][C];                       // per-(wave, segment) counters of an iteration
     } ub;
     __shared__ uint32_t sh[NW];
+    __shared__ uint32_t red[4];
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
     __shared__ uint16_t wl[WIDEST ? C : 1];        // split-widest: the iteration's walk list
     __shared__ uint32_t lcnt[WIDEST ? K : 1][NW];  // split-widest: walk-list slots per (dimension, wave)
@@ -203,9 +316,9 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
         }
     } else {
-        // the records, then each slot's index (rank 0 -> index) and point: the
-        // loads of each kind go out together, and the gathers complete while
-        // the group sorts
+        // the records, then each slot's index (rank 0 -> index): the loads of
+        // each kind go out together, and the index gathers complete while the
+        // group sorts (the points follow after the sorts)
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
@@ -216,20 +329,11 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
             seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
         }
-        bool oob = false;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const bool in = rec[i].x < ti.n;
-            oob |= ok[i] && !in;
-            idx[i] = (ok[i] && in) ? o.perm0[off + rec[i].x] : 0u;
+            idx[i] = (ok[i] && in) ? o.perm0[off + rec[i].x] : 0xFFFFFFFFu;
         }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const bool in = idx[i] < ti.n;
-            oob |= ok[i] && !in;
-            pc[i] = (ok[i] && in) ? load_point<K>(o.pts, off + idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        if (__any(oob) && lane == 0) atomicOr(o.status, KDT_STATUS_INTERNAL);
     }
     if (FP) {
         if (__any(bad) && lane == 0) atomicOr(o.status, KDT_STATUS_NONFINITE);
@@ -278,19 +382,24 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     if (!FP) free_dim = WIDEST ? (uint32_t)o.dimnode[off] : 0u;
     __syncthreads();
 
-    // ---- ord_d: the group sorted by rank_d (stable LSD radix in LDS) ----
-    // fewest passes over the B key bits with digits of at most 9 bits
+    // ---- ord_d: the group sorted by rank_d: bucket sort, or where the keys
+    // bunch, stable LSD radix in LDS with the fewest passes over the B key
+    // bits (digits of at most 9 bits) ----
     const uint32_t nsb = ((B + 7u) / 8u == (B + 8u) / 9u) ? 8u : 9u;
     for (uint32_t d = 0; d < (uint32_t)K; ++d) {
         if (d == free_dim) {
             for (uint32_t p = threadIdx.x; p < m; p += TAIL_THREADS) ord[d][p] = (uint16_t)p;
             continue;
         }
+        uint32_t key[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) key[i] = pick4(rec[i], d);
+        if (tail_bucket_sort<ITEMS>(key, ok, ord[d], ub.bsort.bc, ub.bsort.tk, ub.bsort.ts, red, sh)) continue;
         uint64_t it[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-            it[i] = ((uint64_t)pick4(rec[i], d) << 12) | e;
+            it[i] = ((uint64_t)key[i] << 12) | e;
         }
         for (uint32_t sft = 12; sft < 12 + B; sft += nsb)
             tail_sort_pass<ITEMS>(it, ok, sft, (1u << nsb) - 1u, ub.sort.x, ub.sort.wh, ub.sort.dstart, sh);
@@ -301,6 +410,20 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
         }
     }
     __syncthreads();
+
+    if (!FP) {
+        // the points of the slots (an index out of range -- a corrupt input
+        // record -- is flagged and its slot reads point 0)
+        bool oob = false;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const bool in = idx[i] < ti.n;
+            oob |= ok[i] && !in;
+            if (!in) idx[i] = 0u;
+            pc[i] = ok[i] ? load_point<K>(o.pts, off + idx[i]) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (__any(oob) && lane == 0) atomicOr(o.status, KDT_STATUS_INTERNAL);
+    }
 
     // ---- iterations l0 .. L-2 ----
     uint32_t cur = 0;
