@@ -8,7 +8,8 @@
 //     iteration in LDS);
 //   * larger trees go through init, prep, [root dims], k presorts x 4
 //     passes, iteration 0, then iterations 1.. while some subtree is larger
-//     than TAIL_CAP (each: radix select of every subtree's pivot key, then
+//     than TAIL_CAP (each: radix select of every subtree's pivot key, the
+//     pivot kernel that reads it off the histograms and places the node, then
 //     one segmented onesweep split pass that applies the tag update), then
 //     one tail launch that runs each tree's remaining iterations, each tree
 //     from its own level.
@@ -82,11 +83,11 @@ kdt_status check_launch(const char* what)
 // While enabled, every kernel enqueued by a build is bracketed by two
 // hipEvents on the build's stream and tagged with its kind and algorithmic
 // bytes (the bytes the step must move by definition).
-enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PART, KIND_TAIL,
-            KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_COUNT };
+enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
+            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
-                                            "k_level0", "k_level_select", "k_level_part", "k_tail",
-                                            "k_tail_whole", "share_tables", "k_word"};
+                                            "k_level0", "k_level_select", "k_level_pivot", "k_level_part",
+                                            "k_tail", "k_tail_whole", "share_tables", "k_word"};
 
 struct ProfRec {
     int kind;
@@ -213,6 +214,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     uint32_t* perms = (uint32_t*)(ws + p.o_perms);
     uint32_t* ranks = (uint32_t*)(ws + p.o_ranks);
     uint32_t* recbase = (uint32_t*)(ws + p.o_rec);
+    uint32_t* piv = (uint32_t*)(ws + p.o_piv);
     uint32_t* rec[2] = {recbase, recbase + p.rec_words};
     const uint32_t ntotal = (uint32_t)p.ntotal;
     const uint32_t nlarge_trees = (uint32_t)p.large.size();
@@ -382,6 +384,26 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                         return s;
                 }
             }
+            {
+                LevelPivotArgs pa{};
+                pa.sh = shares(p, ll.psteps, p.t_pivot[li], ws);
+                pa.rin = rec[cur];
+                pa.hist = hist;
+                pa.piv = piv;
+                pa.perms = perms;
+                pa.ntotal = ntotal;
+                pa.passes = p.P;
+                pa.radix_bits = p.RB;
+                pa.sorted = ll.sorted ? 1u : 0u;
+                pa.k = k;
+                pa.o = o;
+                double segs = 0;
+                for (const TreeStep& s : ll.psteps) segs += make_level(p.trees[s.tree].n, l).nseg;
+                const double per_seg = ll.sorted ? 4.0 * K : 4.0 * p.P * (1u << p.RB);
+                if (kdt_status s = run_kernel(st, KIND_PIVOT, segs * per_seg,
+                                              [&] { launch_level_pivot((int)k, pa, ll.pivot_tiles, widest, st); }))
+                    return s;
+            }
             const bool keys_next = li + 1 < p.levels.size() && !p.levels[li + 1].sorted;
             const uint32_t zero_words = li + 2 < p.levels.size() ? p.levels[li + 2].hist_words : 0u;
             LevelPartArgs a{};
@@ -390,12 +412,10 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             a.rout = rec[cur ^ 1];
             a.kout = skey[l & 1u];
             a.hist = hist;
-            a.perms = perms;
-            a.ntotal = ntotal;
+            a.piv = piv;
             a.passes = p.P;
             a.radix_bits = p.RB;
             a.items = ll.items;
-            a.sorted = ll.sorted ? 1u : 0u;
             a.keys_next = keys_next ? 1u : 0u;
             a.lb = lb[q & 1];
             a.lb_zero = lb[(q + 1) & 1];

@@ -23,23 +23,8 @@ __device__ __forceinline__ bool in_bounds(uint32_t pos, uint32_t limit, uint32_t
 // The share that tile (or workgroup) g belongs to; g is the same in every
 // lane.  The result is made wave-uniform field by field, so that it and all
 // the segment arithmetic derived from it live in scalar registers.
-__device__ __forceinline__ void find_share(const Shares& sh, uint32_t g, TreeStep& st, TreeInfo& ti)
+__device__ __forceinline__ void uniform_step(TreeStep& st, const TreeStep& s)
 {
-    TreeStep s;
-    TreeInfo t;
-    if (sh.steps == nullptr) {
-        s = sh.step0;
-        t = sh.tree0;
-    } else {
-        uint32_t lo = 0, hi = sh.nsteps - 1u;
-        while (lo < hi) {                   // largest i with steps[i].tile0 <= g
-            const uint32_t mid = (lo + hi + 1u) >> 1;
-            if (sh.steps[mid].tile0 <= g) lo = mid;
-            else hi = mid - 1u;
-        }
-        s = sh.steps[lo];
-        t = sh.trees[s.tree];
-    }
     st.tree = uniform(s.tree);
     st.level = uniform(s.level);
     st.tile0 = uniform(s.tile0);
@@ -47,10 +32,35 @@ __device__ __forceinline__ void find_share(const Shares& sh, uint32_t g, TreeSte
     st.hist_next = uniform(s.hist_next);
     st.pair0 = uniform(s.pair0);
     st.buf = uniform(s.buf);
+    st.piv = uniform(s.piv);
+}
+
+__device__ __forceinline__ void uniform_tree(TreeInfo& ti, const TreeInfo& t)
+{
     ti.off = uniform(t.off);
     ti.n = uniform(t.n);
     ti.box_off = uniform(t.box_off);
     ti.idx = uniform(t.idx);
+}
+
+// (fields are read one by one in each branch: a copy of the whole struct
+// through a select between the kernel argument and the table can leave a
+// private-memory frame behind)
+__device__ __forceinline__ void find_share(const Shares& sh, uint32_t g, TreeStep& st, TreeInfo& ti)
+{
+    if (sh.steps == nullptr) {
+        uniform_step(st, sh.step0);
+        uniform_tree(ti, sh.tree0);
+        return;
+    }
+    uint32_t lo = 0, hi = sh.nsteps - 1u;
+    while (lo < hi) {                   // largest i with steps[i].tile0 <= g
+        const uint32_t mid = (lo + hi + 1u) >> 1;
+        if (sh.steps[mid].tile0 <= g) lo = mid;
+        else hi = mid - 1u;
+    }
+    uniform_step(st, sh.steps[lo]);
+    uniform_tree(ti, sh.trees[st.tree]);
 }
 
 // Node `node` of tree ti holds its point of local index idx.

@@ -100,6 +100,24 @@ struct LevelSelectArgs {
     uint32_t* status;
 };
 
+// The pivot of every subtree of iteration l, one wave per subtree: its key
+// (from the digit histograms, or, when `sorted`, the key at its position),
+// its node's point (placed here) and, for split-widest, its children's
+// dimensions and domains.  Writes piv[share.piv + 2*seg] = key and
+// piv[share.piv + 2*seg + 1] = child dimensions (left | right << 8).
+struct LevelPivotArgs {
+    Shares sh;              // shares of one iteration, workgroups of PIVOT_SEGS subtrees
+    const uint32_t* rin;    // records (read when `sorted`)
+    const uint32_t* hist;   // histogram region; share.hist word offsets
+    uint32_t* piv;
+    const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
+    uint32_t ntotal;
+    uint32_t passes, radix_bits;
+    uint32_t sorted;
+    uint32_t k;
+    Outs o;
+};
+
 // The update of iteration l: a stable three-way split of every subtree's
 // segment around its pivot (smaller key, the pivot, larger key), which is
 // the sorted order of Sec. 3.1 restricted to what the tag update reads.
@@ -108,12 +126,10 @@ struct LevelPartArgs {
     const uint32_t* rin;
     uint32_t* rout;         // next iteration's records
     uint32_t* kout;         // next iteration's split keys (keys_next)
-    uint32_t* hist;         // histogram region; share.hist / share.hist_next are word offsets in it
-    const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
-    uint32_t ntotal;
+    uint32_t* hist;         // histogram region; share.hist_next word offsets (next iteration's top digit)
+    const uint32_t* piv;    // pivot entries of this iteration (LevelPivotArgs)
     uint32_t passes, radix_bits;
     uint32_t items;         // records per thread in this launch's tiles (tile = SWEEP_THREADS * items)
-    uint32_t sorted;        // every segment is in split-key order (the pivot is at its left size)
     uint32_t keys_next;     // write the next iteration's split keys and top-digit histograms
     uint32_t* lb;
     uint32_t* lb_zero;
@@ -141,6 +157,7 @@ void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hi
 void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st);
 void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t st);
+void launch_level_pivot(int k, const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_level_part(int k, const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_tail(int k, const TailArgs& a, uint32_t groups, bool widest, hipStream_t st);
 

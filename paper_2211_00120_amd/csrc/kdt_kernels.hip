@@ -472,6 +472,19 @@ void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t s
 }
 
 template <int K>
+void launch_level_pivot_k(const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st);
+
+void launch_level_pivot(int k, const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st)
+{
+    switch (k) {
+    case 1: launch_level_pivot_k<1>(a, tiles, widest, st); break;
+    case 2: launch_level_pivot_k<2>(a, tiles, widest, st); break;
+    case 3: launch_level_pivot_k<3>(a, tiles, widest, st); break;
+    default: launch_level_pivot_k<4>(a, tiles, widest, st); break;
+    }
+}
+
+template <int K>
 void launch_level_part_k(const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 
 void launch_level_part(int k, const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st)

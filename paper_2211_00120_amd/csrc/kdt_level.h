@@ -9,10 +9,11 @@
 // comparison per point, and a stable split by it leaves the two children in
 // their parent's order -- so every segment keeps the order of iteration 0,
 // the root dimension's sorted order.  The pivot's key is the key of rank
-// ss(2s+1) in the segment; k_level_select finds it digit by digit from
-// per-segment digit histograms (radix select), and where the segment is
-// already in split-key order (round robin, split dimension = the root's),
-// it is simply the key at that position.
+// ss(2s+1) in the segment; k_level_select counts it digit by digit into
+// per-segment digit histograms (radix select) and k_level_pivot reads it off
+// them, one wave per segment -- or, where the segment is already in
+// split-key order (round robin, split dimension = the root's), takes the key
+// at that position.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,6 +30,52 @@ namespace kdt {
 // Digit of the split pass: 0 smaller key, 1 the pivot, 2 larger key.
 constexpr int PART_RB = 2;
 
+template <int K, bool WIDEST>
+__global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs a)
+{
+    TreeStep st;
+    TreeInfo ti;
+    find_share(a.sh, blockIdx.x, st, ti);
+    const Level v = make_level(ti.n, st.level);
+    const uint32_t seg = (blockIdx.x - st.tile0) * PIVOT_SEGS + (threadIdx.x >> 6);
+    if (seg >= v.nseg) return;
+    const size_t off = ti.off;
+    const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[off + v.Fl + seg] : st.level % a.k;
+    const uint32_t ls = seg_left_size(v, seg);
+    const uint32_t s = v.Fl + seg;
+    uint32_t p = 0;
+    if (a.sorted) {
+        // the pivot's position: segment start from the segment-size
+        // arithmetic the split pass uses (the equivalent seg_offset form,
+        // next to seg_left_size in this kernel, lost its min() to the
+        // optimiser)
+        const uint32_t pos = tiles_seg_offset(tiles_level(v, 1u), seg) + ls;
+        p = pick4(load_rec4<K>(a.rin, off + pos), d);
+    } else {
+        const uint32_t RBv = a.radix_bits;
+        const uint32_t NB = 1u << RBv;
+        const uint32_t* h = a.hist + st.hist + (size_t)seg * a.passes * NB;
+        uint32_t kk = ls;
+        for (int jj = (int)a.passes - 1; jj >= 0; --jj)
+            p = (p << RBv) | wave_find_bucket(h + (size_t)jj * NB, NB, kk, a.o.status);
+    }
+    if (lane_id() != 0) return;
+    uint32_t idx = 0;
+    if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
+    if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
+    place<K, WIDEST>(a.o, ti, s, idx);
+    uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;
+    if (WIDEST) {
+        const float plane = a.o.pts[(off + idx) * K + d];
+        const float* bc = a.o.box[st.level & 1u] + ((size_t)ti.box_off + seg) * 8;
+        c0 = child_dim<K>(bc, plane, d, 0u);
+        c1 = child_dim<K>(bc, plane, d, 1u);
+        widest_children<K>(a.o, ti, s, seg, plane, d, a.o.box[st.level & 1u], a.o.box[(st.level + 1u) & 1u]);
+    }
+    a.piv[st.piv + 2u * seg] = p;
+    a.piv[st.piv + 2u * seg + 1u] = c0 | (c1 << 8);
+}
+
 template <int K, bool WIDEST, int ITEMS>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
 {
@@ -36,8 +83,6 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
     __shared__ SweepSmem<PART_RB, K, false> sm;
     __shared__ uint32_t nh[2 * MAX_BINS];   // top-digit histograms of the two children
     __shared__ uint32_t segc[4];            // the segment's count of each split digit
-    __shared__ uint32_t ctl[2];             // the children's split dimensions
-    __shared__ uint32_t sel[2];
 
     if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
     __syncthreads();
@@ -62,13 +107,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
     const uint32_t P = a.passes;
     const uint32_t top = RBv * (P - 1u);
     const uint32_t ls = seg_left_size(v, seg);        // ss(2s+1): rank of the pivot in the segment
-    const uint32_t s = v.Fl + seg;
     const bool keys = a.keys_next != 0u && st.hist_next != 0xFFFFFFFFu;
     if (keys) {
         for (uint32_t x = threadIdx.x; x < 2u * NB; x += SWEEP_THREADS) nh[x] = 0u;
     }
 
-    // the tile's records first, so that their loads overlap the pivot search
+    // the tile's records
     uint4 rec[ITEMS];
     bool ok[ITEMS];
 #pragma unroll
@@ -78,43 +122,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         rec[i] = ok[i] ? load_rec4<K>(a.rin, off + soff + start + j) : make_uint4(0u, 0u, 0u, 0u);
     }
 
-    // the pivot's key (its rank in dimension d)
-    uint32_t p = 0;
-    if (a.sorted) {
-        p = pick4(load_rec4<K>(a.rin, off + soff + ls), d);
-    } else {
-        const uint32_t* h = a.hist + st.hist + (size_t)seg * P * NB;
-        uint32_t c[MAX_LEVEL_PASSES][FIND_BPT];
-#pragma unroll
-        for (uint32_t jj = 0; jj < MAX_LEVEL_PASSES; ++jj)
-            if (jj < P) load_bins(h + (size_t)jj * NB, NB, c[jj]);
-        uint32_t kk = ls;
-#pragma unroll
-        for (int jj = (int)MAX_LEVEL_PASSES - 1; jj >= 0; --jj)
-            if ((uint32_t)jj < P) p = (p << RBv) | find_bucket(c[jj], NB, kk, sm.sh, sel, a.o.status);
-    }
-    p = uniform(p);
-    // the pivot's point fixes node s (the segment's first tile places it)
-    // and, for split-widest, the children's dimensions; sweep_tile's
-    // barriers publish ctl and segc before they are read
+    // the pivot's key and the children's dimensions (k_level_pivot)
+    const uint32_t p = uniform(a.piv[st.piv + 2u * seg]);
+    const uint32_t cdw = uniform(a.piv[st.piv + 2u * seg + 1u]);
+    const uint32_t cd0 = cdw & 0xFFu, cd1 = cdw >> 8;
     if (threadIdx.x == 0) {
-        uint32_t idx = 0;
-        if (WIDEST || u == 0) {
-            if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
-            if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
-        }
-        uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;
-        if (WIDEST) {
-            const float plane = a.o.pts[(off + idx) * K + d];
-            const float* bc = a.o.box[st.level & 1u] + ((size_t)ti.box_off + seg) * 8;
-            c0 = child_dim<K>(bc, plane, d, 0u);
-            c1 = child_dim<K>(bc, plane, d, 1u);
-            if (u == 0) widest_children<K>(a.o, ti, s, seg, plane, d, a.o.box[st.level & 1u],
-                                           a.o.box[(st.level + 1u) & 1u]);
-        }
-        if (u == 0) place<K, WIDEST>(a.o, ti, s, idx);
-        ctl[0] = c0;
-        ctl[1] = c1;
+        // sweep_tile's barriers publish these before they are read
         segc[0] = ls;
         segc[1] = 1u;
         segc[2] = ssz - ls - 1u;
@@ -139,7 +152,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - v.nseg, a.o.status)) return;
         store_rec4<K>(a.rout, off + nxt, r);
         if (keys) {
-            const uint32_t kv = pick4(r, ctl[side]);
+            const uint32_t kv = K == 1 ? r.x : (side ? pick4(r, cd1) : pick4(r, cd0));
             a.kout[off + nxt] = kv;
             atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
         }
@@ -158,6 +171,13 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
     }
     zero_range(a.lb_zero, a.lb_zero_n);
     zero_range(a.zero2, a.zero2_n);
+}
+
+template <int K>
+void launch_level_pivot_k(const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st)
+{
+    if (widest) k_level_pivot<K, true><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
+    else k_level_pivot<K, false><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
 }
 
 template <int K, int ITEMS>

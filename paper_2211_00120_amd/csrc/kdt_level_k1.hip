@@ -3,5 +3,6 @@
 #include "kdt_level.h"
 
 namespace kdt {
+template void launch_level_pivot_k<1>(const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 template void launch_level_part_k<1>(const LevelPartArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 }  // namespace kdt

@@ -33,6 +33,7 @@ TreeStep step(uint32_t tree, uint32_t level, uint32_t tile0)
     s.hist_next = NO_HIST;
     s.pair0 = 0;
     s.buf = 0;
+    s.piv = 0;
     return s;
 }
 
@@ -226,12 +227,18 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
             const Level v = make_level(n[t], l);
             TreeStep s = step(t, l, ll.tiles);
             s.hist = ll.hist_words;
+            s.piv = ll.piv_words;
             ll.tiles += tiles_level(v, (uint32_t)SWEEP_THREADS * ll.items).tiles;
             ll.hist_words += v.nseg * p.P * NB;
             ll.steps.push_back(s);
             TreeStep h = step(t, l, ll.select_tiles);
             ll.select_tiles += tiles_level(v, HIST_TILE).tiles;
             ll.ssteps.push_back(h);
+            TreeStep pv = step(t, l, ll.pivot_tiles);
+            pv.piv = ll.piv_words;
+            ll.pivot_tiles += ceil_div(v.nseg, PIVOT_SEGS);
+            ll.piv_words += 2u * v.nseg;
+            ll.psteps.push_back(pv);
         }
         p.hist_words = std::max(p.hist_words, ll.hist_words);
         p.levels.push_back(std::move(ll));
@@ -242,7 +249,9 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         for (size_t i = 0; i < ll.steps.size(); ++i) {
             ll.steps[i].hist += base;
             ll.ssteps[i].hist = ll.steps[i].hist;
+            ll.psteps[i].hist = ll.steps[i].hist;
         }
+        p.piv_words = std::max(p.piv_words, ll.piv_words);
     }
     // each share's histogram offset for the next iteration
     auto next_hist = [&](size_t li, uint32_t tree) {
@@ -292,6 +301,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     for (const LevelLaunch& ll : p.levels) {
         p.t_level.push_back(push_table(p.blob, ll.steps.data(), ll.steps.size() * sizeof(TreeStep)));
         p.t_select.push_back(push_table(p.blob, ll.ssteps.data(), ll.ssteps.size() * sizeof(TreeStep)));
+        p.t_pivot.push_back(push_table(p.blob, ll.psteps.data(), ll.psteps.size() * sizeof(TreeStep)));
     }
 
     // workspace
@@ -318,6 +328,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_box[0] = take((size_t)p.box_entries * 8 * 4);
     p.o_box[1] = take((size_t)p.box_entries * 8 * 4);
     p.o_bbox = take((size_t)p.large.size() * KEYSUM_WORDS * 4);
+    p.o_piv = take((size_t)p.piv_words * 4);
     p.o_tables = take(p.tables ? p.blob.size() : 0);
     p.total = o;
     return p;

@@ -28,17 +28,20 @@ struct PlanOptions {
 };
 
 // One iteration run as digit passes over every tree that still has subtrees
-// larger than TAIL_CAP: P-1 pivot-select launches (none when `sorted`), then
-// the split.
+// larger than TAIL_CAP: P-1 pivot-select launches (none when `sorted`), the
+// pivot launch, then the split.
 struct LevelLaunch {
     uint32_t level = 0;
     uint32_t items = 4;              // records per thread of its split tiles
     uint32_t tiles = 0;              // split tiles
     uint32_t select_tiles = 0;       // pivot-select tiles
+    uint32_t pivot_tiles = 0;        // pivot workgroups (PIVOT_SEGS subtrees each)
+    uint32_t piv_words = 0;          // words of its pivot entries
     uint32_t hist_words = 0;         // words of its digit histograms
     bool sorted = false;             // round robin at the root's dimension: segments are in key order
     std::vector<TreeStep> steps;     // split shares
     std::vector<TreeStep> ssteps;    // pivot-select shares (tiles of HIST_TILE)
+    std::vector<TreeStep> psteps;    // pivot shares (workgroups of PIVOT_SEGS subtrees)
 };
 
 // Everything about one call that depends only on the tree sizes, k and mode.
@@ -57,15 +60,16 @@ struct Plan {
     std::vector<LevelLaunch> levels; // iterations 1.. run as passes
     uint32_t hist_words = 0;         // per third of the histogram region
     uint32_t lb_words = 0;           // per look-back buffer
+    uint32_t piv_words = 0;          // pivot entries of the largest iteration
     uint32_t box_entries = 0;        // per split-widest domain buffer
     std::vector<uint32_t> pass_words;// look-back words of every onesweep pass, in order
     bool tables = false;             // some launch reads a device share table
     std::vector<uint8_t> blob;       // the share tables, as uploaded
     size_t t_trees = 0, t_small = 0, t_prep = 0, t_presort = 0, t_level0 = 0, t_tail = 0, t_roots = 0;
-    std::vector<size_t> t_level, t_select;
+    std::vector<size_t> t_level, t_select, t_pivot;
     // workspace offsets (bytes)
     size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,
-           o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_tables = 0,
+           o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_piv = 0, o_tables = 0,
            total = 0;
     size_t rec_words = 0;            // words per record buffer
 };

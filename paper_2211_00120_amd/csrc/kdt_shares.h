@@ -37,6 +37,7 @@ constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
 #endif
 constexpr int PART_ITEMS = KDT_PART_ITEMS;
 constexpr uint32_t HIST_TILE = 16384;      // keys per workgroup of the pivot selects
+constexpr uint32_t PIVOT_SEGS = 4;         // subtrees per pivot workgroup (one wave each)
 constexpr int TAIL_THREADS = 512;          // subtree tail: 512 threads x 4 slots = up to 2048 points
 constexpr int TAIL_ITEMS = 4;
 constexpr uint32_t TAIL_CAP = (uint32_t)TAIL_THREADS * TAIL_ITEMS;
@@ -58,6 +59,7 @@ struct TreeStep {
     uint32_t hist_next;  // word offset of its histograms for the next iteration (~0u: none)
     uint32_t pair0;      // tail: level-l0 subtrees [0, pair0) take one workgroup each, the later ones two
     uint32_t buf;        // tail: record buffer (0/1) that holds the tree's level-l0 records
+    uint32_t piv;        // word offset of the share's per-subtree pivot entries (2 words each)
 };
 
 }  // namespace kdt

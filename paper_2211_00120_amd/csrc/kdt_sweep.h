@@ -160,6 +160,46 @@ __device__ __forceinline__ uint32_t find_bucket(const uint32_t (&c)[FIND_BPT], u
     return uniform(bk);
 }
 
+// find_bucket for one wave on its own (no barriers): each lane takes NB/64
+// consecutive counts of h.
+__device__ __forceinline__ uint32_t wave_find_bucket(const uint32_t* h, uint32_t NB, uint32_t& kk,
+                                                     uint32_t* status)
+{
+    constexpr uint32_t MAXB = MAX_BINS / 64u;
+    const uint32_t lane = lane_id();
+    const uint32_t bpl = NB / 64u;
+    uint32_t c[MAXB];
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < MAXB; ++b) {
+        c[b] = b < bpl ? h[lane * bpl + b] : 0u;
+        sum += c[b];
+    }
+    const uint32_t ex = wave_incl_scan(sum) - sum;
+    const uint64_t hit = __ballot(kk >= ex && kk - ex < sum);
+    if (hit == 0u) {
+        if (lane == 0) atomicOr(status, 0x100u);
+        kk = 0u;
+        return 0u;
+    }
+    const int src = __builtin_ctzll(hit);
+    uint32_t bsel = 0, rest = 0;
+    if ((int)lane == src) {
+        uint32_t run = ex;
+#pragma unroll
+        for (uint32_t b = 0; b < MAXB; ++b) {
+            if (b < bpl && kk - run < c[b]) {
+                bsel = lane * bpl + b;
+                rest = kk - run;
+                break;
+            }
+            run += c[b];
+        }
+    }
+    kk = uniform((uint32_t)__shfl((int)rest, src, 64));
+    return uniform((uint32_t)__shfl((int)bsel, src, 64));
+}
+
 // Stable wave multisplit over RB-bit digits of the first `active` items.
 template <int RB, int ITEMS>
 __device__ __forceinline__ void wave_multisplit16(const uint32_t (&digit)[ITEMS], const bool (&valid)[ITEMS],

@@ -148,7 +148,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         CHECK(ll.sorted == (!widest && l % k == 0), "level %u sorted flag", l);
         if (opt.max_items) CHECK(ll.items <= opt.max_items, "items cap");
         std::vector<std::pair<uint64_t, uint64_t>> hist;
-        uint32_t tiles = 0, htiles = 0;
+        uint32_t tiles = 0, htiles = 0, ptiles = 0, pwords = 0;
         size_t si = 0;
         for (uint32_t t : p.large) {
             if (l >= l0[t]) continue;
@@ -160,6 +160,11 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
             const Level v = make_level(n[t], l);
             CHECK(s.tree == t && s.level == l && s.tile0 == tiles, "level %u share of tree %u", l, t);
             CHECK(h.tree == t && h.tile0 == htiles && h.hist == s.hist, "select share of tree %u", t);
+            const TreeStep& pv = ll.psteps[si - 1];
+            CHECK(pv.tree == t && pv.tile0 == ptiles && pv.hist == s.hist && pv.piv == s.piv && s.piv == pwords,
+                  "pivot share of tree %u", t);
+            ptiles += (v.nseg + PIVOT_SEGS - 1) / PIVOT_SEGS;
+            pwords += 2 * v.nseg;
             tiles += tiles_level(v, (uint32_t)SWEEP_THREADS * ll.items).tiles;
             htiles += tiles_level(v, HIST_TILE).tiles;
             const uint64_t lo = (l % 3u) * (uint64_t)p.hist_words, hi = lo + p.hist_words;
@@ -179,7 +184,9 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         }
         CHECK(disjoint(hist), "histogram ranges overlap at level %u", l);
         CHECK(si == ll.steps.size() && ll.ssteps.size() == si, "level %u share count", l);
-        CHECK(tiles == ll.tiles && htiles == ll.select_tiles, "level %u tile totals", l);
+        CHECK(tiles == ll.tiles && htiles == ll.select_tiles && ptiles == ll.pivot_tiles, "level %u tile totals", l);
+        CHECK(pwords == ll.piv_words && pwords <= p.piv_words && ll.psteps.size() == ll.steps.size(),
+              "level %u pivot words", l);
         uint32_t hw = 0;
         for (const TreeStep& s : ll.steps) hw += make_level(n[s.tree], l).nseg * p.P * NB;
         CHECK(hw == ll.hist_words && hw <= p.hist_words, "level %u hist words", l);
@@ -238,7 +245,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         {p.o_lb[1], (size_t)p.lb_words * 4, "lb1"}, {p.o_keys, N * k * 4, "keys"}, {p.o_perms, N * k * 4, "perms"},
         {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, p.rec_words * 8, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
         {p.o_dimnode, N, "dimnode"}, {p.o_box[0], (size_t)p.box_entries * 32, "box0"},
-        {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * KEYSUM_WORDS * 4, "keysum"},
+        {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * KEYSUM_WORDS * 4, "keysum"}, {p.o_piv, (size_t)p.piv_words * 4, "piv"},
         {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}};
     size_t end = 0;
     for (const R& r : regs) {
@@ -259,6 +266,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
               "level table %zu", li);
         CHECK(same(p.t_select[li], p.levels[li].ssteps.data(), p.levels[li].ssteps.size() * sizeof(TreeStep)),
               "select table %zu", li);
+        CHECK(same(p.t_pivot[li], p.levels[li].psteps.data(), p.levels[li].psteps.size() * sizeof(TreeStep)),
+              "pivot table %zu", li);
     }
     CHECK(p.tables == (p.small.size() > 1 || p.large.size() > 1), "table flag");
     check_steps_tile(p.small, (uint32_t)p.small.size(), "small");
