@@ -156,6 +156,10 @@ void kdt_release_cached(void);
 typedef struct kdt_tuning {
     uint32_t radix_bits;   /* 0 (planner's choice) or 8..10 */
     uint32_t level_items;  /* 0 (planner's choice), 4 or 8: cap on records per thread of level-sort tiles */
+    uint32_t rank_layout;  /* 0 (planner's choice: 2 when the rank table exceeds 128 MiB), 1 (each dimension's
+                              last presort pass writes a point-major rank table) or 2 (it writes one rank array
+                              per dimension, which a packing pass turns into the point-major table); never
+                              swept by kdt_tune_batched */
     double ms;             /* kdt_tune_batched: time of one build with this choice */
 } kdt_tuning;
 
@@ -168,7 +172,7 @@ kdt_status kdt_tuning_get(uint32_t k, int dim_mode, uint32_t rank_bits, kdt_tuni
 kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kdt_tuning* t);
 
 /* Text file of recorded choices, one "k dim_mode rank_bits radix_bits
- * level_items" line each; load merges into the current table and fails
+ * level_items rank_layout" line each; load merges into the current table and fails
  * without changing it on a malformed file. */
 kdt_status kdt_tuning_save(const char* path);
 kdt_status kdt_tuning_load(const char* path);

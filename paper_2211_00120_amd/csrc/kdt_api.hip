@@ -84,10 +84,10 @@ kdt_status check_launch(const char* what)
 // hipEvents on the build's stream and tagged with its kind and algorithmic
 // bytes (the bytes the step must move by definition).
 enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
-            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_COUNT };
+            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
                                             "k_level0", "k_level_select", "k_level_pivot", "k_level_part",
-                                            "k_tail", "k_tail_whole", "share_tables", "k_word"};
+                                            "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_pack"};
 
 struct ProfRec {
     int kind;
@@ -321,8 +321,9 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 a.counter = counters + q;
                 a.perm_out = perms + (size_t)d * ntotal;
                 a.rank_table = ranks;
+                a.rank_stride = p.rank_dm ? 1u : k;
+                a.rank_dstride = p.rank_dm ? (size_t)ntotal : 1u;
                 a.dimnode = widest ? o.dimnode : nullptr;
-                a.k = k;
                 a.dim = d;
                 a.status = dstatus;
                 double bytes = 0;
@@ -342,6 +343,16 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             }
         }
 
+        // per-dimension ranks -> point-major records in rec[1], which is free
+        // until iteration 1 writes it
+        uint32_t* rank_table = ranks;
+        if (p.rank_dm) {
+            rank_table = rec[1];
+            if (kdt_status s = run_kernel(st, KIND_PACK, ntotal * 8.0 * K,
+                                          [&] { launch_rank_pack((int)k, ranks, rank_table, ntotal, st); }))
+                return s;
+        }
+
         // iteration 0 writes the records of iteration 1 into rec[0]
         int cur = 0;
         {
@@ -349,7 +360,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             Level0Args a{};
             a.sh = shares(p, p.level0, p.t_level0, ws);
             a.perms = perms;
-            a.rank_table = ranks;
+            a.rank_table = rank_table;
             a.rout = rec[cur];
             a.kout = skey[0];
             a.hist = hist;
@@ -469,10 +480,10 @@ kdt_status batched_plan(const uint32_t* h_offsets, uint32_t C, uint32_t k, bool 
     for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
     // the tuning in effect is part of the key
     const PlanOptions opt = tuned_options(k, widest, plan_rank_bits(n));
-    std::string key(16 + (size_t)(C + 1) * 4, '\0');
-    const uint32_t head[4] = {k, widest ? 1u : 0u, opt.radix_bits, opt.max_items};
-    memcpy(&key[0], head, 16);
-    memcpy(&key[16], h_offsets, (size_t)(C + 1) * 4);
+    std::string key(20 + (size_t)(C + 1) * 4, '\0');
+    const uint32_t head[5] = {k, widest ? 1u : 0u, opt.radix_bits, opt.max_items, opt.rank_layout};
+    memcpy(&key[0], head, 20);
+    memcpy(&key[20], h_offsets, (size_t)(C + 1) * 4);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     std::shared_ptr<CachedPlan> cp;
     auto it = g_plans.find(key);
@@ -710,6 +721,7 @@ kdt_status kdt_tune_batched(const float* d_points, const uint32_t* h_offsets, ui
     set_tuned_options(k, widest, bits, chosen);
     best->radix_bits = chosen.radix_bits;
     best->level_items = chosen.max_items;
+    best->rank_layout = chosen.rank_layout;
     best->ms = best_ms;
     return KDT_OK;
 }
@@ -725,6 +737,7 @@ kdt_status kdt_tuning_get(uint32_t k, int dim_mode, uint32_t rank_bits, kdt_tuni
     memset(out, 0, sizeof *out);
     out->radix_bits = o.radix_bits;
     out->level_items = o.max_items;
+    out->rank_layout = o.rank_layout;
     return KDT_OK;
 }
 
@@ -732,13 +745,14 @@ kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kd
 {
     if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
     if (!t || rank_bits > 32 || (t->radix_bits && (t->radix_bits < 8 || t->radix_bits > 10)) ||
-        (t->level_items && t->level_items != 4 && t->level_items != 8)) {
-        set_err("tuning must have radix_bits 0 or 8..10 and level_items 0, 4 or 8");
+        (t->level_items && t->level_items != 4 && t->level_items != 8) || t->rank_layout > 2) {
+        set_err("tuning must have radix_bits 0 or 8..10, level_items 0, 4 or 8 and rank_layout 0..2");
         return KDT_EINVAL;
     }
     PlanOptions o;
     o.radix_bits = t->radix_bits;
     o.max_items = t->level_items;
+    o.rank_layout = t->rank_layout;
     set_tuned_options(k, dim_mode == KDT_DIM_WIDEST, rank_bits, o);
     return KDT_OK;
 }

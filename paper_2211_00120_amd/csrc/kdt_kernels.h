@@ -66,9 +66,11 @@ struct PresortArgs {
     uint32_t lb_zero_n;
     uint32_t* counter;      // dynamic tile counter of this pass
     uint32_t* perm_out;     // last pass: per tree rank -> local index of this dimension
-    uint32_t* rank_table;   // last pass: point-major ranks, [(off + i)*k + dim], except each tree's root dimension
+    uint32_t* rank_table;   // last pass: ranks at [(off + i)*rank_stride + dim*rank_dstride], except each tree's
+                            // root dimension: point-major (k, 1) or per-dimension arrays (1, ntotal)
     const uint8_t* dimnode; // split-widest: node dims (the root's is tree's first entry); null: root dimension 0
-    uint32_t k;
+    uint32_t rank_stride;
+    size_t rank_dstride;
     uint32_t dim;
     uint32_t* status;
 };
@@ -155,6 +157,9 @@ void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1
 void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st);
 void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st);
+// Per-dimension rank arrays dm[d*ntotal + i] -> point-major records
+// pm[i*k + d], i < ntotal.
+void launch_rank_pack(int k, const uint32_t* dm, uint32_t* pm, uint32_t ntotal, hipStream_t st);
 void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t st);
 void launch_level_pivot(int k, const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st);

@@ -167,8 +167,8 @@ __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
 // One stable LSD digit pass of the (key, index) sort of one dimension, every
 // tree a segment of its own.  A tree's first pass that runs reads the keys
 // of prep and takes the local index as value; LAST writes the sorted indices
-// (rank -> index) and scatters each index's rank into the point-major rank
-// table.  Pairs are stored interleaved (uint2).  Passes whose digit is the
+// (rank -> index) and scatters each index's rank into the rank table
+// (point-major, or one array per dimension).  Pairs are stored interleaved (uint2).  Passes whose digit is the
 // same in every key of the tree are skipped (see PresortArgs).
 template <bool LAST>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
@@ -234,13 +234,59 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
             if (LAST) {
                 a.perm_out[off + pos] = r.y;
-                if (to_table) a.rank_table[(off + r.y) * a.k + a.dim] = pos;
+                if (to_table) a.rank_table[(off + r.y) * a.rank_stride + a.dim * a.rank_dstride] = pos;
             } else {
                 reinterpret_cast<uint2*>(kvout)[off + pos] = make_uint2(r.x, r.y);
             }
         });
     // clear the next pass's look-back words (nothing waits on these stores)
     zero_range(a.lb_zero, a.lb_zero_n);
+}
+
+// ------------------------------------------------------------- rank packing
+
+// Per-dimension rank arrays to point-major records, PACK_PER points per
+// thread (loads first, then stores).  Each tree's root-dimension slot is
+// copied as it is (never written by the presort); iteration 0 replaces it.
+constexpr uint32_t PACK_PER = 4;
+
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_rank_pack(const uint32_t* __restrict__ dm, uint32_t* __restrict__ pm,
+                                                     uint32_t ntotal)
+{
+    const size_t base = (size_t)blockIdx.x * BLOCK * PACK_PER + threadIdx.x;
+    uint32_t v[PACK_PER][K];
+#pragma unroll
+    for (uint32_t j = 0; j < PACK_PER; ++j) {
+        const size_t i = base + (size_t)j * BLOCK;
+#pragma unroll
+        for (int d = 0; d < K; ++d) v[j][d] = i < ntotal ? dm[(size_t)d * ntotal + i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < PACK_PER; ++j) {
+        const size_t i = base + (size_t)j * BLOCK;
+        if (i >= ntotal) continue;
+        if constexpr (K == 4) {
+            reinterpret_cast<uint4*>(pm)[i] = make_uint4(v[j][0], v[j][1], v[j][2], v[j][3]);
+        } else if constexpr (K == 2) {
+            reinterpret_cast<uint2*>(pm)[i] = make_uint2(v[j][0], v[j][1]);
+        } else {
+#pragma unroll
+            for (int d = 0; d < K; ++d) pm[i * K + d] = v[j][d];
+        }
+    }
+}
+
+void launch_rank_pack(int k, const uint32_t* dm, uint32_t* pm, uint32_t ntotal, hipStream_t st)
+{
+    const uint32_t grid = (uint32_t)(((size_t)ntotal + BLOCK * PACK_PER - 1) / (BLOCK * PACK_PER));
+    if (!grid) return;
+    switch (k) {
+    case 2: k_rank_pack<2><<<grid, BLOCK, 0, st>>>(dm, pm, ntotal); break;
+    case 3: k_rank_pack<3><<<grid, BLOCK, 0, st>>>(dm, pm, ntotal); break;
+    case 4: k_rank_pack<4><<<grid, BLOCK, 0, st>>>(dm, pm, ntotal); break;
+    default: break;
+    }
 }
 
 // ------------------------------------------------------------------ level 0

@@ -82,15 +82,15 @@ void clear_tuning()
     g_tune.clear();
 }
 
-// One line per entry: "k widest bits radix_bits max_items".
+// One line per entry: "k widest bits radix_bits max_items rank_layout".
 bool save_tuning(const char* path)
 {
     FILE* f = fopen(path, "w");
     if (!f) return false;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune)
-        fprintf(f, "%u %d %u %u %u\n", std::get<0>(kv.first), std::get<1>(kv.first) ? 1 : 0, std::get<2>(kv.first),
-                kv.second.radix_bits, kv.second.max_items);
+        fprintf(f, "%u %d %u %u %u %u\n", std::get<0>(kv.first), std::get<1>(kv.first) ? 1 : 0,
+                std::get<2>(kv.first), kv.second.radix_bits, kv.second.max_items, kv.second.rank_layout);
     return fclose(f) == 0;
 }
 
@@ -99,17 +99,19 @@ bool load_tuning(const char* path)
     FILE* f = fopen(path, "r");
     if (!f) return false;
     std::map<std::tuple<uint32_t, bool, uint32_t>, PlanOptions> t;
-    unsigned k, w, bits, rb, items;
+    unsigned k, w, bits, rb, items, layout;
     int r;
     bool ok = true;
-    while ((r = fscanf(f, "%u %u %u %u %u", &k, &w, &bits, &rb, &items)) == 5) {
-        if (k < 1 || k > 4 || w > 1 || bits > 32 || (rb && (rb < 8 || rb > 10)) || (items && items != 4 && items != 8)) {
+    while ((r = fscanf(f, "%u %u %u %u %u %u", &k, &w, &bits, &rb, &items, &layout)) == 6) {
+        if (k < 1 || k > 4 || w > 1 || bits > 32 || (rb && (rb < 8 || rb > 10)) || (items && items != 4 && items != 8) ||
+            layout > 2) {
             ok = false;
             break;
         }
         PlanOptions o;
         o.radix_bits = rb;
         o.max_items = items;
+        o.rank_layout = layout;
         t[std::make_tuple((uint32_t)k, w == 1u, (uint32_t)bits)] = o;
     }
     if (r != EOF) ok = false;
@@ -151,7 +153,7 @@ uint32_t first_tail_level(uint32_t n)
 Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& given)
 {
     const PlanOptions opt =
-        (given.radix_bits || given.max_items) ? given : tuned_options(k, widest, plan_rank_bits(n));
+        (given.radix_bits || given.max_items || given.rank_layout) ? given : tuned_options(k, widest, plan_rank_bits(n));
     Plan p;
     p.k = k;
     p.widest = widest;
@@ -192,6 +194,9 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         p.P = (p.B + p.RB - 1u) / p.RB;
     }
     const uint32_t items_cap = (opt.max_items == 4 || opt.max_items == 8) ? opt.max_items : 8u;
+    // rank table layout (k = 1 scatters nothing: the only dimension is the root's)
+    p.rank_dm = k >= 2 && !p.large.empty() &&
+                (opt.rank_layout == 2 || (opt.rank_layout == 0 && p.ntotal * k * 4 > RANK_DM_BYTES));
     const uint32_t NB = 1u << p.RB;
 
     // per-tree shares of the whole-array steps

@@ -25,7 +25,14 @@ constexpr uint32_t NO_HIST = 0xFFFFFFFFu;
 struct PlanOptions {
     uint32_t radix_bits = 0;   // digit width of the pivot selects: 8, 9 or 10
     uint32_t max_items = 0;    // cap on records per thread of the split tiles: 4 or 8
+    uint32_t rank_layout = 0;  // 1: point-major rank table, 2: per-dimension rank arrays + packing pass
 };
+
+// Rank tables larger than this are scattered into per-dimension arrays and
+// then packed (random 4-byte writes that leave a line partly written cost
+// about twice as much as ones that, over the pass, fill it); smaller ones
+// stay resident in the last-level cache and are written point-major.
+constexpr uint64_t RANK_DM_BYTES = 128ull << 20;
 
 // One iteration run as digit passes over every tree that still has subtrees
 // larger than TAIL_CAP: P-1 pivot-select launches (none when `sorted`), the
@@ -55,6 +62,7 @@ struct Plan {
     std::vector<uint32_t> large;     // trees built by digit passes
     std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
     uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / digits of the pivot selects
+    bool rank_dm = false;            // presorts scatter per-dimension ranks, a pass packs them
     std::vector<TreeStep> prep, presort, level0, tail, roots;
     uint32_t prep_tiles = 0, presort_tiles = 0, tail_groups = 0;
     std::vector<LevelLaunch> levels; // iterations 1.. run as passes

@@ -88,7 +88,8 @@ class Result(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("radix_bits", ctypes.c_uint32), ("level_items", ctypes.c_uint32), ("ms", ctypes.c_double)]
+    _fields_ = [("radix_bits", ctypes.c_uint32), ("level_items", ctypes.c_uint32), ("rank_layout", ctypes.c_uint32),
+                ("ms", ctypes.c_double)]
 
 
 class KdtError(RuntimeError):
@@ -252,11 +253,11 @@ def tuning_get(k: int, mode: int, rank_bits: int):
     rc = lib().kdt_tuning_get(k, mode, rank_bits, ctypes.byref(t))
     if rc != OK:
         raise KdtError(rc, "kdt_tuning_get")
-    return t.radix_bits, t.level_items
+    return t.radix_bits, t.level_items, t.rank_layout
 
 
-def tuning_set(k: int, mode: int, rank_bits: int, radix_bits: int, level_items: int):
-    t = Tuning(radix_bits, level_items, 0.0)
+def tuning_set(k: int, mode: int, rank_bits: int, radix_bits: int, level_items: int, rank_layout: int = 0):
+    t = Tuning(radix_bits, level_items, rank_layout, 0.0)
     rc = lib().kdt_tuning_set(k, mode, rank_bits, ctypes.byref(t))
     if rc != OK:
         raise KdtError(rc, "kdt_tuning_set")

@@ -254,6 +254,14 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     }
     CHECK(end <= p.total && p.total % WS_ALIGN == 0, "total");
     CHECK(p.rec_words >= N * k && p.rec_words >= 2 * N, "record words");
+    // rank layout: per-dimension arrays (in the ranks region) packed into the
+    // second record buffer, for k >= 2 only, when forced or when the
+    // point-major table would exceed RANK_DM_BYTES
+    {
+        const bool want = k >= 2 && !p.large.empty() &&
+                          (opt.rank_layout == 2 || (opt.rank_layout == 0 && (uint64_t)N * k * 4 > RANK_DM_BYTES));
+        CHECK(p.rank_dm == want, "rank layout (k %u, layout %u, N %zu)", k, opt.rank_layout, N);
+    }
     // the uploaded tables hold the host lists
     auto same = [&](size_t at, const void* v, size_t bytes) {
         return at + bytes <= p.blob.size() && (bytes == 0 || std::memcmp(p.blob.data() + at, v, bytes) == 0);
@@ -297,6 +305,7 @@ int main()
         PlanOptions opt;
         if (rep % 4 == 1) opt.radix_bits = 8 + (uint32_t)(u(rng) * 3);
         if (rep % 5 == 2) opt.max_items = 4;
+        opt.rank_layout = rep % 3;
         check_plan(n, 1 + rep % 4, rep % 2 == 1, opt);
     }
     if (g_fail) return 1;

@@ -227,6 +227,31 @@ def test_batched_full_4096_clouds():
         _assert_cloud(pts, offsets, int(c), tree_b, perm_b, dim_b, mode, "batched-4096")
 
 
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_batched_rank_layouts(mode):
+    """A batch built with per-dimension rank arrays plus packing equals the
+    same batch built with the point-major scatter, and every cloud is the
+    oracle's tree."""
+    sizes = [70000, 3000, 0, 130000, 9000, 1500, 40000, 2049]
+    clouds = [workloads.grid(n, 4, 140 + i, levels=11) for i, n in enumerate(sizes)]
+    pts, offsets = _concat(clouds)
+    bits = int(max(sizes) - 1).bit_length()
+    kdt.tuning_clear()
+    try:
+        got = {}
+        for layout in (1, 2):
+            _say(f"case batched rank layout {layout} mode {mode}")
+            kdt.tuning_set(4, mode, bits, 0, 0, layout)
+            got[layout] = _run_batched(pts, offsets, mode)
+            assert got[layout][3] == kdt.OK
+        assert got[1][0].tobytes() == got[2][0].tobytes()
+        assert np.array_equal(got[1][1], got[2][1]) and np.array_equal(got[1][2], got[2][2])
+        for c in range(len(sizes)):
+            _assert_cloud(pts, offsets, c, *got[2][:3], mode, "rank-layout-2")
+    finally:
+        kdt.tuning_clear()
+
+
 def test_tuner_choices_give_identical_trees():
     """Every digit-width / tile choice the tuner may record builds the same
     trees; kdt_tune_batched records one of them for the batch's class."""
@@ -252,7 +277,7 @@ def test_tuner_choices_give_identical_trees():
         torch.cuda.synchronize()
         _say(f"tuner picked radix {rb} items {items} at {ms:.3f} ms")
         assert rb in (8, 9, 10) and items in (4, 8) and ms > 0
-        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, bits) == (rb, items)
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, bits) == (rb, items, 0)
         got = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
         assert np.array_equal(got[1], ref[1])
         for c in range(len(sizes)):
