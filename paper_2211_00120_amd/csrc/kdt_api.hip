@@ -291,8 +291,8 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 return s;
 
         // presort: per dimension, 4 stable digit passes of (key, index); the
-        // (key, index) ping-pong lives in the record region (2 * rec_words >=
-        // 4 * ntotal words), which is free until iteration 0.  A pass whose
+        // (key, index) ping-pongs live in the record region (>= 4 *
+        // presort_group * ntotal words), which is free until iteration 0.  A pass whose
         // digit is the same in all keys of a tree is skipped for that tree;
         // for the profile's byte counts, the key summaries are read back
         // (profiling builds only)
@@ -302,45 +302,55 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             HIP_TRY(hipMemcpyAsync(keysum.data(), o.bbox, keysum.size() * 4, hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
+        // the plan's launches, each over a group of dimensions, each dimension
+        // with its own ping-pong (the group's slot j: words [4j, 4j+4) *
+        // ntotal of the record region; a launch of one dimension of a group
+        // takes that dimension's slot)
         uint32_t q = 0;
-        uint32_t* kv[2] = {recbase, recbase + 2 * (size_t)ntotal};
-        for (uint32_t d = 0; d < k; ++d) {
-            for (uint32_t ps = 0; ps < 4; ++ps, ++q) {
+        for (const Plan::PresortLaunch& pl : p.presort_launches) {
+            const uint32_t d0 = pl.dim0, nd = pl.ndims, ps = pl.pass;
+            {
                 PresortArgs a{};
                 a.sh = shares(p, p.presort, p.t_presort, ws);
-                a.kin = keys + (size_t)d * ntotal;
-                a.kv[0] = kv[0];
-                a.kv[1] = kv[1];
+                a.keys = keys;
+                a.kv_words = 2 * (size_t)ntotal;
+                a.kv = recbase + 2 * (size_t)(d0 % p.presort_group) * a.kv_words;
                 a.keysum = o.bbox;
                 a.pass = ps;
-                a.hist = hist_rank + (d * 4 + ps) * RADIX_HOST;
+                a.dim0 = d0;
+                a.ndims = nd;
+                a.hist = hist_rank;
                 a.hist_stride = k * 4 * RADIX_HOST;
                 a.lb = lb[q & 1];
+                a.lb_dim_words = p.presort_tiles * RADIX_HOST;
                 a.lb_zero = lb[(q + 1) & 1];
                 a.lb_zero_n = next_words(q);
                 a.counter = counters + q;
-                a.perm_out = perms + (size_t)d * ntotal;
+                a.perms = perms;
                 a.rank_table = ranks;
                 a.rank_stride = p.rank_dm ? 1u : k;
                 a.rank_dstride = p.rank_dm ? (size_t)ntotal : 1u;
                 a.dimnode = widest ? o.dimnode : nullptr;
-                a.dim = d;
+                a.ntotal = ntotal;
                 a.status = dstatus;
                 double bytes = 0;
                 if (g_prof.on) {
-                    for (uint32_t i = 0; i < nlarge_trees; ++i) {
-                        const uint32_t vary = keysum[i * KEYSUM_WORDS + 8 + d] ^ keysum[i * KEYSUM_WORDS + 12 + d];
-                        auto runs = [&](uint32_t qq) { return ((vary >> (8 * qq)) & 0xFFu) != 0u; };
-                        if (ps < 3 && !runs(ps)) continue;
-                        bool first = true;
-                        for (uint32_t qq = 0; qq < ps; ++qq) first = first && !runs(qq);
-                        bytes += p.trees[p.large[i]].n * (first ? 12.0 : 16.0);
-                    }
+                    for (uint32_t d = d0; d < d0 + nd; ++d)
+                        for (uint32_t i = 0; i < nlarge_trees; ++i) {
+                            const uint32_t vary =
+                                keysum[i * KEYSUM_WORDS + 8 + d] ^ keysum[i * KEYSUM_WORDS + 12 + d];
+                            auto runs = [&](uint32_t qq) { return ((vary >> (8 * qq)) & 0xFFu) != 0u; };
+                            if (ps < 3 && !runs(ps)) continue;
+                            bool first = true;
+                            for (uint32_t qq = 0; qq < ps; ++qq) first = first && !runs(qq);
+                            bytes += p.trees[p.large[i]].n * (first ? 12.0 : 16.0);
+                        }
                 }
                 if (kdt_status s = run_kernel(st, KIND_PRESORT, bytes,
-                                              [&] { launch_presort_pass(a, ps == 3, p.presort_tiles, st); }))
+                                              [&] { launch_presort_pass(a, ps == 3, nd * p.presort_tiles, st); }))
                     return s;
             }
+            ++q;
         }
 
         // per-dimension ranks -> point-major records in rec[1], which is free

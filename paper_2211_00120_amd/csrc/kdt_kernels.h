@@ -55,23 +55,27 @@ struct PrepArgs {
 // The last pass always runs.
 struct PresortArgs {
     Shares sh;              // one share per tree, tiles of PRESORT_TILE points
-    const uint32_t* kin;    // prep's keys of this dimension (value = local index)
-    uint32_t* kv[2];        // (key, local index) pairs, interleaved
+    const uint32_t* keys;   // prep's keys, [d*ntotal + off + i] (value = local index)
+    uint32_t* kv;           // (key, local index) pairs, interleaved: dimension slot j ping-pongs between
+                            // kv + (2j)*kv_words and kv + (2j+1)*kv_words
+    size_t kv_words;
     const uint32_t* keysum; // per tree key summaries
     uint32_t pass;
-    const uint32_t* hist;   // per tree histograms of this dimension and pass: hist + idx*hist_stride
+    uint32_t dim0, ndims;   // the launch sorts dimensions dim0 .. dim0+ndims-1, tiles interleaved
+    const uint32_t* hist;   // per tree digit histograms: hist + idx*hist_stride + (d*4 + pass)*RADIX
     uint32_t hist_stride;
-    uint32_t* lb;           // look-back words of this pass
+    uint32_t* lb;           // look-back words of this pass, dimension slot j at lb + j*lb_dim_words
+    uint32_t lb_dim_words;
     uint32_t* lb_zero;      // look-back words to clear for the next pass
     uint32_t lb_zero_n;
     uint32_t* counter;      // dynamic tile counter of this pass
-    uint32_t* perm_out;     // last pass: per tree rank -> local index of this dimension
-    uint32_t* rank_table;   // last pass: ranks at [(off + i)*rank_stride + dim*rank_dstride], except each tree's
+    uint32_t* perms;        // last pass: per tree rank -> local index, [d*ntotal + off + rank]
+    uint32_t* rank_table;   // last pass: ranks at [(off + i)*rank_stride + d*rank_dstride], except each tree's
                             // root dimension: point-major (k, 1) or per-dimension arrays (1, ntotal)
     const uint8_t* dimnode; // split-widest: node dims (the root's is tree's first entry); null: root dimension 0
     uint32_t rank_stride;
     size_t rank_dstride;
-    uint32_t dim;
+    uint32_t ntotal;
     uint32_t* status;
 };
 

@@ -164,8 +164,10 @@ __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
 
 // ------------------------------------------------------------ presort passes
 
-// One stable LSD digit pass of the (key, index) sort of one dimension, every
-// tree a segment of its own.  A tree's first pass that runs reads the keys
+// One stable LSD digit pass of the (key, index) sorts of a group of
+// dimensions, every tree a segment of its own.  The dimensions' tiles are
+// interleaved (tile t of the launch is tile t / ndims of dimension slot
+// t % ndims), so the look-back chains of the group advance side by side.  A tree's first pass that runs reads the keys
 // of prep and takes the local index as value; LAST writes the sorted indices
 // (rank -> index) and scatters each index's rank into the rank table
 // (point-major, or one array per dimension).  Pairs are stored interleaved (uint2).  Passes whose digit is the
@@ -180,13 +182,15 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 
     if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
     __syncthreads();
-    const uint32_t g = uniform(sm.tile);
+    const uint32_t tt = uniform(sm.tile);
+    const uint32_t slot = tt % a.ndims, g = tt / a.ndims;
+    const uint32_t dim = a.dim0 + slot;
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, g, st, ti);
     // digits of this dimension that are not the same in every key of the tree
     const uint32_t* sum = a.keysum + (size_t)ti.idx * KEYSUM_WORDS;
-    const uint32_t vary = uniform(sum[8 + a.dim] ^ sum[12 + a.dim]);
+    const uint32_t vary = uniform(sum[8 + dim] ^ sum[12 + dim]);
     const uint32_t q = a.pass;
     if (!LAST && ((vary >> (8u * q)) & 0xFFu) == 0u) {
         zero_range(a.lb_zero, a.lb_zero_n);
@@ -195,8 +199,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     uint32_t ran = 0;                       // passes of this tree that ran before this one
     for (uint32_t qq = 0; qq < q; ++qq) ran += ((vary >> (8u * qq)) & 0xFFu) != 0u;
     const bool first = ran == 0u;
-    const uint32_t* kvin = a.kv[(ran + 1u) & 1u];
-    uint32_t* kvout = a.kv[ran & 1u];
+    uint32_t* kvs = a.kv + (size_t)(2u * slot) * a.kv_words;
+    const uint32_t* kvin = kvs + (size_t)((ran + 1u) & 1u) * a.kv_words;
+    uint32_t* kvout = kvs + (size_t)(ran & 1u) * a.kv_words;
+    const uint32_t* kin = a.keys + (size_t)dim * a.ntotal;
+    uint32_t* perm_out = a.perms + (size_t)dim * a.ntotal;
     const uint32_t start = (g - st.tile0) * T;
     const uint32_t cnt = min(T, ti.n - start);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
@@ -213,7 +220,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         rec[i] = make_uint4(0u, 0u, 0u, 0u);
         if (ok[i]) {
             if (first) {
-                rec[i].x = a.kin[off + start + j];
+                rec[i].x = kin[off + start + j];
                 rec[i].y = start + j;
             } else {
                 const uint2 kv = reinterpret_cast<const uint2*>(kvin)[off + start + j];
@@ -226,15 +233,16 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     const uint32_t n = ti.n;
     // iteration 0 reads the root dimension's ranks as positions in perm_out,
     // so only the other dimensions go into the (randomly written) rank table
-    const bool to_table = !LAST || a.dim != (a.dimnode ? (uint32_t)a.dimnode[off] : 0u);
+    const bool to_table = !LAST || dim != (a.dimnode ? (uint32_t)a.dimnode[off] : 0u);
     sweep_tile<RB, ITEMS, 2>(
-        sm, rec, ok, dig, ITEMS, cnt, a.hist + (size_t)ti.idx * a.hist_stride, 0u, a.lb, g, st.tile0, a.status,
+        sm, rec, ok, dig, ITEMS, cnt, a.hist + (size_t)ti.idx * a.hist_stride + (dim * 4u + q) * RADIX, 0u,
+        a.lb + (size_t)slot * a.lb_dim_words, g, st.tile0, a.status,
         [&](const uint4& r) { return (r.x >> shift) & 0xFFu; },
         [&](uint32_t, uint32_t pos, const uint4& r) {
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
             if (LAST) {
-                a.perm_out[off + pos] = r.y;
-                if (to_table) a.rank_table[(off + r.y) * a.rank_stride + a.dim * a.rank_dstride] = pos;
+                perm_out[off + pos] = r.y;
+                if (to_table) a.rank_table[(off + r.y) * a.rank_stride + dim * a.rank_dstride] = pos;
             } else {
                 reinterpret_cast<uint2*>(kvout)[off + pos] = make_uint2(r.x, r.y);
             }

@@ -289,8 +289,21 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     }
 
     // look-back words per pass, in the order the passes run
+    // presort launches: passes 0-2 of a group of dimensions share a launch;
+    // so does the last pass, unless it scatters into per-dimension arrays
+    // too large for the cache (several at once only evict each other)
+    p.presort_group = std::min(k, PRESORT_GROUP);
     if (!p.large.empty())
-        for (uint32_t q = 0; q < 4u * k; ++q) p.pass_words.push_back(p.presort_tiles * RADIX_HOST);
+        for (uint32_t d0 = 0; d0 < k; d0 += p.presort_group) {
+            const uint32_t nd = std::min(p.presort_group, k - d0);
+            for (uint32_t q = 0; q < 3u; ++q) p.presort_launches.push_back({d0, nd, q});
+            if (p.rank_dm)
+                for (uint32_t d = d0; d < d0 + nd; ++d) p.presort_launches.push_back({d, 1u, 3u});
+            else
+                p.presort_launches.push_back({d0, nd, 3u});
+        }
+    for (const Plan::PresortLaunch& pl : p.presort_launches)
+        p.pass_words.push_back(pl.ndims * p.presort_tiles * RADIX_HOST);
     for (const LevelLaunch& ll : p.levels) p.pass_words.push_back(ll.tiles * PART_BINS);
     for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
 
@@ -326,8 +339,9 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_keys = take(N * k * 4);
     p.o_perms = take(N * k * 4);
     p.o_ranks = take(N * k * 4);
-    p.rec_words = std::max(N * k, 2 * N);   // also holds the presort's (key, index) ping-pong
-    p.o_rec = take(p.rec_words * 2 * 4);
+    // the record buffers also hold the presort's (key, index) ping-pongs
+    p.rec_words = std::max(N * k, 2 * N);
+    p.o_rec = take(std::max(p.rec_words * 2, (size_t)4 * p.presort_group * N) * 4);
     p.o_nodeperm = take(N * 4);
     p.o_dimnode = take(N);
     p.o_box[0] = take((size_t)p.box_entries * 8 * 4);

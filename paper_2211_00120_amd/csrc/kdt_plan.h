@@ -63,6 +63,11 @@ struct Plan {
     std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
     uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / digits of the pivot selects
     bool rank_dm = false;            // presorts scatter per-dimension ranks, a pass packs them
+    uint32_t presort_group = 1;      // dimensions sharing the presort launches of passes 0-2
+    struct PresortLaunch {
+        uint32_t dim0, ndims, pass;  // digit pass `pass` of dimensions dim0 .. dim0+ndims-1
+    };
+    std::vector<PresortLaunch> presort_launches;  // in order
     std::vector<TreeStep> prep, presort, level0, tail, roots;
     uint32_t prep_tiles = 0, presort_tiles = 0, tail_groups = 0;
     std::vector<LevelLaunch> levels; // iterations 1.. run as passes

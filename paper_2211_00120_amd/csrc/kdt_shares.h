@@ -31,6 +31,12 @@ constexpr int SWEEP_THREADS = KDT_SWEEP_THREADS;
 #endif
 constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
 constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
+// Dimensions whose presort digit passes share a launch (each needs its own
+// (key, index) ping-pong of 4 words per point).
+#ifndef KDT_PRESORT_GROUP
+#define KDT_PRESORT_GROUP 4
+#endif
+constexpr uint32_t PRESORT_GROUP = KDT_PRESORT_GROUP;
 // Records per thread of the large split tiles (the small ones take 4).
 #ifndef KDT_PART_ITEMS
 #define KDT_PART_ITEMS 8

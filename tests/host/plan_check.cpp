@@ -231,10 +231,39 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     }
     CHECK(groups == p.tail_groups, "tail groups");
     // look-back words
-    const size_t npass = (p.large.empty() ? 0 : 4u * k) + p.levels.size();
+    // presort: dimensions in groups of presort_group; passes 0-2 of a group
+    // share a launch, and so does pass 3 unless the ranks go to per-dimension
+    // arrays (then one launch per dimension); every launch's look-back words
+    // cover its dimensions
+    const uint32_t G = p.presort_group;
+    CHECK(G >= 1 && G <= PRESORT_GROUP && G <= k, "presort group %u", G);
+    std::vector<Plan::PresortLaunch> want;
+    if (!p.large.empty())
+        for (uint32_t d0 = 0; d0 < k; d0 += G) {
+            const uint32_t nd = std::min(G, k - d0);
+            for (uint32_t q = 0; q < 3u; ++q) want.push_back({d0, nd, q});
+            if (p.rank_dm)
+                for (uint32_t d = d0; d < d0 + nd; ++d) want.push_back({d, 1u, 3u});
+            else
+                want.push_back({d0, nd, 3u});
+        }
+    CHECK(want.size() == p.presort_launches.size(), "presort launch count");
+    uint32_t sorted_passes[4] = {0, 0, 0, 0};
+    for (size_t i = 0; i < want.size() && i < p.presort_launches.size(); ++i) {
+        const Plan::PresortLaunch& a = p.presort_launches[i];
+        CHECK(a.dim0 == want[i].dim0 && a.ndims == want[i].ndims && a.pass == want[i].pass, "presort launch %zu", i);
+        // a one-dimension launch inside a group uses its dimension's slot
+        CHECK(a.ndims == G || a.ndims == 1 || a.dim0 + a.ndims == k, "presort launch shape");
+        for (uint32_t d = a.dim0; d < a.dim0 + a.ndims && d < 4; ++d) sorted_passes[d] |= 1u << a.pass;
+    }
+    for (uint32_t d = 0; d < k && !p.large.empty(); ++d) CHECK(sorted_passes[d] == 0xFu, "dimension %u passes", d);
+    const size_t npass = p.presort_launches.size() + p.levels.size();
     CHECK(p.pass_words.size() == npass && npass <= MAX_PASSES, "pass count");
-    for (size_t li = 0; li < p.levels.size(); ++li)
-        CHECK(p.pass_words[4u * k + li] == p.levels[li].tiles * PART_BINS, "split look-back words of level %zu", li);
+    for (size_t i = 0; i < p.presort_launches.size() && p.pass_words.size() == npass; ++i)
+        CHECK(p.pass_words[i] == p.presort_launches[i].ndims * p.presort_tiles * RADIX_HOST, "presort look-back words");
+    for (size_t li = 0; li < p.levels.size() && p.pass_words.size() == npass; ++li)
+        CHECK(p.pass_words[p.presort_launches.size() + li] == p.levels[li].tiles * PART_BINS,
+              "split look-back words of level %zu", li);
     for (uint32_t w : p.pass_words) CHECK(w <= p.lb_words, "look-back words");
     // workspace regions: aligned, in order, disjoint
     const size_t N = p.ntotal;
@@ -243,7 +272,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         {p.o_hist_rank, p.large.size() * k * 4 * RADIX_HOST * 4, "hist_rank"},
         {p.o_hist, (size_t)p.hist_words * 12, "hist"}, {p.o_lb[0], (size_t)p.lb_words * 4, "lb0"},
         {p.o_lb[1], (size_t)p.lb_words * 4, "lb1"}, {p.o_keys, N * k * 4, "keys"}, {p.o_perms, N * k * 4, "perms"},
-        {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, p.rec_words * 8, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
+        {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, std::max(p.rec_words * 2, (size_t)4 * G * N) * 4, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
         {p.o_dimnode, N, "dimnode"}, {p.o_box[0], (size_t)p.box_entries * 32, "box0"},
         {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * KEYSUM_WORDS * 4, "keysum"}, {p.o_piv, (size_t)p.piv_words * 4, "piv"},
         {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}};
