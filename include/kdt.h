@@ -156,7 +156,7 @@ void kdt_release_cached(void);
 typedef struct kdt_tuning {
     uint32_t radix_bits;   /* 0 (planner's choice) or 8..10 */
     uint32_t level_items;  /* 0 (planner's choice), 4 or 8: cap on records per thread of level-sort tiles */
-    uint32_t rank_layout;  /* 0 (planner's choice: 2 when the rank table exceeds 128 MiB), 1 (each dimension's
+    uint32_t rank_layout;  /* 0 (planner's choice: 2 when the largest tree's rank table exceeds 128 MiB), 1 (each dimension's
                               last presort pass writes a point-major rank table) or 2 (it writes one rank array
                               per dimension, which a packing pass turns into the point-major table); never
                               swept by kdt_tune_batched */

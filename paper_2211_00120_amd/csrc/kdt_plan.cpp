@@ -194,9 +194,13 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         p.P = (p.B + p.RB - 1u) / p.RB;
     }
     const uint32_t items_cap = (opt.max_items == 4 || opt.max_items == 8) ? opt.max_items : 8u;
-    // rank table layout (k = 1 scatters nothing: the only dimension is the root's)
+    // rank table layout (k = 1 scatters nothing: the only dimension is the
+    // root's); the tiles of one tree run together, so the largest tree's
+    // table is what the scatters of a pass spread over
+    uint32_t nmax = 0;
+    for (uint32_t t : p.large) nmax = std::max(nmax, n[t]);
     p.rank_dm = k >= 2 && !p.large.empty() &&
-                (opt.rank_layout == 2 || (opt.rank_layout == 0 && p.ntotal * k * 4 > RANK_DM_BYTES));
+                (opt.rank_layout == 2 || (opt.rank_layout == 0 && (uint64_t)nmax * k * 4 > RANK_DM_BYTES));
     const uint32_t NB = 1u << p.RB;
 
     // per-tree shares of the whole-array steps

@@ -28,10 +28,11 @@ struct PlanOptions {
     uint32_t rank_layout = 0;  // 1: point-major rank table, 2: per-dimension rank arrays + packing pass
 };
 
-// Rank tables larger than this are scattered into per-dimension arrays and
-// then packed (random 4-byte writes that leave a line partly written cost
-// about twice as much as ones that, over the pass, fill it); smaller ones
-// stay resident in the last-level cache and are written point-major.
+// A tree whose rank table is larger than this has its ranks scattered into
+// per-dimension arrays and then packed (random 4-byte writes that leave a
+// line partly written cost about twice as much as ones that, over the pass,
+// fill it); smaller tables stay in the last-level cache while their tree's
+// tiles run and are written point-major.
 constexpr uint64_t RANK_DM_BYTES = 128ull << 20;
 
 // One iteration run as digit passes over every tree that still has subtrees

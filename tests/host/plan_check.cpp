@@ -284,11 +284,13 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     CHECK(end <= p.total && p.total % WS_ALIGN == 0, "total");
     CHECK(p.rec_words >= N * k && p.rec_words >= 2 * N, "record words");
     // rank layout: per-dimension arrays (in the ranks region) packed into the
-    // second record buffer, for k >= 2 only, when forced or when the
-    // point-major table would exceed RANK_DM_BYTES
+    // second record buffer, for k >= 2 only, when forced or when the largest
+    // tree's point-major table would exceed RANK_DM_BYTES
     {
+        uint64_t nmax = 0;
+        for (uint32_t t : p.large) nmax = std::max<uint64_t>(nmax, n[t]);
         const bool want = k >= 2 && !p.large.empty() &&
-                          (opt.rank_layout == 2 || (opt.rank_layout == 0 && (uint64_t)N * k * 4 > RANK_DM_BYTES));
+                          (opt.rank_layout == 2 || (opt.rank_layout == 0 && nmax * k * 4 > RANK_DM_BYTES));
         CHECK(p.rank_dm == want, "rank layout (k %u, layout %u, N %zu)", k, opt.rank_layout, N);
     }
     // the uploaded tables hold the host lists
