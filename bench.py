@@ -183,9 +183,9 @@ def run_batched(args, data, mode, cfg):
                           stream=stream)
 
     if args.autotune:
-        rb, items, tms = kdt.tune_batched(d_pts, offsets, mode, reps=2, workspace=ws, stream=stream)
-        cfg["tuned"] = {"radix_bits": rb, "level_items": items}
-        print(f"# autotune: radix {rb} items {items} ({tms:.3f} ms)", file=sys.stderr, flush=True)
+        rb, items, pdims, tms = kdt.tune_batched(d_pts, offsets, mode, reps=2, workspace=ws, stream=stream)
+        cfg["tuned"] = {"radix_bits": rb, "level_items": items, "presort_dims": pdims}
+        print(f"# autotune: radix {rb} items {items} presort dims {pdims} ({tms:.3f} ms)", file=sys.stderr, flush=True)
     # per-kernel breakdown from profiled eager builds on the side stream
     with torch.cuda.stream(stream):
         for _ in range(max(args.warmup, 1)):
@@ -457,7 +457,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--autotune", action="store_true",
-                    help="before warm-up, let kdt_tune_batched pick the digit width and tile size for this input")
+                    help="before warm-up, let kdt_tune_batched pick the digit width, tile size and presort grouping for this input")
     ap.add_argument("--requests", type=int, default=2000, help="serving: trace length")
     ap.add_argument("--inflight", type=int, default=4, help="serving: batches on the device at once")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -524,9 +524,9 @@ def main():
 
     if args.autotune:
         import numpy as np
-        rb, items, tms = kdt.tune_batched(d_pts, np.array([0, n], np.uint32), mode, reps=3, workspace=ws)
-        cfg["tuned"] = {"radix_bits": rb, "level_items": items}
-        print(f"# autotune: radix {rb} items {items} ({tms:.3f} ms)", file=sys.stderr, flush=True)
+        rb, items, pdims, tms = kdt.tune_batched(d_pts, np.array([0, n], np.uint32), mode, reps=3, workspace=ws)
+        cfg["tuned"] = {"radix_bits": rb, "level_items": items, "presort_dims": pdims}
+        print(f"# autotune: radix {rb} items {items} presort dims {pdims} ({tms:.3f} ms)", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         step()

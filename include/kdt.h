@@ -142,8 +142,10 @@ void kdt_release_cached(void);
 /*
  * Autotuner.  The level sorts can run with 8-, 9- or 10-bit digits (fewer
  * bits: more passes, smaller histograms and look-back tables) and with tiles
- * of 512 x 4 or 512 x 8 records.  Without tuning the planner picks the
- * fewest passes and the largest tile the level's subtrees fill.
+ * of 512 x 4 or 512 x 8 records; the presort's digit passes can run one
+ * dimension per launch or all dimensions per launch.  Without tuning the
+ * planner picks the fewest passes, the largest tile the level's subtrees
+ * fill, and all dimensions per launch.
  * kdt_tune_batched times a whole kdt_build_batched of the given batch (in
  * device memory) for every combination, `reps` builds each after one
  * warm-up, and records the fastest for builds of this k, split rule and
@@ -160,6 +162,9 @@ typedef struct kdt_tuning {
                               last presort pass writes a point-major rank table) or 2 (it writes one rank array
                               per dimension, which a packing pass turns into the point-major table); never
                               swept by kdt_tune_batched */
+    uint32_t presort_dims; /* 0 (planner's choice: all k) or 1..4 (clamped to k): dimensions whose presort
+                              digit passes share a launch, each with its own look-back chain (a last pass
+                              that scatters into per-dimension arrays always runs one dimension per launch) */
     double ms;             /* kdt_tune_batched: time of one build with this choice */
 } kdt_tuning;
 
@@ -172,7 +177,7 @@ kdt_status kdt_tuning_get(uint32_t k, int dim_mode, uint32_t rank_bits, kdt_tuni
 kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kdt_tuning* t);
 
 /* Text file of recorded choices, one "k dim_mode rank_bits radix_bits
- * level_items rank_layout" line each; load merges into the current table and fails
+ * level_items rank_layout presort_dims" line each; load merges into the current table and fails
  * without changing it on a malformed file. */
 kdt_status kdt_tuning_save(const char* path);
 kdt_status kdt_tuning_load(const char* path);

@@ -490,10 +490,10 @@ kdt_status batched_plan(const uint32_t* h_offsets, uint32_t C, uint32_t k, bool 
     for (uint32_t c = 0; c < C; ++c) n[c] = h_offsets[c + 1] - h_offsets[c];
     // the tuning in effect is part of the key
     const PlanOptions opt = tuned_options(k, widest, plan_rank_bits(n));
-    std::string key(20 + (size_t)(C + 1) * 4, '\0');
-    const uint32_t head[5] = {k, widest ? 1u : 0u, opt.radix_bits, opt.max_items, opt.rank_layout};
-    memcpy(&key[0], head, 20);
-    memcpy(&key[20], h_offsets, (size_t)(C + 1) * 4);
+    std::string key(24 + (size_t)(C + 1) * 4, '\0');
+    const uint32_t head[6] = {k, widest ? 1u : 0u, opt.radix_bits, opt.max_items, opt.rank_layout, opt.presort_dims};
+    memcpy(&key[0], head, 24);
+    memcpy(&key[24], h_offsets, (size_t)(C + 1) * 4);
     std::lock_guard<std::mutex> lk(g_plan_mu);
     std::shared_ptr<CachedPlan> cp;
     auto it = g_plans.find(key);
@@ -732,6 +732,7 @@ kdt_status kdt_tune_batched(const float* d_points, const uint32_t* h_offsets, ui
     best->radix_bits = chosen.radix_bits;
     best->level_items = chosen.max_items;
     best->rank_layout = chosen.rank_layout;
+    best->presort_dims = chosen.presort_dims;
     best->ms = best_ms;
     return KDT_OK;
 }
@@ -748,6 +749,7 @@ kdt_status kdt_tuning_get(uint32_t k, int dim_mode, uint32_t rank_bits, kdt_tuni
     out->radix_bits = o.radix_bits;
     out->level_items = o.max_items;
     out->rank_layout = o.rank_layout;
+    out->presort_dims = o.presort_dims;
     return KDT_OK;
 }
 
@@ -755,14 +757,16 @@ kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kd
 {
     if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
     if (!t || rank_bits > 32 || (t->radix_bits && (t->radix_bits < 8 || t->radix_bits > 10)) ||
-        (t->level_items && t->level_items != 4 && t->level_items != 8) || t->rank_layout > 2) {
-        set_err("tuning must have radix_bits 0 or 8..10, level_items 0, 4 or 8 and rank_layout 0..2");
+        (t->level_items && t->level_items != 4 && t->level_items != 8) || t->rank_layout > 2 || t->presort_dims > 4) {
+        set_err("tuning must have radix_bits 0 or 8..10, level_items 0, 4 or 8, rank_layout 0..2 and "
+                "presort_dims 0..4");
         return KDT_EINVAL;
     }
     PlanOptions o;
     o.radix_bits = t->radix_bits;
     o.max_items = t->level_items;
     o.rank_layout = t->rank_layout;
+    o.presort_dims = t->presort_dims;
     set_tuned_options(k, dim_mode == KDT_DIM_WIDEST, rank_bits, o);
     return KDT_OK;
 }

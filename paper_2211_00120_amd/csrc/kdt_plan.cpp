@@ -54,12 +54,14 @@ std::vector<PlanOptions> tuning_candidates()
 {
     std::vector<PlanOptions> c;
     for (uint32_t rb : {8u, 9u, 10u})
-        for (uint32_t items : {4u, 8u}) {
-            PlanOptions o;
-            o.radix_bits = rb;
-            o.max_items = items;
-            c.push_back(o);
-        }
+        for (uint32_t items : {4u, 8u})
+            for (uint32_t dims : {1u, PRESORT_GROUP}) {
+                PlanOptions o;
+                o.radix_bits = rb;
+                o.max_items = items;
+                o.presort_dims = dims;
+                c.push_back(o);
+            }
     return c;
 }
 
@@ -82,15 +84,16 @@ void clear_tuning()
     g_tune.clear();
 }
 
-// One line per entry: "k widest bits radix_bits max_items rank_layout".
+// One line per entry: "k widest bits radix_bits max_items rank_layout presort_dims".
 bool save_tuning(const char* path)
 {
     FILE* f = fopen(path, "w");
     if (!f) return false;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto& kv : g_tune)
-        fprintf(f, "%u %d %u %u %u %u\n", std::get<0>(kv.first), std::get<1>(kv.first) ? 1 : 0,
-                std::get<2>(kv.first), kv.second.radix_bits, kv.second.max_items, kv.second.rank_layout);
+        fprintf(f, "%u %d %u %u %u %u %u\n", std::get<0>(kv.first), std::get<1>(kv.first) ? 1 : 0,
+                std::get<2>(kv.first), kv.second.radix_bits, kv.second.max_items, kv.second.rank_layout,
+                kv.second.presort_dims);
     return fclose(f) == 0;
 }
 
@@ -99,12 +102,12 @@ bool load_tuning(const char* path)
     FILE* f = fopen(path, "r");
     if (!f) return false;
     std::map<std::tuple<uint32_t, bool, uint32_t>, PlanOptions> t;
-    unsigned k, w, bits, rb, items, layout;
+    unsigned k, w, bits, rb, items, layout, dims;
     int r;
     bool ok = true;
-    while ((r = fscanf(f, "%u %u %u %u %u %u", &k, &w, &bits, &rb, &items, &layout)) == 6) {
+    while ((r = fscanf(f, "%u %u %u %u %u %u %u", &k, &w, &bits, &rb, &items, &layout, &dims)) == 7) {
         if (k < 1 || k > 4 || w > 1 || bits > 32 || (rb && (rb < 8 || rb > 10)) || (items && items != 4 && items != 8) ||
-            layout > 2) {
+            layout > 2 || dims > 4) {
             ok = false;
             break;
         }
@@ -112,6 +115,7 @@ bool load_tuning(const char* path)
         o.radix_bits = rb;
         o.max_items = items;
         o.rank_layout = layout;
+        o.presort_dims = dims;
         t[std::make_tuple((uint32_t)k, w == 1u, (uint32_t)bits)] = o;
     }
     if (r != EOF) ok = false;
@@ -153,7 +157,9 @@ uint32_t first_tail_level(uint32_t n)
 Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const PlanOptions& given)
 {
     const PlanOptions opt =
-        (given.radix_bits || given.max_items || given.rank_layout) ? given : tuned_options(k, widest, plan_rank_bits(n));
+        (given.radix_bits || given.max_items || given.rank_layout || given.presort_dims)
+            ? given
+            : tuned_options(k, widest, plan_rank_bits(n));
     Plan p;
     p.k = k;
     p.widest = widest;
@@ -296,7 +302,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     // presort launches: passes 0-2 of a group of dimensions share a launch;
     // so does the last pass, unless it scatters into per-dimension arrays
     // too large for the cache (several at once only evict each other)
-    p.presort_group = std::min(k, PRESORT_GROUP);
+    p.presort_group = std::min(k, opt.presort_dims ? std::min(opt.presort_dims, PRESORT_GROUP) : PRESORT_GROUP);
     if (!p.large.empty())
         for (uint32_t d0 = 0; d0 < k; d0 += p.presort_group) {
             const uint32_t nd = std::min(p.presort_group, k - d0);

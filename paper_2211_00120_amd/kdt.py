@@ -89,7 +89,7 @@ class Result(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("radix_bits", ctypes.c_uint32), ("level_items", ctypes.c_uint32), ("rank_layout", ctypes.c_uint32),
-                ("ms", ctypes.c_double)]
+                ("presort_dims", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
 
 class KdtError(RuntimeError):
@@ -230,8 +230,9 @@ def build_batched(points, offsets, mode: int = ROUND_ROBIN, *, tree=None, perm=N
 
 
 def tune_batched(points, offsets, mode: int = ROUND_ROBIN, reps: int = 3, workspace=None, stream=None):
-    """kdt_tune_batched: time every digit-width / tile choice on this batch
-    and record the fastest; returns (radix_bits, level_items, ms)."""
+    """kdt_tune_batched: time every digit-width / tile / presort-grouping
+    choice on this batch and record the fastest; returns (radix_bits,
+    level_items, presort_dims, ms)."""
     import torch
     _check_points(points)
     n, k = points.shape
@@ -245,7 +246,7 @@ def tune_batched(points, offsets, mode: int = ROUND_ROBIN, reps: int = 3, worksp
                                 _stream(stream), ctypes.byref(best))
     if rc != OK:
         raise KdtError(rc, "kdt_tune_batched")
-    return best.radix_bits, best.level_items, best.ms
+    return best.radix_bits, best.level_items, best.presort_dims, best.ms
 
 
 def tuning_get(k: int, mode: int, rank_bits: int):
@@ -253,11 +254,12 @@ def tuning_get(k: int, mode: int, rank_bits: int):
     rc = lib().kdt_tuning_get(k, mode, rank_bits, ctypes.byref(t))
     if rc != OK:
         raise KdtError(rc, "kdt_tuning_get")
-    return t.radix_bits, t.level_items, t.rank_layout
+    return t.radix_bits, t.level_items, t.rank_layout, t.presort_dims
 
 
-def tuning_set(k: int, mode: int, rank_bits: int, radix_bits: int, level_items: int, rank_layout: int = 0):
-    t = Tuning(radix_bits, level_items, rank_layout, 0.0)
+def tuning_set(k: int, mode: int, rank_bits: int, radix_bits: int, level_items: int, rank_layout: int = 0,
+               presort_dims: int = 0):
+    t = Tuning(radix_bits, level_items, rank_layout, presort_dims, 0.0)
     rc = lib().kdt_tuning_set(k, mode, rank_bits, ctypes.byref(t))
     if rc != OK:
         raise KdtError(rc, "kdt_tuning_set")

@@ -236,7 +236,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     // arrays (then one launch per dimension); every launch's look-back words
     // cover its dimensions
     const uint32_t G = p.presort_group;
-    CHECK(G >= 1 && G <= PRESORT_GROUP && G <= k, "presort group %u", G);
+    CHECK(G == std::min(k, opt.presort_dims ? std::min(opt.presort_dims, PRESORT_GROUP) : PRESORT_GROUP),
+          "presort group %u (option %u)", G, opt.presort_dims);
     std::vector<Plan::PresortLaunch> want;
     if (!p.large.empty())
         for (uint32_t d0 = 0; d0 < k; d0 += G) {
@@ -337,6 +338,7 @@ int main()
         if (rep % 4 == 1) opt.radix_bits = 8 + (uint32_t)(u(rng) * 3);
         if (rep % 5 == 2) opt.max_items = 4;
         opt.rank_layout = rep % 3;
+        opt.presort_dims = rep % 5;
         check_plan(n, 1 + rep % 4, rep % 2 == 1, opt);
     }
     if (g_fail) return 1;

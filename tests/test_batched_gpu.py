@@ -265,19 +265,20 @@ def test_tuner_choices_give_identical_trees():
         bits = int(np.ceil(np.log2(max(sizes))))
         for rb in (8, 9, 10):
             for items in (4, 8):
-                _say(f"case tuner: radix {rb} items {items}")
-                kdt.tuning_set(3, kdt.ROUND_ROBIN, bits, rb, items)
-                got = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
-                assert got[3] == kdt.OK
-                assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
-                assert got[0].tobytes() == ref[0].tobytes()
+                for pdims in (1, 2, 4):
+                    _say(f"case tuner: radix {rb} items {items} presort dims {pdims}")
+                    kdt.tuning_set(3, kdt.ROUND_ROBIN, bits, rb, items, 0, pdims)
+                    got = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
+                    assert got[3] == kdt.OK
+                    assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+                    assert got[0].tobytes() == ref[0].tobytes()
         kdt.tuning_clear()
         t = torch.from_numpy(pts).to(DEV)
-        rb, items, ms = kdt.tune_batched(t, offsets, kdt.ROUND_ROBIN, reps=2)
+        rb, items, pdims, ms = kdt.tune_batched(t, offsets, kdt.ROUND_ROBIN, reps=2)
         torch.cuda.synchronize()
-        _say(f"tuner picked radix {rb} items {items} at {ms:.3f} ms")
-        assert rb in (8, 9, 10) and items in (4, 8) and ms > 0
-        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, bits) == (rb, items, 0)
+        _say(f"tuner picked radix {rb} items {items} presort dims {pdims} at {ms:.3f} ms")
+        assert rb in (8, 9, 10) and items in (4, 8) and pdims in (1, 4) and ms > 0
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, bits) == (rb, items, 0, pdims)
         got = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
         assert np.array_equal(got[1], ref[1])
         for c in range(len(sizes)):

@@ -173,31 +173,33 @@ def test_server_argument_errors():
 def test_tuning_table_round_trip(tmp_path):
     kdt.tuning_clear()
     try:
-        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (0, 0, 0)
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (0, 0, 0, 0)
         kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 10, 4)
-        kdt.tuning_set(4, kdt.WIDEST, 27, 8, 8, 2)
-        kdt.tuning_set(2, kdt.WIDEST, 20, 0, 0, 1)
-        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0)
+        kdt.tuning_set(4, kdt.WIDEST, 27, 8, 8, 2, 1)
+        kdt.tuning_set(2, kdt.WIDEST, 20, 0, 0, 1, 4)
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0, 0)
         with pytest.raises(kdt.KdtError):
             kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 11, 4)
         with pytest.raises(kdt.KdtError):
             kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 5)
         with pytest.raises(kdt.KdtError):
             kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 4, 3)
+        with pytest.raises(kdt.KdtError):
+            kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 4, 0, 5)
         path = str(tmp_path / "tune.txt")
         kdt.tuning_save(path)
         kdt.tuning_clear()
-        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (0, 0, 0)
+        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (0, 0, 0, 0)
         kdt.tuning_load(path)
-        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (8, 8, 2)
-        assert kdt.tuning_get(2, kdt.WIDEST, 20) == (0, 0, 1)
-        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0)
-        for text in ("3 0 24 12 4 0\n", "3 0 24 8 4 3\n", "3 0 24 8 4\n"):
+        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (8, 8, 2, 1)
+        assert kdt.tuning_get(2, kdt.WIDEST, 20) == (0, 0, 1, 4)
+        assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0, 0)
+        for text in ("3 0 24 12 4 0 0\n", "3 0 24 8 4 3 0\n", "3 0 24 8 4 0 5\n", "3 0 24 8 4 0\n"):
             bad = tmp_path / "bad.txt"
             bad.write_text(text)
             with pytest.raises(kdt.KdtError):
                 kdt.tuning_load(str(bad))
-            assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0)     # unchanged by the failed load
+            assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0, 0)     # unchanged by the failed load
         # sizes hold every choice: setting a tuning never grows them
         before = kdt.workspace_bytes(10_000_000, 3, kdt.ROUND_ROBIN)
         kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 8)

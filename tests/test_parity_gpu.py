@@ -133,7 +133,7 @@ def test_rank_layouts(layout, mode, k):
     kdt.tuning_clear()
     try:
         kdt.tuning_set(k, mode, bits, 0, 0, layout)
-        assert kdt.tuning_get(k, mode, bits) == (0, 0, layout)
+        assert kdt.tuning_get(k, mode, bits) == (0, 0, layout, 0)
         _assert_same(pts, mode, f"rank-layout-{layout}")
     finally:
         kdt.tuning_clear()
