@@ -42,7 +42,10 @@ constexpr uint32_t PRESORT_GROUP = KDT_PRESORT_GROUP;
 #define KDT_PART_ITEMS 8
 #endif
 constexpr int PART_ITEMS = KDT_PART_ITEMS;
-constexpr uint32_t HIST_TILE = 16384;      // keys per workgroup of the pivot selects
+#ifndef KDT_HIST_TILE
+#define KDT_HIST_TILE 8192
+#endif
+constexpr uint32_t HIST_TILE = KDT_HIST_TILE;  // keys per workgroup of the pivot selects
 constexpr uint32_t PIVOT_SEGS = 4;         // subtrees per pivot workgroup (one wave each)
 constexpr int TAIL_THREADS = 512;          // subtree tail: 512 threads x 4 slots = up to 2048 points
 constexpr int TAIL_ITEMS = 4;

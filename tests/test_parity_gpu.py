@@ -119,22 +119,25 @@ def test_constant_digit_passes(mode):
         _assert_same(np.ascontiguousarray(pts[:, cols]), mode, f"digit-pattern-{cols}")
 
 
+@pytest.mark.parametrize("pdims", [0, 1, 2])
 @pytest.mark.parametrize("layout", [1, 2])
 @pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
 @pytest.mark.parametrize("k", [2, 3, 4])
-def test_rank_layouts(layout, mode, k):
+def test_rank_layouts(pdims, layout, mode, k):
     """Both rank-table layouts (the last presort passes scatter point-major
     records; or per-dimension arrays that a packing pass turns into records)
-    build the oracle's tree.  The planner picks by the table's size, so each
-    layout is forced through the tuning table of this size class."""
+    build the oracle's tree, whatever number of dimensions share a presort
+    launch (0: the planner's, all of them).  The planner picks the layout by
+    the table's size, so each is forced through the tuning table of this
+    size class."""
     n = 150_001
     bits = (n - 1).bit_length()
     pts = workloads.grid(n, k, 300 + k, levels=9)
     kdt.tuning_clear()
     try:
-        kdt.tuning_set(k, mode, bits, 0, 0, layout)
-        assert kdt.tuning_get(k, mode, bits) == (0, 0, layout, 0)
-        _assert_same(pts, mode, f"rank-layout-{layout}")
+        kdt.tuning_set(k, mode, bits, 0, 0, layout, pdims)
+        assert kdt.tuning_get(k, mode, bits) == (0, 0, layout, pdims)
+        _assert_same(pts, mode, f"rank-layout-{layout}-presort-dims-{pdims}")
     finally:
         kdt.tuning_clear()
 
