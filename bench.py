@@ -49,12 +49,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_2211_00120_amd/csrc/kdt_kernels.hip", "paper_2211_00120_amd/csrc/kdt_tail.hip",
-                  "paper_2211_00120_amd/csrc/kdt_common.h", "paper_2211_00120_amd/csrc/kdt_device.h",
-                  "paper_2211_00120_amd/csrc/kdt_layout.h", "paper_2211_00120_amd/csrc/kdt_kernels.h",
-                  "paper_2211_00120_amd/csrc/kdt_sweep.h", "paper_2211_00120_amd/csrc/kdt_level.h",
-                  "paper_2211_00120_amd/csrc/kdt_level_k1.hip", "paper_2211_00120_amd/csrc/kdt_level_k2.hip",
-                  "paper_2211_00120_amd/csrc/kdt_level_k3.hip", "paper_2211_00120_amd/csrc/kdt_level_k4.hip"]
+# every library source: kernels, tile constants, planner and launch sequence
+# all shape what a kernel moves
+KERNEL_SOURCES = sorted(os.path.join("paper_2211_00120_amd", "csrc", f)
+                        for f in os.listdir(os.path.join(ROOT, "paper_2211_00120_amd", "csrc"))
+                        if f.endswith((".hip", ".h", ".cpp")))
 METRIC = "k-d build Mpoints/s + achieved HBM GB/s; batched vs per-cloud, bit-exact"
 
 
