@@ -84,10 +84,11 @@ kdt_status check_launch(const char* what)
 // hipEvents on the build's stream and tagged with its kind and algorithmic
 // bytes (the bytes the step must move by definition).
 enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
-            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_COUNT };
+            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_BUCKET, KIND_WINDOW, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
                                             "k_level0", "k_level_select", "k_level_pivot", "k_level_part",
-                                            "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_pack"};
+                                            "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_pack",
+                                            "k_rank_bucket", "k_rank_window"};
 
 struct ProfRec {
     int kind;
@@ -215,6 +216,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     uint32_t* ranks = (uint32_t*)(ws + p.o_ranks);
     uint32_t* recbase = (uint32_t*)(ws + p.o_rec);
     uint32_t* piv = (uint32_t*)(ws + p.o_piv);
+    uint32_t* wcount = (uint32_t*)(ws + p.o_wcount);
     uint32_t* rec[2] = {recbase, recbase + p.rec_words};
     const uint32_t ntotal = (uint32_t)p.ntotal;
     const uint32_t nlarge_trees = (uint32_t)p.large.size();
@@ -255,7 +257,8 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
 
     if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, [&] {
             launch_init(dstatus, counters, hist_rank, nlarge_trees * k * 4 * RADIX_HOST, lb[0],
-                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, o.bbox, nlarge_trees, st);
+                        pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, wcount,
+                        p.rank_dm ? k * RANK_MAX_WIN : 0u, o.bbox, nlarge_trees, st);
         }))
         return s;
 
@@ -327,7 +330,8 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 a.lb_zero_n = next_words(q);
                 a.counter = counters + q;
                 a.perms = perms;
-                a.rank_table = ranks;
+                // per-dimension arrays are written by the windowed scatter below
+                a.rank_table = p.rank_dm ? nullptr : ranks;
                 a.rank_stride = p.rank_dm ? 1u : k;
                 a.rank_dstride = p.rank_dm ? (size_t)ntotal : 1u;
                 a.dimnode = widest ? o.dimnode : nullptr;
@@ -351,6 +355,36 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     return s;
             }
             ++q;
+            if (p.rank_dm && ps == 3) {
+                // the dimensions' ranks into their arrays, window by window;
+                // the buckets take the ping-pong of the dimension just sorted
+                for (uint32_t d = d0; d < d0 + nd; ++d) {
+                    if (!widest && d == 0) continue;   // every tree's root dimension: no ranks needed
+                    RankBucketArgs b{};
+                    b.sh = shares(p, p.presort, p.t_presort, ws);
+                    b.perm = perms + (size_t)d * ntotal;
+                    b.pairs = recbase + 4 * (size_t)(d % p.presort_group) * ntotal;
+                    b.wcount = wcount + (size_t)d * RANK_MAX_WIN;
+                    b.wbits = p.rank_wbits;
+                    b.nwin = p.rank_nwin;
+                    b.dimnode = widest ? o.dimnode : nullptr;
+                    b.dim = d;
+                    b.status = dstatus;
+                    if (kdt_status s = run_kernel(st, KIND_BUCKET, nlarge * 12.0,
+                                                  [&] { launch_rank_bucket(b, p.presort_tiles, st); }))
+                        return s;
+                    RankWindowArgs wa{};
+                    wa.pairs = b.pairs;
+                    wa.wcount = b.wcount;
+                    wa.dm = ranks + (size_t)d * ntotal;
+                    wa.wbits = p.rank_wbits;
+                    wa.nwin = p.rank_nwin;
+                    wa.chunks = std::max(1u, (1u << p.rank_wbits) / RANK_WIN_CHUNK);
+                    wa.ntotal = ntotal;
+                    if (kdt_status s = run_kernel(st, KIND_WINDOW, nlarge * 12.0, [&] { launch_rank_window(wa, st); }))
+                        return s;
+                }
+            }
         }
 
         // per-dimension ranks -> point-major records in rec[1], which is free

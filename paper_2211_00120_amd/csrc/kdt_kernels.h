@@ -157,10 +157,36 @@ struct TailArgs {
 void launch_set_word(uint32_t* dst, uint32_t value, hipStream_t st);
 void launch_copy_word(uint32_t* dst, const uint32_t* src, hipStream_t st);
 void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1, uint32_t* z2, uint32_t n2,
-                 uint32_t* z3, uint32_t n3, uint32_t* bbox, uint32_t nbox, hipStream_t st);
+                 uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* bbox, uint32_t nbox, hipStream_t st);
 void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st);
 void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st);
+// Windowed scatter of one dimension's ranks into its per-dimension array
+// (see k_rank_bucket).  Windows of 2^wbits global indices, at most
+// RANK_MAX_WIN of them; each bucket holds up to 2^wbits (index, rank) pairs.
+
+struct RankBucketArgs {
+    Shares sh;              // presort shares: tiles of PRESORT_TILE ranks per tree
+    const uint32_t* perm;   // this dimension's rank -> local index, [off + rank]
+    uint32_t* pairs;        // bucket w: uint2 (global index, rank) at [(w << wbits) + e]
+    uint32_t* wcount;       // pairs in each bucket (zero before the launch)
+    uint32_t wbits, nwin;
+    const uint8_t* dimnode; // split-widest: a tree's root dimension is dimnode[off]; null: 0
+    uint32_t dim;
+    uint32_t* status;
+};
+
+struct RankWindowArgs {
+    const uint32_t* pairs;
+    const uint32_t* wcount;
+    uint32_t* dm;           // this dimension's rank array, [global index]
+    uint32_t wbits, nwin, chunks;   // chunks = 2^wbits / RANK_WIN_CHUNK (at least 1)
+    uint32_t ntotal;
+};
+
+void launch_rank_bucket(const RankBucketArgs& a, uint32_t tiles, hipStream_t st);
+void launch_rank_window(const RankWindowArgs& a, hipStream_t st);
+
 // Per-dimension rank arrays dm[d*ntotal + i] -> point-major records
 // pm[i*k + d], i < ntotal.
 void launch_rank_pack(int k, const uint32_t* dm, uint32_t* pm, uint32_t ntotal, hipStream_t st);

@@ -43,7 +43,7 @@ namespace kdt {
 
 __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1,
                                                 uint32_t* z2, uint32_t n2, uint32_t* z3, uint32_t n3,
-                                                uint32_t* bbox, uint32_t nbox)
+                                                uint32_t* z4, uint32_t n4, uint32_t* bbox, uint32_t nbox)
 {
     const uint32_t gid = blockIdx.x * BLOCK + threadIdx.x;
     if (gid == 0) *status = 0u;
@@ -51,6 +51,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* coun
     zero_range(z1, n1);
     zero_range(z2, n2);
     zero_range(z3, n3);
+    zero_range(z4, n4);
     // per-tree scene boxes as running (min, max) of orderable keys
     // per-tree key summaries: running minima and ANDs start all ones, maxima
     // and ORs all zeros
@@ -242,13 +243,103 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
             if (LAST) {
                 perm_out[off + pos] = r.y;
-                if (to_table) a.rank_table[(off + r.y) * a.rank_stride + dim * a.rank_dstride] = pos;
+                if (to_table && a.rank_table) a.rank_table[(off + r.y) * a.rank_stride + dim * a.rank_dstride] = pos;
             } else {
                 reinterpret_cast<uint2*>(kvout)[off + pos] = make_uint2(r.x, r.y);
             }
         });
     // clear the next pass's look-back words (nothing waits on these stores)
     zero_range(a.lb_zero, a.lb_zero_n);
+}
+
+// ------------------------------------------------------ windowed rank scatter
+
+// The per-dimension rank arrays of a large tree are written in two steps
+// instead of one random scatter: k_rank_bucket reads a dimension's rank ->
+// index list and appends each (global index, rank) pair to the bucket of its
+// index window (2^wbits indices; a tile counts its pairs per window in LDS
+// and reserves room with one atomic per window), then k_rank_window writes
+// the ranks one window at a time, so that the lines it writes stay in cache
+// until they are full.  The order of pairs inside a bucket is immaterial.
+__global__ void __launch_bounds__(SWEEP_THREADS) k_rank_bucket(RankBucketArgs a)
+{
+    constexpr int ITEMS = PRESORT_ITEMS;
+    __shared__ uint32_t cnt[RANK_MAX_WIN];
+    __shared__ uint32_t base[RANK_MAX_WIN];
+    TreeStep st;
+    TreeInfo ti;
+    find_share(a.sh, blockIdx.x, st, ti);
+    const size_t off = ti.off;
+    // a tree's root dimension has no rank array (iteration 0 uses positions)
+    if (a.dim == (a.dimnode ? (uint32_t)a.dimnode[off] : 0u)) return;
+    for (uint32_t x = threadIdx.x; x < a.nwin; x += SWEEP_THREADS) cnt[x] = 0u;
+    __syncthreads();
+    const uint32_t start = (blockIdx.x - st.tile0) * PRESORT_TILE;
+    const uint32_t m = min(PRESORT_TILE, ti.n - start);
+    uint32_t gi[ITEMS], slot[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t j = (uint32_t)i * SWEEP_THREADS + threadIdx.x;
+        gi[i] = 0xFFFFFFFFu;
+        slot[i] = 0u;
+        if (j < m) {
+            const uint32_t idx = a.perm[off + start + j];
+            if (in_bounds(idx, ti.n, a.status)) {
+                gi[i] = (uint32_t)off + idx;
+                slot[i] = atomicAdd(&cnt[gi[i] >> a.wbits], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < a.nwin; x += SWEEP_THREADS) {
+        const uint32_t c = cnt[x];
+        base[x] = c ? atomicAdd(&a.wcount[x], c) : 0u;
+    }
+    __syncthreads();
+    const uint32_t W = 1u << a.wbits;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        if (gi[i] == 0xFFFFFFFFu) continue;
+        const uint32_t w = gi[i] >> a.wbits;
+        const uint32_t e = base[w] + slot[i];
+        if (!in_bounds(e, W, a.status)) continue;
+        const uint32_t j = (uint32_t)i * SWEEP_THREADS + threadIdx.x;
+        reinterpret_cast<uint2*>(a.pairs)[((size_t)w << a.wbits) + e] = make_uint2(gi[i], start + j);
+    }
+}
+
+// One chunk of RANK_WIN_CHUNK pairs of one window's bucket per workgroup.
+// Workgroups are dispatched to the 8 XCDs round-robin, so workgroup b takes
+// a window w = b mod 8 (mod 8): the lines of a window are then all written
+// through one XCD's L2, which holds them until they are full.
+__global__ void __launch_bounds__(BLOCK) k_rank_window(RankWindowArgs a)
+{
+    constexpr uint32_t PER = RANK_WIN_CHUNK / BLOCK;
+    const uint32_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
+    const uint32_t w = x + 8u * (j / a.chunks), c = j % a.chunks;
+    if (w >= a.nwin) return;
+    const uint32_t n = min(a.wcount[w], 1u << a.wbits);
+    const uint2* pr = reinterpret_cast<const uint2*>(a.pairs) + ((size_t)w << a.wbits);
+    uint2 v[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t e = c * RANK_WIN_CHUNK + j * BLOCK + threadIdx.x;
+        v[j] = e < n ? pr[e] : make_uint2(0xFFFFFFFFu, 0u);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j)
+        if (v[j].x < a.ntotal) a.dm[v[j].x] = v[j].y;
+}
+
+void launch_rank_bucket(const RankBucketArgs& a, uint32_t tiles, hipStream_t st)
+{
+    if (tiles) k_rank_bucket<<<tiles, SWEEP_THREADS, 0, st>>>(a);
+}
+
+void launch_rank_window(const RankWindowArgs& a, hipStream_t st)
+{
+    const uint32_t grid = ((a.nwin + 7u) / 8u) * 8u * a.chunks;
+    if (grid) k_rank_window<<<grid, BLOCK, 0, st>>>(a);
 }
 
 // ------------------------------------------------------------- rank packing
@@ -457,16 +548,17 @@ void launch_set_word(uint32_t* dst, uint32_t value, hipStream_t st) { k_set_word
 void launch_copy_word(uint32_t* dst, const uint32_t* src, hipStream_t st) { k_copy_word<<<1, 64, 0, st>>>(dst, src); }
 
 void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1, uint32_t* z2, uint32_t n2,
-                 uint32_t* z3, uint32_t n3, uint32_t* bbox, uint32_t nbox, hipStream_t st)
+                 uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* bbox, uint32_t nbox, hipStream_t st)
 {
     uint32_t big = n1 > n2 ? n1 : n2;
     big = big > n3 ? big : n3;
+    big = big > n4 ? big : n4;
     big = big > MAX_PASSES ? big : MAX_PASSES;
     big = big > nbox * KEYSUM_WORDS ? big : nbox * KEYSUM_WORDS;
     uint32_t grid = ceil_div(big, BLOCK);
     if (grid > 2048) grid = 2048;
     if (grid == 0) grid = 1;
-    k_init<<<grid, BLOCK, 0, st>>>(status, counters, z1, n1, z2, n2, z3, n3, bbox, nbox);
+    k_init<<<grid, BLOCK, 0, st>>>(status, counters, z1, n1, z2, n2, z3, n3, z4, n4, bbox, nbox);
 }
 
 template <int K>

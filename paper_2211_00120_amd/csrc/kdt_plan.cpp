@@ -207,6 +207,18 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     for (uint32_t t : p.large) nmax = std::max(nmax, n[t]);
     p.rank_dm = k >= 2 && !p.large.empty() &&
                 (opt.rank_layout == 2 || (opt.rank_layout == 0 && (uint64_t)nmax * k * 4 > RANK_DM_BYTES));
+    if (p.rank_dm) {
+        // windows of 2^18 indices (2^wbits: at most RANK_MAX_WIN of them,
+        // and at most ntotal indices each, so that the buckets fit the
+        // 4 * ntotal words of a dimension's ping-pong)
+        uint32_t lg = 0, fl = 0;
+        while ((1ull << lg) < p.ntotal) ++lg;
+        while ((2ull << fl) <= p.ntotal) ++fl;
+        uint32_t wb = std::max<uint32_t>(18u, lg > 11u ? lg - 11u : 0u);
+        wb = std::min(wb, fl);
+        p.rank_wbits = wb;
+        p.rank_nwin = (uint32_t)((p.ntotal + (1ull << wb) - 1) >> wb);
+    }
     const uint32_t NB = 1u << p.RB;
 
     // per-tree shares of the whole-array steps
@@ -359,6 +371,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_bbox = take((size_t)p.large.size() * KEYSUM_WORDS * 4);
     p.o_piv = take((size_t)p.piv_words * 4);
     p.o_tables = take(p.tables ? p.blob.size() : 0);
+    p.o_wcount = take((size_t)k * RANK_MAX_WIN * 4);
     p.total = o;
     return p;
 }

@@ -64,7 +64,8 @@ struct Plan {
     std::vector<uint32_t> large;     // trees built by digit passes
     std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
     uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / digits of the pivot selects
-    bool rank_dm = false;            // presorts scatter per-dimension ranks, a pass packs them
+    bool rank_dm = false;            // per-dimension rank arrays (windowed scatter), a pass packs them
+    uint32_t rank_wbits = 0, rank_nwin = 0;  // index windows of the windowed scatter
     uint32_t presort_group = 1;      // dimensions sharing the presort launches of passes 0-2
     struct PresortLaunch {
         uint32_t dim0, ndims, pass;  // digit pass `pass` of dimensions dim0 .. dim0+ndims-1
@@ -85,7 +86,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,
            o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_piv = 0, o_tables = 0,
-           total = 0;
+           o_wcount = 0, total = 0;
     size_t rec_words = 0;            // words per record buffer
 };
 

@@ -42,6 +42,8 @@ constexpr uint32_t PRESORT_GROUP = KDT_PRESORT_GROUP;
 #define KDT_PART_ITEMS 8
 #endif
 constexpr int PART_ITEMS = KDT_PART_ITEMS;
+constexpr uint32_t RANK_MAX_WIN = 2048;      // index windows of the windowed rank scatter
+constexpr uint32_t RANK_WIN_CHUNK = 4096;    // pairs per k_rank_window workgroup
 #ifndef KDT_HIST_TILE
 #define KDT_HIST_TILE 8192
 #endif

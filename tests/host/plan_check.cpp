@@ -276,7 +276,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, std::max(p.rec_words * 2, (size_t)4 * G * N) * 4, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
         {p.o_dimnode, N, "dimnode"}, {p.o_box[0], (size_t)p.box_entries * 32, "box0"},
         {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * KEYSUM_WORDS * 4, "keysum"}, {p.o_piv, (size_t)p.piv_words * 4, "piv"},
-        {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}};
+        {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}, {p.o_wcount, (size_t)k * RANK_MAX_WIN * 4, "wcount"}};
     size_t end = 0;
     for (const R& r : regs) {
         CHECK(r.off % WS_ALIGN == 0 && r.off >= end, "region %s at %zu (previous end %zu)", r.name, r.off, end);
@@ -293,6 +293,15 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         const bool want = k >= 2 && !p.large.empty() &&
                           (opt.rank_layout == 2 || (opt.rank_layout == 0 && nmax * k * 4 > RANK_DM_BYTES));
         CHECK(p.rank_dm == want, "rank layout (k %u, layout %u, N %zu)", k, opt.rank_layout, N);
+        // windowed scatter: at most RANK_MAX_WIN windows covering every
+        // index, each of at most N indices, and the buckets (2 words per
+        // pair, 2^wbits pairs per window) inside one dimension's ping-pong
+        if (p.rank_dm) {
+            const uint64_t W = 1ull << p.rank_wbits;
+            CHECK(p.rank_nwin >= 1 && p.rank_nwin <= RANK_MAX_WIN, "window count %u", p.rank_nwin);
+            CHECK(W * p.rank_nwin >= N && W * (p.rank_nwin - 1) < N, "windows cover the indices");
+            CHECK(W <= N && 2 * W * p.rank_nwin <= 4 * (uint64_t)N, "buckets fit a ping-pong");
+        }
     }
     // the uploaded tables hold the host lists
     auto same = [&](size_t at, const void* v, size_t bytes) {
