@@ -208,13 +208,13 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.rank_dm = k >= 2 && !p.large.empty() &&
                 (opt.rank_layout == 2 || (opt.rank_layout == 0 && (uint64_t)nmax * k * 4 > RANK_DM_BYTES));
     if (p.rank_dm) {
-        // windows of 2^18 indices (2^wbits: at most RANK_MAX_WIN of them,
+        // windows of 2^RANK_WIN_BITS indices (2^wbits: at most RANK_MAX_WIN of them,
         // and at most ntotal indices each, so that the buckets fit the
         // 4 * ntotal words of a dimension's ping-pong)
         uint32_t lg = 0, fl = 0;
         while ((1ull << lg) < p.ntotal) ++lg;
         while ((2ull << fl) <= p.ntotal) ++fl;
-        uint32_t wb = std::max<uint32_t>(18u, lg > 11u ? lg - 11u : 0u);
+        uint32_t wb = std::max<uint32_t>(RANK_WIN_BITS, lg > 11u ? lg - 11u : 0u);
         wb = std::min(wb, fl);
         p.rank_wbits = wb;
         p.rank_nwin = (uint32_t)((p.ntotal + (1ull << wb) - 1) >> wb);

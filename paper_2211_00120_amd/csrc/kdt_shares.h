@@ -43,7 +43,14 @@ constexpr uint32_t PRESORT_GROUP = KDT_PRESORT_GROUP;
 #endif
 constexpr int PART_ITEMS = KDT_PART_ITEMS;
 constexpr uint32_t RANK_MAX_WIN = 2048;      // index windows of the windowed rank scatter
-constexpr uint32_t RANK_WIN_CHUNK = 4096;    // pairs per k_rank_window workgroup
+#ifndef KDT_RANK_WIN_BITS
+#define KDT_RANK_WIN_BITS 18
+#endif
+constexpr uint32_t RANK_WIN_BITS = KDT_RANK_WIN_BITS;  // log2 of the indices per window (at least)
+#ifndef KDT_RANK_WIN_CHUNK
+#define KDT_RANK_WIN_CHUNK 8192
+#endif
+constexpr uint32_t RANK_WIN_CHUNK = KDT_RANK_WIN_CHUNK;  // pairs per k_rank_window workgroup
 #ifndef KDT_HIST_TILE
 #define KDT_HIST_TILE 8192
 #endif
