@@ -329,6 +329,10 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 a.lb_zero = lb[(q + 1) & 1];
                 a.lb_zero_n = next_words(q);
                 a.counter = counters + q;
+                if (p.xq) {
+                    a.xq = (const uint32_t*)(ws + p.o_tables + p.t_xq);
+                    a.xq_cnt = counters + MAX_PASSES + 8 * (size_t)(&pl - p.presort_launches.data());
+                }
                 a.perms = perms;
                 // per-dimension arrays are written by the windowed scatter below
                 a.rank_table = p.rank_dm ? nullptr : ranks;

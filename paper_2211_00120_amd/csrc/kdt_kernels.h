@@ -69,6 +69,8 @@ struct PresortArgs {
     uint32_t* lb_zero;      // look-back words to clear for the next pass
     uint32_t lb_zero_n;
     uint32_t* counter;      // dynamic tile counter of this pass
+    const uint32_t* xq;     // per-XCD tile queues (null: take tiles from `counter`)
+    uint32_t* xq_cnt;       // the 8 queue counters of this launch
     uint32_t* perms;        // last pass: per tree rank -> local index, [d*ntotal + off + rank]
     uint32_t* rank_table;   // last pass: ranks at [(off + i)*rank_stride + d*rank_dstride], except each tree's
                             // root dimension: point-major (k, 1) or per-dimension arrays (1, ntotal)

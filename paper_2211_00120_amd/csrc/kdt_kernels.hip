@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* coun
 {
     const uint32_t gid = blockIdx.x * BLOCK + threadIdx.x;
     if (gid == 0) *status = 0u;
-    if (gid < MAX_PASSES) counters[gid] = 0u;
+    if (gid < MAX_COUNTERS) counters[gid] = 0u;
     zero_range(z1, n1);
     zero_range(z2, n2);
     zero_range(z3, n3);
@@ -173,6 +173,25 @@ __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
 // (rank -> index) and scatters each index's rank into the rank table
 // (point-major, or one array per dimension).  Pairs are stored interleaved (uint2).  Passes whose digit is the
 // same in every key of the tree are skipped (see PresortArgs).
+// Tile of a launch over ndims dimensions taken from per-XCD queues (xq:
+// off[8], len[8], then each queue's presort tile indices, a tree's tiles in
+// order inside one queue): first from the queue of the XCD this workgroup
+// runs on, so that a tree's tiles share that XCD's L2, then from the others.
+// The launch has one workgroup per tile, so every tile is taken exactly once,
+// and the tiles of a tree are taken in order (its look-back waits only on
+// tiles taken before it).
+__device__ uint32_t xq_take(const uint32_t* xq, uint32_t* cnt, uint32_t ndims, uint32_t* status)
+{
+    const uint32_t x0 = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u;   // HW_REG_XCC_ID[3:0]
+    for (uint32_t kk = 0; kk < 8u; ++kk) {
+        const uint32_t x = (x0 + kk) & 7u;
+        const uint32_t t = atomicAdd(&cnt[x], 1u);
+        if (t < xq[8 + x] * ndims) return xq[16 + xq[x] + t / ndims] * ndims + t % ndims;
+    }
+    atomicOr(status, KDT_STATUS_INTERNAL);
+    return 0xFFFFFFFFu;
+}
+
 template <bool LAST>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 {
@@ -181,9 +200,13 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     constexpr uint32_t T = SWEEP_THREADS * ITEMS;
     __shared__ SweepSmem<RB, 2> sm;
 
-    if (threadIdx.x == 0) sm.tile = atomicAdd(a.counter, 1u);
+    if (threadIdx.x == 0) sm.tile = a.xq ? xq_take(a.xq, a.xq_cnt, a.ndims, a.status) : atomicAdd(a.counter, 1u);
     __syncthreads();
     const uint32_t tt = uniform(sm.tile);
+    if (tt == 0xFFFFFFFFu) {
+        zero_range(a.lb_zero, a.lb_zero_n);
+        return;
+    }
     const uint32_t slot = tt % a.ndims, g = tt / a.ndims;
     const uint32_t dim = a.dim0 + slot;
     TreeStep st;
@@ -553,7 +576,7 @@ void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1
     uint32_t big = n1 > n2 ? n1 : n2;
     big = big > n3 ? big : n3;
     big = big > n4 ? big : n4;
-    big = big > MAX_PASSES ? big : MAX_PASSES;
+    big = big > MAX_COUNTERS ? big : MAX_COUNTERS;
     big = big > nbox * KEYSUM_WORDS ? big : nbox * KEYSUM_WORDS;
     uint32_t grid = ceil_div(big, BLOCK);
     if (grid > 2048) grid = 2048;

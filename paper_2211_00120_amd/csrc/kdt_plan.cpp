@@ -326,6 +326,35 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         }
     for (const Plan::PresortLaunch& pl : p.presort_launches)
         p.pass_words.push_back(pl.ndims * p.presort_tiles * RADIX_HOST);
+
+    // per-XCD presort tile queues: trees to the queue with the fewest tiles
+    // so far, largest first; each queue lists its trees' tiles in tree order
+    p.xq = p.large.size() >= XQ_MIN_TREES && p.presort_launches.size() <= XQ_LAUNCHES;
+    if (p.xq) {
+        std::vector<uint32_t> order(p.large.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (uint32_t)i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](uint32_t x, uint32_t y) { return n[p.large[x]] > n[p.large[y]]; });
+        std::vector<std::vector<uint32_t>> qs(8);
+        uint64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        std::vector<uint32_t> owner(p.large.size());
+        for (uint32_t i : order) {
+            const uint32_t x = (uint32_t)(std::min_element(load, load + 8) - load);
+            owner[i] = x;
+            load[x] += ceil_div(n[p.large[i]], PRESORT_TILE);
+        }
+        for (size_t i = 0; i < p.large.size(); ++i) {
+            const TreeStep& s = p.presort[i];
+            const uint32_t nt = ceil_div(n[p.large[i]], PRESORT_TILE);
+            for (uint32_t g = 0; g < nt; ++g) qs[owner[i]].push_back(s.tile0 + g);
+        }
+        p.xq_table.assign(16, 0u);
+        for (uint32_t x = 0; x < 8; ++x) {
+            p.xq_table[x] = (uint32_t)(p.xq_table.size() - 16);
+            p.xq_table[8 + x] = (uint32_t)qs[x].size();
+            p.xq_table.insert(p.xq_table.end(), qs[x].begin(), qs[x].end());
+        }
+    }
     for (const LevelLaunch& ll : p.levels) p.pass_words.push_back(ll.tiles * PART_BINS);
     for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
 
@@ -334,6 +363,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.t_small = push_table(p.blob, p.small.data(), p.small.size() * sizeof(TreeStep));
     p.t_prep = push_table(p.blob, p.prep.data(), p.prep.size() * sizeof(TreeStep));
     p.t_presort = push_table(p.blob, p.presort.data(), p.presort.size() * sizeof(TreeStep));
+    p.t_xq = push_table(p.blob, p.xq_table.data(), p.xq_table.size() * 4);
     p.t_level0 = push_table(p.blob, p.level0.data(), p.level0.size() * sizeof(TreeStep));
     p.t_tail = push_table(p.blob, p.tail.data(), p.tail.size() * sizeof(TreeStep));
     p.t_roots = push_table(p.blob, p.roots.data(), p.roots.size() * sizeof(TreeStep));
@@ -353,7 +383,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         return r;
     };
     p.o_status = take(64);
-    p.o_counters = take(MAX_PASSES * 4);
+    p.o_counters = take(MAX_COUNTERS * 4);
     p.o_hist_rank = take((size_t)p.large.size() * k * 4 * RADIX_HOST * 4);
     p.o_hist = take((size_t)p.hist_words * 3 * 4);
     p.o_lb[0] = take((size_t)p.lb_words * 4);

@@ -11,6 +11,9 @@ constexpr uint32_t KDT_STATUS_INTERNAL = 0x100; // an internal bound or wait che
 
 constexpr uint32_t RADIX_HOST = 256;
 constexpr uint32_t MAX_PASSES = 256;       // onesweep passes per build (tile counters)
+constexpr uint32_t XQ_LAUNCHES = 16;       // presort launches that can take tiles from per-XCD queues
+constexpr uint32_t MAX_COUNTERS = MAX_PASSES + 8 * XQ_LAUNCHES;   // pass counters, then 8 queue counters each
+constexpr uint32_t XQ_MIN_TREES = 16;      // trees from which presorts use per-XCD tile queues
 constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digits of a rank of at most 30 bits (8..10-bit digits)
 constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
 constexpr uint32_t PART_BINS = 4;          // digit values of the split passes (smaller, pivot, larger)

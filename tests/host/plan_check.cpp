@@ -258,6 +258,31 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         for (uint32_t d = a.dim0; d < a.dim0 + a.ndims && d < 4; ++d) sorted_passes[d] |= 1u << a.pass;
     }
     for (uint32_t d = 0; d < k && !p.large.empty(); ++d) CHECK(sorted_passes[d] == 0xFu, "dimension %u passes", d);
+    // per-XCD presort queues (many trees): every presort tile in exactly one
+    // queue, a tree's tiles all in one queue and in order
+    CHECK(p.xq == (p.large.size() >= XQ_MIN_TREES && p.presort_launches.size() <= XQ_LAUNCHES), "xq choice");
+    if (p.xq) {
+        CHECK(p.xq_table.size() == 16 + (size_t)p.presort_tiles, "xq table size");
+        std::vector<int> seen(p.presort_tiles, 0);
+        std::vector<int> queue_of(p.large.size(), -1);
+        std::vector<int64_t> last(p.large.size(), -1);
+        for (uint32_t x = 0; x < 8 && p.xq_table.size() >= 16; ++x) {
+            const uint32_t off = p.xq_table[x], len = p.xq_table[8 + x];
+            CHECK(16 + (size_t)off + len <= p.xq_table.size(), "queue %u bounds", x);
+            for (uint32_t i = 0; i < len && 16 + (size_t)off + i < p.xq_table.size(); ++i) {
+                const uint32_t g = p.xq_table[16 + off + i];
+                if (g >= p.presort_tiles) { CHECK(false, "queue %u tile %u out of range", x, g); continue; }
+                seen[g]++;
+                size_t tr = 0;
+                while (tr + 1 < p.large.size() && p.presort[tr + 1].tile0 <= g) ++tr;
+                CHECK(queue_of[tr] < 0 || queue_of[tr] == (int)x, "tree %zu in two queues", tr);
+                queue_of[tr] = (int)x;
+                CHECK((int64_t)g > last[tr], "tree %zu tiles out of order", tr);
+                last[tr] = g;
+            }
+        }
+        for (uint32_t g = 0; g < p.presort_tiles; ++g) CHECK(seen[g] == 1, "tile %u queued %d times", g, seen[g]);
+    }
     const size_t npass = p.presort_launches.size() + p.levels.size();
     CHECK(p.pass_words.size() == npass && npass <= MAX_PASSES, "pass count");
     for (size_t i = 0; i < p.presort_launches.size() && p.pass_words.size() == npass; ++i)
@@ -269,7 +294,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     // workspace regions: aligned, in order, disjoint
     const size_t N = p.ntotal;
     struct R { size_t off, bytes; const char* name; } regs[] = {
-        {p.o_status, 64, "status"}, {p.o_counters, MAX_PASSES * 4, "counters"},
+        {p.o_status, 64, "status"}, {p.o_counters, MAX_COUNTERS * 4, "counters"},
         {p.o_hist_rank, p.large.size() * k * 4 * RADIX_HOST * 4, "hist_rank"},
         {p.o_hist, (size_t)p.hist_words * 12, "hist"}, {p.o_lb[0], (size_t)p.lb_words * 4, "lb0"},
         {p.o_lb[1], (size_t)p.lb_words * 4, "lb1"}, {p.o_keys, N * k * 4, "keys"}, {p.o_perms, N * k * 4, "perms"},
