@@ -200,6 +200,19 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     constexpr uint32_t T = SWEEP_THREADS * ITEMS;
     __shared__ SweepSmem<RB, 2> sm;
 
+    if (!LAST && a.sh.nsteps == 1) {
+        // one tree: when its keys share this digit in every dimension of the
+        // launch, no tile runs, and the workgroup leaves without taking a
+        // tile (the whole launch would otherwise queue on the tile counter)
+        const uint32_t* sum = a.keysum + (size_t)a.sh.tree0.idx * KEYSUM_WORDS;
+        uint32_t runs = 0u;
+        for (uint32_t j = 0; j < a.ndims; ++j)
+            runs |= ((sum[8 + a.dim0 + j] ^ sum[12 + a.dim0 + j]) >> (8u * a.pass)) & 0xFFu;
+        if (uniform(runs) == 0u) {
+            zero_range(a.lb_zero, a.lb_zero_n);
+            return;
+        }
+    }
     if (threadIdx.x == 0) sm.tile = a.xq ? xq_take(a.xq, a.xq_cnt, a.ndims, a.status) : atomicAdd(a.counter, 1u);
     __syncthreads();
     const uint32_t tt = uniform(sm.tile);
