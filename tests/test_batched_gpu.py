@@ -252,6 +252,32 @@ def test_batched_rank_layouts(mode):
         kdt.tuning_clear()
 
 
+@pytest.mark.parametrize("layout", [0, 2])
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_batched_many_large_clouds(mode, layout):
+    """Enough clouds of more than 2048 points that the presort takes its
+    tiles from per-XCD queues (whole clouds per queue): every cloud is still
+    the oracle's tree, with either rank layout (0: the planner's, which for
+    these sizes is the point-major scatter; 2: per-dimension arrays written
+    through index windows)."""
+    rng = np.random.default_rng(77)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(2100), np.log(40000), 24))] + [5, 700, 2048, 0]
+    clouds = [workloads.grid(n, 3, 400 + i, levels=10) for i, n in enumerate(sizes)]
+    pts, offsets = _concat(clouds)
+    bits = int(max(sizes) - 1).bit_length()
+    kdt.tuning_clear()
+    try:
+        if layout:
+            kdt.tuning_set(3, mode, bits, 0, 0, layout)
+        _say(f"case many large clouds: mode {mode} layout {layout} n={pts.shape[0]}")
+        got = _run_batched(pts, offsets, mode)
+        assert got[3] == kdt.OK
+        for c in range(len(sizes)):
+            _assert_cloud(pts, offsets, c, *got[:3], mode, f"many-large-{layout}")
+    finally:
+        kdt.tuning_clear()
+
+
 def test_tuner_choices_give_identical_trees():
     """Every digit-width / tile choice the tuner may record builds the same
     trees; kdt_tune_batched records one of them for the batch's class."""
