@@ -73,7 +73,8 @@ struct PresortArgs {
     uint32_t* xq_cnt;       // the 8 queue counters of this launch
     uint32_t* perms;        // last pass: per tree rank -> local index, [d*ntotal + off + rank]
     uint32_t* rank_table;   // last pass: ranks at [(off + i)*rank_stride + d*rank_dstride], except each tree's
-                            // root dimension: point-major (k, 1) or per-dimension arrays (1, ntotal)
+                            // root dimension: point-major (k, 1) or per-dimension arrays (1, ntotal); null when
+                            // the per-dimension arrays are written by k_rank_bucket / k_rank_window instead
     const uint8_t* dimnode; // split-widest: node dims (the root's is tree's first entry); null: root dimension 0
     uint32_t rank_stride;
     size_t rank_dstride;
@@ -84,7 +85,7 @@ struct PresortArgs {
 struct Level0Args {
     Shares sh;              // one share per tree, tiles of PREP_TILE ranks
     const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
-    const uint32_t* rank_table;
+    const uint32_t* rank_table;   // point-major rank records, [(off + i)*k + d]
     uint32_t* rout;         // iteration-1 records
     uint32_t* kout;         // iteration-1 split keys (share.hist_next != NO_HIST and keys_next)
     uint32_t* hist;         // base of the iteration-1 histograms (share.hist_next offsets)

@@ -165,14 +165,6 @@ __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
 
 // ------------------------------------------------------------ presort passes
 
-// One stable LSD digit pass of the (key, index) sorts of a group of
-// dimensions, every tree a segment of its own.  The dimensions' tiles are
-// interleaved (tile t of the launch is tile t / ndims of dimension slot
-// t % ndims), so the look-back chains of the group advance side by side.  A tree's first pass that runs reads the keys
-// of prep and takes the local index as value; LAST writes the sorted indices
-// (rank -> index) and scatters each index's rank into the rank table
-// (point-major, or one array per dimension).  Pairs are stored interleaved (uint2).  Passes whose digit is the
-// same in every key of the tree are skipped (see PresortArgs).
 // Tile of a launch over ndims dimensions taken from per-XCD queues (xq:
 // off[8], len[8], then each queue's presort tile indices, a tree's tiles in
 // order inside one queue): first from the queue of the XCD this workgroup
@@ -192,6 +184,16 @@ __device__ uint32_t xq_take(const uint32_t* xq, uint32_t* cnt, uint32_t ndims, u
     return 0xFFFFFFFFu;
 }
 
+// One stable LSD digit pass of the (key, index) sorts of a group of
+// dimensions, every tree a segment of its own.  The dimensions' tiles are
+// interleaved (tile t of the launch is tile t / ndims of dimension slot
+// t % ndims), so the look-back chains of the group advance side by side.
+// A tree's first pass that runs reads the keys of prep and takes the local
+// index as value; LAST writes the sorted indices (rank -> index) and, unless
+// the ranks go through the windowed scatter, scatters each index's rank into
+// the point-major rank table.  Pairs are stored interleaved (uint2).  Passes
+// whose digit is the same in every key of the tree are skipped (see
+// PresortArgs).
 template <bool LAST>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 {
@@ -279,7 +281,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
             if (LAST) {
                 perm_out[off + pos] = r.y;
-                if (to_table && a.rank_table) a.rank_table[(off + r.y) * a.rank_stride + dim * a.rank_dstride] = pos;
+                if (to_table && a.rank_table)
+                    a.rank_table[(off + r.y) * a.rank_stride + dim * a.rank_dstride] = pos;
             } else {
                 reinterpret_cast<uint2*>(kvout)[off + pos] = make_uint2(r.x, r.y);
             }
