@@ -311,18 +311,14 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     }
 
     // look-back words per pass, in the order the passes run
-    // presort launches: passes 0-2 of a group of dimensions share a launch;
-    // so does the last pass, unless it scatters into per-dimension arrays
-    // too large for the cache (several at once only evict each other)
+    // presort launches: the 4 passes of a group of dimensions share a launch
+    // each (per-dimension rank arrays are written after the last one, by the
+    // windowed scatter)
     p.presort_group = std::min(k, opt.presort_dims ? std::min(opt.presort_dims, PRESORT_GROUP) : PRESORT_GROUP);
     if (!p.large.empty())
         for (uint32_t d0 = 0; d0 < k; d0 += p.presort_group) {
             const uint32_t nd = std::min(p.presort_group, k - d0);
-            for (uint32_t q = 0; q < 3u; ++q) p.presort_launches.push_back({d0, nd, q});
-            if (p.rank_dm)
-                for (uint32_t d = d0; d < d0 + nd; ++d) p.presort_launches.push_back({d, 1u, 3u});
-            else
-                p.presort_launches.push_back({d0, nd, 3u});
+            for (uint32_t q = 0; q < 4u; ++q) p.presort_launches.push_back({d0, nd, q});
         }
     for (const Plan::PresortLaunch& pl : p.presort_launches)
         p.pass_words.push_back(pl.ndims * p.presort_tiles * RADIX_HOST);

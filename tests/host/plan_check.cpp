@@ -231,10 +231,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     }
     CHECK(groups == p.tail_groups, "tail groups");
     // look-back words
-    // presort: dimensions in groups of presort_group; passes 0-2 of a group
-    // share a launch, and so does pass 3 unless the ranks go to per-dimension
-    // arrays (then one launch per dimension); every launch's look-back words
-    // cover its dimensions
+    // presort: dimensions in groups of presort_group, each of the 4 passes of
+    // a group one launch; every launch's look-back words cover its dimensions
     const uint32_t G = p.presort_group;
     CHECK(G == std::min(k, opt.presort_dims ? std::min(opt.presort_dims, PRESORT_GROUP) : PRESORT_GROUP),
           "presort group %u (option %u)", G, opt.presort_dims);
@@ -242,11 +240,7 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     if (!p.large.empty())
         for (uint32_t d0 = 0; d0 < k; d0 += G) {
             const uint32_t nd = std::min(G, k - d0);
-            for (uint32_t q = 0; q < 3u; ++q) want.push_back({d0, nd, q});
-            if (p.rank_dm)
-                for (uint32_t d = d0; d < d0 + nd; ++d) want.push_back({d, 1u, 3u});
-            else
-                want.push_back({d0, nd, 3u});
+            for (uint32_t q = 0; q < 4u; ++q) want.push_back({d0, nd, q});
         }
     CHECK(want.size() == p.presort_launches.size(), "presort launch count");
     uint32_t sorted_passes[4] = {0, 0, 0, 0};
