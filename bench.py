@@ -157,6 +157,19 @@ def kernel_table(prof, steps):
     return roofline, kernels
 
 
+def calibration_copy(args, dev):
+    """One device-to-device copy of a known size, for scaling rocprofv3's
+    FETCH_SIZE / WRITE_SIZE counters of the same run."""
+    import torch
+    if args.calibrate_copy_mib:
+        src = torch.ones(args.calibrate_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+
 def run_batched(args, data, mode, cfg):
     """One step = one graph replay of kdt_build_batched over every cloud."""
     import numpy as np
@@ -176,6 +189,7 @@ def run_batched(args, data, mode, cfg):
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.empty(kdt.batched_workspace_bytes(offsets, k, mode), dtype=torch.uint8, device=dev)
     stream = torch.cuda.Stream()
+    calibration_copy(args, dev)
 
     def build_eager():
         kdt.build_batched(d_pts, offsets, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws,
@@ -219,10 +233,16 @@ def run_batched(args, data, mode, cfg):
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed / 1e6
     if roofline:
+        tr = committed_traffic(roofline["kernel"], cfg["workload"], kernel_source_sha())
+        roofline["traffic"] = tr["hbm_bytes_per_launch"] if tr else None
         build_alg = sum(v["alg_bytes"] for v in prof.values()) / psteps
         roofline["build_alg_GBs"] = round(build_alg / (ms_per_step * 1e6), 1)
     print(f"# batched graph: {ms_per_step:.3f} ms per build, status {st}", file=sys.stderr, flush=True)
 
+    if args.no_per_cloud:
+        return {"value": round(value, 3), "ms_per_step": round(ms_per_step, 4), "roofline": roofline,
+                "kernels": kernels, "bit_exact": None, "cpu_baseline": None, "per_cloud": None,
+                "batched_vs_per_cloud": None}
     # the same clouds as one kdt_build_ws call each, one after another on one
     # stream, preallocated, no host synchronisation between calls
     nmax = int(np.max(np.diff(offsets.astype(np.int64))))
@@ -452,6 +472,8 @@ def main():
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--no-check", action="store_true", help="skip the full-tree bit-exactness check")
+    ap.add_argument("--no-per-cloud", action="store_true",
+                    help="batched: skip the comparison with one single build per cloud (for counter runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
@@ -510,13 +532,7 @@ def main():
     ws = torch.empty(kdt.workspace_bytes(n, k, mode), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    if args.calibrate_copy_mib:
-        src = torch.ones(args.calibrate_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(args, dev)
 
     def step():
         kdt.build_ws(d_pts, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws, stream=stream)
