@@ -417,8 +417,10 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             a.passes = p.P;
             a.radix_bits = p.RB;
             a.o = o;
+            a.xmap = p.xmap0.empty() ? nullptr : (const uint32_t*)(ws + p.o_tables + p.t_xmap0);
+            const uint32_t grid = p.xmap0.empty() ? p.prep_tiles : (uint32_t)p.xmap0.size();
             if (kdt_status s = run_kernel(st, KIND_LEVEL0, nlarge * (4.0 + 8.0 * K + (keys1 ? 4.0 : 0.0)),
-                                          [&] { launch_level0((int)k, a, p.prep_tiles, widest, st); }))
+                                          [&] { launch_level0((int)k, a, grid, widest, st); }))
                 return s;
         }
 

@@ -84,6 +84,7 @@ struct PresortArgs {
 
 struct Level0Args {
     Shares sh;              // one share per tree, tiles of PREP_TILE ranks
+    const uint32_t* xmap;   // null, or per workgroup its tile (0xFFFFFFFF: none), trees grouped by XCD
     const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
     const uint32_t* rank_table;   // point-major rank records, [(off + i)*k + d]
     uint32_t* rout;         // iteration-1 records

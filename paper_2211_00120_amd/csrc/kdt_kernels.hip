@@ -442,9 +442,14 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
 {
     __shared__ uint32_t nh[2 * MAX_BINS];
     __shared__ uint32_t cdim[2];
+    // with an XCD map, workgroup b (on XCD b mod 8) takes the tile the map
+    // gives it: a tree's tiles all on one XCD, whose L2 then holds its rank
+    // records for the gathers below; padding entries take none
+    const uint32_t tile = a.xmap ? a.xmap[blockIdx.x] : blockIdx.x;
+    if (tile == 0xFFFFFFFFu) return;
     TreeStep st;
     TreeInfo ti;
-    find_share(a.sh, blockIdx.x, st, ti);
+    find_share(a.sh, tile, st, ti);
     const uint32_t P = a.passes;
     const uint32_t RBv = a.radix_bits;
     const uint32_t NB = 1u << RBv;
@@ -474,7 +479,7 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
     }
     __syncthreads();
     const uint32_t cd0 = uniform(cdim[0]), cd1 = uniform(cdim[1]);
-    const uint32_t start = (blockIdx.x - st.tile0) * PREP_TILE;
+    const uint32_t start = (tile - st.tile0) * PREP_TILE;
     const uint32_t end = min(start + PREP_TILE, n);
     for (uint32_t r = start + threadIdx.x; r < end; r += BLOCK) {
         const uint32_t idx = perm_d0[r];

@@ -350,6 +350,18 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
             p.xq_table[8 + x] = (uint32_t)qs[x].size();
             p.xq_table.insert(p.xq_table.end(), qs[x].begin(), qs[x].end());
         }
+        // iteration 0 (static tiles): workgroup b runs on XCD b mod 8 and
+        // takes the (b / 8)-th prep tile of that XCD's trees
+        std::vector<std::vector<uint32_t>> ls(8);
+        for (size_t i = 0; i < p.large.size(); ++i) {
+            const uint32_t nt = ceil_div(n[p.large[i]], PREP_TILE);
+            for (uint32_t g = 0; g < nt; ++g) ls[owner[i]].push_back(p.level0[i].tile0 + g);
+        }
+        size_t longest = 0;
+        for (const auto& l : ls) longest = std::max(longest, l.size());
+        p.xmap0.assign(8 * longest, 0xFFFFFFFFu);
+        for (uint32_t x = 0; x < 8; ++x)
+            for (size_t j = 0; j < ls[x].size(); ++j) p.xmap0[8 * j + x] = ls[x][j];
     }
     for (const LevelLaunch& ll : p.levels) p.pass_words.push_back(ll.tiles * PART_BINS);
     for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
@@ -360,6 +372,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.t_prep = push_table(p.blob, p.prep.data(), p.prep.size() * sizeof(TreeStep));
     p.t_presort = push_table(p.blob, p.presort.data(), p.presort.size() * sizeof(TreeStep));
     p.t_xq = push_table(p.blob, p.xq_table.data(), p.xq_table.size() * 4);
+    p.t_xmap0 = push_table(p.blob, p.xmap0.data(), p.xmap0.size() * 4);
     p.t_level0 = push_table(p.blob, p.level0.data(), p.level0.size() * sizeof(TreeStep));
     p.t_tail = push_table(p.blob, p.tail.data(), p.tail.size() * sizeof(TreeStep));
     p.t_roots = push_table(p.blob, p.roots.data(), p.roots.size() * sizeof(TreeStep));

@@ -276,6 +276,22 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
             }
         }
         for (uint32_t g = 0; g < p.presort_tiles; ++g) CHECK(seen[g] == 1, "tile %u queued %d times", g, seen[g]);
+        // iteration 0's XCD map: every prep tile once; workgroup b holds a
+        // tile of a tree whose presort queue is b mod 8
+        CHECK(p.xmap0.size() % 8 == 0, "xmap0 size");
+        std::vector<int> once(p.prep_tiles, 0);
+        for (size_t b = 0; b < p.xmap0.size(); ++b) {
+            const uint32_t g = p.xmap0[b];
+            if (g == 0xFFFFFFFFu) continue;
+            if (g >= p.prep_tiles) { CHECK(false, "xmap0 tile %u out of range", g); continue; }
+            once[g]++;
+            size_t tr = 0;
+            while (tr + 1 < p.large.size() && p.level0[tr + 1].tile0 <= g) ++tr;
+            CHECK(queue_of[tr] == (int)(b % 8), "xmap0: tree %zu off its XCD", tr);
+        }
+        for (uint32_t g = 0; g < p.prep_tiles; ++g) CHECK(once[g] == 1, "prep tile %u mapped %d times", g, once[g]);
+    } else {
+        CHECK(p.xmap0.empty(), "xmap0 without queues");
     }
     const size_t npass = p.presort_launches.size() + p.levels.size();
     CHECK(p.pass_words.size() == npass && npass <= MAX_PASSES, "pass count");
