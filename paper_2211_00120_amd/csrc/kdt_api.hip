@@ -500,10 +500,12 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         a.rin[1] = rec[1];
         a.from_points = 0;
         a.o = o;
+        a.xmap = p.xmapt.empty() ? nullptr : (const uint32_t*)(ws + p.o_tables + p.t_xmapt);
+        const uint32_t tail_grid = p.xmapt.empty() ? p.tail_groups : (uint32_t)p.xmapt.size();
         double tail_live = 0;
         for (const TreeStep& s : p.tail) tail_live += p.trees[s.tree].n - full_nodes(s.level);
         if (kdt_status s = run_kernel(st, KIND_TAIL, tail_live * 4.0 * K,
-                                      [&] { launch_tail((int)k, a, p.tail_groups, widest, st); }))
+                                      [&] { launch_tail((int)k, a, tail_grid, widest, st); }))
             return s;
     }
     if (status)

@@ -153,6 +153,7 @@ struct LevelPartArgs {
 
 struct TailArgs {
     Shares sh;              // tail shares: workgroup ranges, level = first tail iteration
+    const uint32_t* xmap;   // null, or per workgroup its group (0xFFFFFFFF: none), trees grouped by XCD
     const uint32_t* rin[2]; // the two record buffers (share.buf selects; from_points: unused)
     uint32_t from_points;   // whole trees of at most TAIL_CAP points, built from the points
     Outs o;

@@ -362,6 +362,18 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         p.xmap0.assign(8 * longest, 0xFFFFFFFFu);
         for (uint32_t x = 0; x < 8; ++x)
             for (size_t j = 0; j < ls[x].size(); ++j) p.xmap0[8 * j + x] = ls[x][j];
+        // the tail's groups the same way
+        std::vector<std::vector<uint32_t>> lt(8);
+        for (size_t i = 0; i < p.large.size(); ++i) {
+            const TreeStep& s = p.tail[i];
+            const uint32_t ng = tail_group_count(make_level(n[p.large[i]], s.level).nseg, s.pair0);
+            for (uint32_t g = 0; g < ng; ++g) lt[owner[i]].push_back(s.tile0 + g);
+        }
+        longest = 0;
+        for (const auto& l : lt) longest = std::max(longest, l.size());
+        p.xmapt.assign(8 * longest, 0xFFFFFFFFu);
+        for (uint32_t x = 0; x < 8; ++x)
+            for (size_t j = 0; j < lt[x].size(); ++j) p.xmapt[8 * j + x] = lt[x][j];
     }
     for (const LevelLaunch& ll : p.levels) p.pass_words.push_back(ll.tiles * PART_BINS);
     for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
@@ -373,6 +385,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.t_presort = push_table(p.blob, p.presort.data(), p.presort.size() * sizeof(TreeStep));
     p.t_xq = push_table(p.blob, p.xq_table.data(), p.xq_table.size() * 4);
     p.t_xmap0 = push_table(p.blob, p.xmap0.data(), p.xmap0.size() * 4);
+    p.t_xmapt = push_table(p.blob, p.xmapt.data(), p.xmapt.size() * 4);
     p.t_level0 = push_table(p.blob, p.level0.data(), p.level0.size() * sizeof(TreeStep));
     p.t_tail = push_table(p.blob, p.tail.data(), p.tail.size() * sizeof(TreeStep));
     p.t_roots = push_table(p.blob, p.roots.data(), p.roots.size() * sizeof(TreeStep));

@@ -74,6 +74,7 @@ struct Plan {
     bool xq = false;                 // presort tiles from per-XCD queues (many trees)
     std::vector<uint32_t> xq_table;  // off[8], len[8], then each queue's presort tile indices
     std::vector<uint32_t> xmap0;     // iteration 0: per workgroup its prep-tile (same trees per XCD as xq)
+    std::vector<uint32_t> xmapt;     // tail: per workgroup its group (same trees per XCD as xq)
     std::vector<TreeStep> prep, presort, level0, tail, roots;
     uint32_t prep_tiles = 0, presort_tiles = 0, tail_groups = 0;
     std::vector<LevelLaunch> levels; // iterations 1.. run as passes
@@ -85,7 +86,7 @@ struct Plan {
     bool tables = false;             // some launch reads a device share table
     std::vector<uint8_t> blob;       // the share tables, as uploaded
     size_t t_trees = 0, t_small = 0, t_prep = 0, t_presort = 0, t_level0 = 0, t_tail = 0, t_roots = 0, t_xq = 0,
-           t_xmap0 = 0;
+           t_xmap0 = 0, t_xmapt = 0;
     std::vector<size_t> t_level, t_select, t_pivot;
     // workspace offsets (bytes)
     size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,

@@ -265,16 +265,21 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     __shared__ uint32_t bxk[8];                    // from_points split-widest: scene box keys
 
     const Outs& o = a.o;
+    // with an XCD map, workgroup b (on XCD b mod 8) takes the group the map
+    // gives it: a tree's groups all on one XCD, whose L2 then holds the
+    // tree's index list and points for the gathers; padding takes none
+    const uint32_t grp = a.xmap ? a.xmap[blockIdx.x] : blockIdx.x;
+    if (grp == 0xFFFFFFFFu) return;
     TreeStep stp;
     TreeInfo ti;
-    find_share(a.sh, blockIdx.x, stp, ti);
+    find_share(a.sh, grp, stp, ti);
     const bool FP = a.from_points != 0u;
     const size_t off = ti.off;
     const Level v0 = make_level(ti.n, FP ? 0u : stp.level);
     const uint32_t l0 = v0.l;
     const uint32_t L = v0.L;
     uint32_t i0, i1;
-    tail_group_range(blockIdx.x - stp.tile0, stp.pair0, v0.nseg, i0, i1);
+    tail_group_range(grp - stp.tile0, stp.pair0, v0.nseg, i0, i1);
     const uint32_t gc = i1 - i0;
     const uint32_t live0 = v0.n - v0.Fl;
     const uint32_t off0 = FP ? 0u : seg_offset(v0, i0);

@@ -290,8 +290,21 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
             CHECK(queue_of[tr] == (int)(b % 8), "xmap0: tree %zu off its XCD", tr);
         }
         for (uint32_t g = 0; g < p.prep_tiles; ++g) CHECK(once[g] == 1, "prep tile %u mapped %d times", g, once[g]);
+        // the tail's XCD map: every group once, on its tree's XCD
+        CHECK(p.xmapt.size() % 8 == 0, "xmapt size");
+        std::vector<int> gonce(p.tail_groups, 0);
+        for (size_t b = 0; b < p.xmapt.size(); ++b) {
+            const uint32_t g = p.xmapt[b];
+            if (g == 0xFFFFFFFFu) continue;
+            if (g >= p.tail_groups) { CHECK(false, "xmapt group %u out of range", g); continue; }
+            gonce[g]++;
+            size_t tr = 0;
+            while (tr + 1 < p.tail.size() && p.tail[tr + 1].tile0 <= g) ++tr;
+            CHECK(queue_of[tr] == (int)(b % 8), "xmapt: tree %zu off its XCD", tr);
+        }
+        for (uint32_t g = 0; g < p.tail_groups; ++g) CHECK(gonce[g] == 1, "tail group %u mapped %d times", g, gonce[g]);
     } else {
-        CHECK(p.xmap0.empty(), "xmap0 without queues");
+        CHECK(p.xmap0.empty() && p.xmapt.empty(), "XCD maps without queues");
     }
     const size_t npass = p.presort_launches.size() + p.levels.size();
     CHECK(p.pass_words.size() == npass && npass <= MAX_PASSES, "pass count");
