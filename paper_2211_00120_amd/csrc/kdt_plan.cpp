@@ -350,30 +350,31 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
             p.xq_table[8 + x] = (uint32_t)qs[x].size();
             p.xq_table.insert(p.xq_table.end(), qs[x].begin(), qs[x].end());
         }
-        // iteration 0 (static tiles): workgroup b runs on XCD b mod 8 and
-        // takes the (b / 8)-th prep tile of that XCD's trees
-        std::vector<std::vector<uint32_t>> ls(8);
+        // static launches (iteration 0, tail): workgroup b runs on XCD b mod
+        // 8 and takes the (b / 8)-th tile of that XCD's trees; tree i owns
+        // tiles first[i] .. first[i] + count[i] - 1; padding entries are empty
+        auto xcd_map = [&](const std::vector<uint32_t>& first, const std::vector<uint32_t>& count) {
+            std::vector<std::vector<uint32_t>> ls(8);
+            for (size_t i = 0; i < p.large.size(); ++i)
+                for (uint32_t g = 0; g < count[i]; ++g) ls[owner[i]].push_back(first[i] + g);
+            size_t longest = 0;
+            for (const auto& l : ls) longest = std::max(longest, l.size());
+            std::vector<uint32_t> m(8 * longest, 0xFFFFFFFFu);
+            for (uint32_t x = 0; x < 8; ++x)
+                for (size_t j = 0; j < ls[x].size(); ++j) m[8 * j + x] = ls[x][j];
+            return m;
+        };
+        std::vector<uint32_t> first(p.large.size()), count(p.large.size());
         for (size_t i = 0; i < p.large.size(); ++i) {
-            const uint32_t nt = ceil_div(n[p.large[i]], PREP_TILE);
-            for (uint32_t g = 0; g < nt; ++g) ls[owner[i]].push_back(p.level0[i].tile0 + g);
+            first[i] = p.level0[i].tile0;
+            count[i] = ceil_div(n[p.large[i]], PREP_TILE);
         }
-        size_t longest = 0;
-        for (const auto& l : ls) longest = std::max(longest, l.size());
-        p.xmap0.assign(8 * longest, 0xFFFFFFFFu);
-        for (uint32_t x = 0; x < 8; ++x)
-            for (size_t j = 0; j < ls[x].size(); ++j) p.xmap0[8 * j + x] = ls[x][j];
-        // the tail's groups the same way
-        std::vector<std::vector<uint32_t>> lt(8);
+        p.xmap0 = xcd_map(first, count);
         for (size_t i = 0; i < p.large.size(); ++i) {
-            const TreeStep& s = p.tail[i];
-            const uint32_t ng = tail_group_count(make_level(n[p.large[i]], s.level).nseg, s.pair0);
-            for (uint32_t g = 0; g < ng; ++g) lt[owner[i]].push_back(s.tile0 + g);
+            first[i] = p.tail[i].tile0;
+            count[i] = tail_group_count(make_level(n[p.large[i]], p.tail[i].level).nseg, p.tail[i].pair0);
         }
-        longest = 0;
-        for (const auto& l : lt) longest = std::max(longest, l.size());
-        p.xmapt.assign(8 * longest, 0xFFFFFFFFu);
-        for (uint32_t x = 0; x < 8; ++x)
-            for (size_t j = 0; j < lt[x].size(); ++j) p.xmapt[8 * j + x] = lt[x][j];
+        p.xmapt = xcd_map(first, count);
     }
     for (const LevelLaunch& ll : p.levels) p.pass_words.push_back(ll.tiles * PART_BINS);
     for (uint32_t w : p.pass_words) p.lb_words = std::max(p.lb_words, w);
