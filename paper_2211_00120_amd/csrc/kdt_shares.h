@@ -30,7 +30,7 @@ constexpr int SWEEP_THREADS = KDT_SWEEP_THREADS;
 
 // Tile shapes (items per thread of a SWEEP_THREADS workgroup); tuning knobs.
 #ifndef KDT_PRESORT_ITEMS
-#define KDT_PRESORT_ITEMS 12
+#define KDT_PRESORT_ITEMS 14
 #endif
 constexpr int PRESORT_ITEMS = KDT_PRESORT_ITEMS;
 constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
