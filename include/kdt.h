@@ -142,7 +142,7 @@ void kdt_release_cached(void);
 /*
  * Autotuner.  The level sorts can run with 8-, 9- or 10-bit digits (fewer
  * bits: more passes, smaller histograms and look-back tables) and with tiles
- * of 512 x 4 or 512 x 8 records; the presort's digit passes can run one
+ * of 512 x 4 or 512 x 10 records; the presort's digit passes can run one
  * dimension per launch or all dimensions per launch.  Without tuning the
  * planner picks the fewest passes, the largest tile the level's subtrees
  * fill, and all dimensions per launch.
@@ -157,7 +157,8 @@ void kdt_release_cached(void);
  */
 typedef struct kdt_tuning {
     uint32_t radix_bits;   /* 0 (planner's choice) or 8..10 */
-    uint32_t level_items;  /* 0 (planner's choice), 4 or 8: cap on records per thread of level-sort tiles */
+    uint32_t level_items;  /* 0 (planner's choice), 4 (split tiles of 512 x 4 records only) or 8 (also the
+                              large split tiles, 512 x 10 records, where an iteration's subtrees fill them) */
     uint32_t rank_layout;  /* 0 (planner's choice: 2 when the largest tree's rank table exceeds 128 MiB), 1 (each dimension's
                               last presort pass writes a point-major rank table) or 2 (it writes one rank array
                               per dimension, which a packing pass turns into the point-major table); never

@@ -24,7 +24,7 @@ constexpr uint32_t NO_HIST = 0xFFFFFFFFu;
 // Choices the planner otherwise makes itself (0 = automatic).
 struct PlanOptions {
     uint32_t radix_bits = 0;   // digit width of the pivot selects: 8, 9 or 10
-    uint32_t max_items = 0;    // cap on records per thread of the split tiles: 4 or 8
+    uint32_t max_items = 0;    // split tiles: 4 (512 x 4 only) or 8 (also 512 x PART_ITEMS)
     uint32_t rank_layout = 0;  // 1: point-major rank table, 2: per-dimension rank arrays + packing pass
     uint32_t presort_dims = 0; // dimensions whose presort digit passes share a launch: 1..4 (clamped to k)
 };

@@ -42,7 +42,7 @@ constexpr uint32_t PRESORT_TILE = (uint32_t)SWEEP_THREADS * PRESORT_ITEMS;
 constexpr uint32_t PRESORT_GROUP = KDT_PRESORT_GROUP;
 // Records per thread of the large split tiles (the small ones take 4).
 #ifndef KDT_PART_ITEMS
-#define KDT_PART_ITEMS 8
+#define KDT_PART_ITEMS 10
 #endif
 constexpr int PART_ITEMS = KDT_PART_ITEMS;
 constexpr uint32_t RANK_MAX_WIN = 2048;      // index windows of the windowed rank scatter

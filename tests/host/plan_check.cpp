@@ -146,7 +146,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         const uint32_t l = (uint32_t)li + 1;
         CHECK(ll.level == l && (ll.items == 4 || ll.items == (uint32_t)PART_ITEMS), "level %u", l);
         CHECK(ll.sorted == (!widest && l % k == 0), "level %u sorted flag", l);
-        if (opt.max_items) CHECK(ll.items <= opt.max_items, "items cap");
+        CHECK(ll.items == 4u || ll.items == (uint32_t)PART_ITEMS, "split tile size");
+        if (opt.max_items == 4) CHECK(ll.items == 4u, "small split tiles only");
         std::vector<std::pair<uint64_t, uint64_t>> hist;
         uint32_t tiles = 0, htiles = 0, ptiles = 0, pwords = 0;
         size_t si = 0;

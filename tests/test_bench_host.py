@@ -73,7 +73,9 @@ def test_committed_records_name_their_kernel_and_workload():
             with open(os.path.join(prof, f)) as fh:
                 rec = json.load(fh)
             assert f == f"traffic_{rec['kernel']}_{rec['workload']}.json"
-            assert rec["hbm_bytes_per_launch"] == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+            # each figure is rounded to whole bytes on its own
+            assert abs(rec["hbm_bytes_per_launch"] - rec["fetch_bytes_per_launch"]
+                       - rec["write_bytes_per_launch"]) <= 1
 
 
 def test_more_than_one_gpu_is_refused():
