@@ -32,11 +32,11 @@ constexpr uint32_t SWEEP_STAGE = 2048;
 // Predecessor windows of the look-back: a short first window (the common
 // case is a nearby inclusive prefix), then wider ones.
 #ifndef KDT_LB_FIRST
-#define KDT_LB_FIRST 4
+#define KDT_LB_FIRST 2
 #endif
 constexpr int LB_FIRST = KDT_LB_FIRST;
 #ifndef KDT_LB_WINDOW
-#define KDT_LB_WINDOW 4
+#define KDT_LB_WINDOW 2
 #endif
 constexpr int LB_WINDOW = KDT_LB_WINDOW;
 
