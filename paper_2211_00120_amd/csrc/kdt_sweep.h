@@ -27,7 +27,10 @@
 namespace kdt {
 
 constexpr int SWEEP_WAVES = SWEEP_THREADS / 64;
-constexpr uint32_t SWEEP_STAGE = 2048;
+#ifndef KDT_SWEEP_STAGE
+#define KDT_SWEEP_STAGE 8192
+#endif
+constexpr uint32_t SWEEP_STAGE = KDT_SWEEP_STAGE;
 
 // Predecessor windows of the look-back: a short first window (the common
 // case is a nearby inclusive prefix), then wider ones.
