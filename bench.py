@@ -6,18 +6,29 @@ are resident in HBM before timing starts; outputs and workspace are
 preallocated.  Prints one JSON line:
 
   value       whole-job build throughput in Mpoints/s (N * steps / time)
-  roofline    the kernel with the largest share of build time, its
-              algorithmic bytes / its HIP-event-measured time against the
-              8 TB/s HBM peak, and (when counters for the current kernel
+  roofline    the kernel with the largest share of build time: the bytes the
+              paper's method moves for the work that kernel completes (each
+              iteration reads and writes every live point's k coordinates and
+              32-bit tag once, 8(k+1) B per live point; the final placement
+              8k B per point) over its HIP-event-measured time, against the
+              8 TB/s HBM peak; the same with this implementation's own byte
+              model ("impl_*"); and (when counters for the current kernel
               sources are committed) its measured HBM traffic per launch
-  cpu_baseline  the CPU oracle timed on a bounded sample of the workload
+  build       the whole build: method bytes per build and, from the committed
+              counters, counted HBM bytes per build, each over the build time
+  cpu_baseline  the CPU oracle (OpenMP tasks on every host core) timed on a
+              bounded, evenly strided sample of the workload, with the core
+              count, the CPU model and the single-core rate
   bit_exact   the GPU tree passes the oracle's full-tree checker (which, the
-              tree being unique, is equality with the oracle's tree)
+              tree being unique, is equality with the oracle's tree), the
+              tree's coordinates equal points[perm] byte for byte, and the
+              device status word is 0
 
 Workloads (--workload):
-  mixture10m   N=10M 3D, half uniform, half 8-component Gaussian mixture, on
-               the 2^-16 grid (heavy ties), round robin  [default]
   cluster100m  N=100M 4D uniform plus a 2^20-point cluster, split-widest
+               [default]
+  mixture10m   N=10M 3D, half uniform, half 8-component Gaussian mixture, on
+               the 2^-16 grid (heavy ties), round robin
   small1024    N=1024 3D uniform, round robin
   uniform      --n points, --k dims, uniform [0,1)^k, round robin (the
                paper's Table 1 workload with k=4)
@@ -41,6 +52,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -97,10 +109,11 @@ def make_workload(name: str, n: int, k: int):
     raise SystemExit(f"unknown workload {name}")
 
 
-def committed_traffic(kernel: str, workload: str, sha: str):
-    """Counter-derived HBM bytes per launch of `kernel`, if committed for the
-    current kernel sources."""
-    path = os.path.join(PROFILE_DIR, f"traffic_{kernel}_{workload}.json")
+def committed_traffic(workload: str, sha: str):
+    """The counter-derived HBM traffic record of `workload`
+    (profiles/traffic_<workload>.json: bytes per launch of every kernel and
+    per build), if it was taken on the current kernel sources."""
+    path = os.path.join(PROFILE_DIR, f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -110,51 +123,130 @@ def committed_traffic(kernel: str, workload: str, sha: str):
     return rec
 
 
+def host_cpu():
+    """(threads this process may run on, CPU model name)."""
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return threads, model
+
+
+def strided_sample(pts, m):
+    """About m points taken at an even stride, so that a workload built as a
+    concatenation of parts (uniform then cluster, uniform then mixture)
+    keeps its mix."""
+    step = max(1, -(-pts.shape[0] // m))
+    return pts[::step]
+
+
 def cpu_baseline(pts, mode, target_s: float):
-    """Time the oracle (single-threaded C) on a prefix of the workload sized to
-    take roughly target_s seconds."""
+    """Time the oracle on an evenly strided sample of the workload sized to
+    take roughly target_s seconds on every host core (OpenMP tasks), and the
+    single-threaded oracle on a smaller sample."""
+    import numpy as np
     import oracle
     omode = oracle.WIDEST if mode == 1 else oracle.RR
-    m = min(pts.shape[0], 200_000)
+    threads, model = host_cpu()
+    # single core: a sample of ~target_s / 4
+    m = min(pts.shape[0], 100_000)
     t0 = time.perf_counter()
-    oracle.build(pts[:m], omode)
-    dt = time.perf_counter() - t0
-    rate = m / max(dt, 1e-9)
-    m2 = int(min(pts.shape[0], max(m, rate * target_s)))
-    if m2 > m:
-        t0 = time.perf_counter()
-        oracle.build(pts[:m2], omode)
-        dt = time.perf_counter() - t0
-        m = m2
-    return {"value": round(m / dt / 1e6, 4), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {m} points of the same workload (same distribution), one build, "
-                      f"{dt:.1f} s on one host core"}
+    oracle.build(strided_sample(pts, m), omode)
+    rate1 = m / max(time.perf_counter() - t0, 1e-9)
+    m1 = int(min(pts.shape[0], max(m, rate1 * target_s / 4)))
+    x = np.ascontiguousarray(strided_sample(pts, m1))
+    t0 = time.perf_counter()
+    oracle.build(x, omode)
+    dt1 = time.perf_counter() - t0
+    rate1 = x.shape[0] / dt1
+    # every core: a sample of ~target_s, from the single-core rate times the cores
+    mp = int(min(pts.shape[0], max(m1, rate1 * max(1, threads // 2) * target_s)))
+    xp = np.ascontiguousarray(strided_sample(pts, mp))
+    t0 = time.perf_counter()
+    oracle.build(xp, omode, threads=threads)
+    dtp = time.perf_counter() - t0
+    return {"value": round(xp.shape[0] / dtp / 1e6, 4), "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "single_core": {"value": round(rate1 / 1e6, 4), "unit": "Mpoints/s",
+                            "sample": f"{x.shape[0]} points, {dt1:.1f} s"},
+            "sample": f"{xp.shape[0]} points of the same workload taken at an even stride (same mix of its "
+                      f"parts), one build by the oracle's recursion with subtrees as OpenMP tasks on {threads} "
+                      f"threads, {dtp:.1f} s"}
 
 
 def kernel_table(prof, steps):
-    """Per-kernel summary and the roofline object of the dominant kernel."""
+    """Per-kernel summary and the roofline object of the dominant kernel (the
+    one with the largest share of event-measured time)."""
     kernels = {}
     if not prof:
         return None, kernels
     total_kernel_ms = sum(v["total_ms"] for v in prof.values())
     for name, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        t = max(v["total_ms"], 1e-12)
         kernels[name] = {
             "launches_per_step": v["launches"] / steps,
             "ms_per_step": round(v["total_ms"] / steps, 4),
             "avg_launch_us": round(v["total_ms"] * 1e3 / max(v["launches"], 1), 3),
             "share": round(v["total_ms"] / max(total_kernel_ms, 1e-12), 4),
-            "alg_GBs": round(v["alg_bytes"] / max(v["total_ms"], 1e-12) / 1e6, 1),
+            "method_GBs": round(v.get("method_bytes", 0.0) / t / 1e6, 1),
+            "impl_GBs": round(v["alg_bytes"] / t / 1e6, 1),
         }
     dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
-    achieved = dom["alg_bytes"] / dom["total_ms"] / 1e6   # GB/s
+    mb = dom.get("method_bytes", 0.0)
+    achieved = mb / dom["total_ms"] / 1e6                  # GB/s
+    impl = dom["alg_bytes"] / dom["total_ms"] / 1e6
     roofline = {
         "bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "alg_bytes_per_launch": round(dom["alg_bytes"] / dom["launches"]),
+        "bytes": "paper method: 8(k+1) B per live point per iteration completed, 8k B per point placed",
+        "bytes_per_launch": round(mb / dom["launches"]),
         "avg_launch_us": round(dom["total_ms"] * 1e3 / dom["launches"], 3),
+        "impl_achieved": round(impl, 1), "impl_frac": round(impl / HBM_PEAK_GBS, 4),
+        "impl_bytes_per_launch": round(dom["alg_bytes"] / dom["launches"]),
         "traffic": None,
     }
     return roofline, kernels
+
+
+def build_rates(prof, steps, ms_per_step, workload):
+    """Whole-build GB/s: the paper method's bytes per build, and (from the
+    committed counters, when they match the sources) the counted HBM bytes
+    per build, each over the un-profiled build time."""
+    out = {"ms": round(ms_per_step, 4)}
+    if prof:
+        mb = sum(v.get("method_bytes", 0.0) for v in prof.values()) / steps
+        ib = sum(v["alg_bytes"] for v in prof.values()) / steps
+        out["method_GB"] = round(mb / 1e9, 3)
+        out["method_GBs"] = round(mb / (ms_per_step * 1e6), 1)
+        out["method_frac"] = round(mb / (ms_per_step * 1e6) / HBM_PEAK_GBS, 4)
+        out["impl_GB"] = round(ib / 1e9, 3)
+        out["impl_GBs"] = round(ib / (ms_per_step * 1e6), 1)
+    tr = committed_traffic(workload, kernel_source_sha())
+    if tr:
+        out["counted_GB"] = round(tr["build_hbm_bytes"] / 1e9, 3)
+        out["counted_GBs"] = round(tr["build_hbm_bytes"] / (ms_per_step * 1e6), 1)
+        out["counted_frac"] = round(tr["build_hbm_bytes"] / (ms_per_step * 1e6) / HBM_PEAK_GBS, 4)
+    else:
+        out["counted_GB"] = out["counted_GBs"] = out["counted_frac"] = None
+    return out
+
+
+def dominant_traffic(roofline, workload):
+    """Counted HBM bytes per launch of the roofline's kernel, or None."""
+    tr = committed_traffic(workload, kernel_source_sha())
+    if not tr or not roofline:
+        return None
+    k = tr.get("kernels", {}).get(roofline["kernel"])
+    return k["hbm_bytes_per_launch"] if k else None
 
 
 def calibration_copy(args, dev):
@@ -233,15 +325,13 @@ def run_batched(args, data, mode, cfg):
     ms_per_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed / 1e6
     if roofline:
-        tr = committed_traffic(roofline["kernel"], cfg["workload"], kernel_source_sha())
-        roofline["traffic"] = tr["hbm_bytes_per_launch"] if tr else None
-        build_alg = sum(v["alg_bytes"] for v in prof.values()) / psteps
-        roofline["build_alg_GBs"] = round(build_alg / (ms_per_step * 1e6), 1)
+        roofline["traffic"] = dominant_traffic(roofline, cfg["workload"])
+    build = build_rates(prof, psteps, ms_per_step, cfg["workload"])
     print(f"# batched graph: {ms_per_step:.3f} ms per build, status {st}", file=sys.stderr, flush=True)
 
     if args.no_per_cloud:
         return {"value": round(value, 3), "ms_per_step": round(ms_per_step, 4), "roofline": roofline,
-                "kernels": kernels, "bit_exact": None, "cpu_baseline": None, "per_cloud": None,
+                "build": build, "kernels": kernels, "bit_exact": None, "cpu_baseline": None, "per_cloud": None,
                 "batched_vs_per_cloud": None}
     # the same clouds as one kdt_build_ws call each, one after another on one
     # stream, preallocated, no host synchronisation between calls
@@ -289,8 +379,8 @@ def run_batched(args, data, mode, cfg):
         cpu = cpu_baseline_clouds(pts, offsets, args.cpu_seconds)
 
     return {
-        "value": round(value, 3), "ms_per_step": round(ms_per_step, 4), "roofline": roofline, "kernels": kernels,
-        "bit_exact": bit_exact, "cpu_baseline": cpu,
+        "value": round(value, 3), "ms_per_step": round(ms_per_step, 4), "roofline": roofline, "build": build,
+        "kernels": kernels, "bit_exact": bit_exact, "cpu_baseline": cpu,
         "per_cloud": {"value": round(n / pc_elapsed * reps / 1e6, 3), "unit": "Mpoints/s",
                       "ms_per_pass": round(pc_ms, 3), "calls": C, "identical_to_batched": same},
         "batched_vs_per_cloud": round(pc_ms / ms_per_step, 3),
@@ -446,21 +536,38 @@ def run_serving(args):
 
 
 def cpu_baseline_clouds(pts, offsets, target_s: float):
-    """The oracle over whole clouds, in order, until about target_s seconds."""
+    """The oracle over whole clouds, in order, until about target_s seconds:
+    one cloud per host thread at a time (clouds are independent), and on one
+    core for comparison."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
+    threads, model = host_cpu()
+    bounds = [(int(offsets[c]), int(offsets[c + 1])) for c in range(len(offsets) - 1)]
+    t0 = time.perf_counter()
+    done1 = 0
+    for a, b in bounds:
+        oracle.build(pts[a:b], oracle.RR)
+        done1 += b - a
+        if time.perf_counter() - t0 > target_s / 4:
+            break
+    dt1 = time.perf_counter() - t0
+    # the C oracle releases the GIL (ctypes), so a thread pool runs clouds in parallel
     t0 = time.perf_counter()
     done = clouds = 0
-    for c in range(len(offsets) - 1):
-        a, b = int(offsets[c]), int(offsets[c + 1])
-        oracle.build(pts[a:b], oracle.RR)
-        done += b - a
-        clouds += 1
-        if time.perf_counter() - t0 > target_s:
-            break
+    with ThreadPoolExecutor(threads) as ex:
+        while clouds < len(bounds) and time.perf_counter() - t0 < target_s:
+            chunk = bounds[clouds:clouds + 4 * threads]
+            list(ex.map(lambda ab: oracle.build(pts[ab[0]:ab[1]], oracle.RR), chunk))
+            done += sum(b - a for a, b in chunk)
+            clouds += len(chunk)
     dt = time.perf_counter() - t0
-    return {"value": round(done / dt / 1e6, 4), "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+    return {"value": round(done / dt / 1e6, 4), "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "single_core": {"value": round(done1 / dt1 / 1e6, 4), "unit": "Mpoints/s",
+                            "sample": f"{done1} points of the first clouds, {dt1:.1f} s"},
             "sample": f"the first {clouds} clouds ({done} points) of the same batch, one build each, "
-                      f"{dt:.1f} s on one host core"}
+                      f"{threads} clouds at a time on {threads} threads, {dt:.1f} s"}
 
 
 def main():
@@ -468,7 +575,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mixture10m")
+    ap.add_argument("--workload", default="cluster100m")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--no-check", action="store_true", help="skip the full-tree bit-exactness check")
@@ -516,7 +623,7 @@ def main():
         out = {"metric": METRIC, "value": r["value"], "unit": "Mpoints/s", "n_gpus": 1, "steps": args.steps,
                "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
                "scaling": "weak", "vs_baseline": None, "dtype": "f32 in, u32 ranks", "data": "synthetic",
-               "config": cfg, "roofline": r["roofline"], "cpu_baseline": r["cpu_baseline"],
+               "config": cfg, "roofline": r["roofline"], "build": r["build"], "cpu_baseline": r["cpu_baseline"],
                "bit_exact": r["bit_exact"], "per_cloud": r["per_cloud"],
                "batched_vs_per_cloud": r["batched_vs_per_cloud"], "kernels": r["kernels"]}
         print(json.dumps(out), flush=True)
@@ -574,19 +681,20 @@ def main():
 
     roofline, kernels = kernel_table(prof, args.steps)
     if roofline:
-        tr = committed_traffic(roofline["kernel"], cfg["workload"], kernel_source_sha())
-        roofline["traffic"] = tr["hbm_bytes_per_launch"] if tr else None
-        build_alg = sum(v["alg_bytes"] for v in prof.values()) / args.steps
-        roofline["build_alg_GBs"] = round(build_alg / (ms_per_step * 1e6), 1)
+        roofline["traffic"] = dominant_traffic(roofline, cfg["workload"])
+    build = build_rates(prof, args.steps, ms_per_step, cfg["workload"])
 
     bit_exact = None
     if not args.no_check:
         import oracle
-        code, node = oracle.check(pts, perm.cpu().numpy().astype(np.uint32), dim.cpu().numpy(),
-                                  oracle.WIDEST if mode == kdt.WIDEST else oracle.RR)
-        same_tree = np.array_equal(tree.cpu().numpy(), pts[perm.cpu().numpy()])
+        h_perm = perm.cpu().numpy().view(np.uint32)
+        t0 = time.perf_counter()
+        code, node = oracle.check(pts, h_perm, dim.cpu().numpy(), oracle.WIDEST if mode == kdt.WIDEST else oracle.RR)
+        print(f"# checker code {code} node {node} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+        # the tree's coordinates are the points in perm order, byte for byte
+        same_tree = tree.cpu().numpy().tobytes() == np.ascontiguousarray(pts[h_perm]).tobytes()
         bit_exact = bool(code == 0 and same_tree and st == 0)
-        print(f"# checker code {code} node {node}, tree gather {same_tree}", file=sys.stderr, flush=True)
+        print(f"# tree bytes equal points[perm]: {same_tree}", file=sys.stderr, flush=True)
 
     cpu = None if args.no_cpu else cpu_baseline(pts, mode, args.cpu_seconds)
 
@@ -605,6 +713,7 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "roofline": roofline,
+        "build": build,
         "cpu_baseline": cpu,
         "bit_exact": bit_exact,
         "kernels": kernels,

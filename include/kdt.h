@@ -3,7 +3,8 @@
  *
  * The library builds the left-balanced, complete k-d tree of Wald,
  * "GPU-friendly, Parallel, and (Almost-)In-Place Construction of Left-Balanced
- * k-d Trees" (arXiv 2211.00120) over N float32 points of dimension k:
+ * k-d Trees" (arXiv 2211.00120) over N float32 (or int32) points of
+ * dimension k:
  *
  *   - the tree is stored in level order, node s has children 2s+1 and 2s+2,
  *     and only the array order carries the topology (Sec. 1, Sec. 2);
@@ -62,6 +63,14 @@ typedef enum kdt_dim_mode {
  * are kept in 30-bit fields. */
 #define KDT_MAX_POINTS 1073741823u
 
+/* Bit of a device status word (kdt_build_ws, kdt_build_batched, server
+ * results): an internal consistency check of the build failed -- a bounds
+ * guard on a scatter or gather, or a bounded wait of the onesweep look-back
+ * or a pivot search that gave up.  The outputs are then unspecified.  No
+ * build of valid arguments in a valid workspace sets it; it turns a corrupt
+ * workspace or a device fault into an error instead of a wrong tree. */
+#define KDT_STATUS_INTERNAL_BIT 0x100u
+
 /* Bytes of device workspace kdt_build_ws needs for (n, k, mode); 0 when the
  * arguments are invalid.  The size depends only on the arguments. */
 size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode);
@@ -80,7 +89,8 @@ size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode);
  *              lowest dimension on ties; defined for leaves too).
  *   d_status   nullable; one uint32 the device sets to KDT_OK or, if any
  *              input coordinate is NaN or infinite, KDT_ENONFINITE (the
- *              outputs are then unspecified).
+ *              outputs are then unspecified); KDT_STATUS_INTERNAL_BIT may be
+ *              or-ed in if an internal check failed (see above).
  *   d_ws       device workspace of at least kdt_workspace_bytes(n,k,mode)
  *              bytes, 256-byte aligned; contents on entry are ignored.
  *
@@ -91,6 +101,32 @@ kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_m
                         float* d_tree, uint32_t* d_perm, uint8_t* d_dim,
                         uint32_t* d_status, void* d_ws, size_t ws_bytes,
                         hipStream_t stream);
+
+/*
+ * kdt_build_ws for int32 coordinates (the paper's int1 workload, Table 1;
+ * Sec. 7.2 templates the builder over the point type).  Same arguments,
+ * workspace size (kdt_workspace_bytes) and outputs, with int32 points and
+ * tree.  Coordinates compare as signed integers, ties by original index;
+ * the split-widest extent of a domain is the exact difference hi - lo (no
+ * int32 overflow).  The status word is always KDT_OK (plus
+ * KDT_STATUS_INTERNAL_BIT on an internal failure): every int32 is finite.
+ */
+kdt_status kdt_build_ws_i32(const int32_t* d_points, uint32_t n, uint32_t k, int dim_mode,
+                            int32_t* d_tree, uint32_t* d_perm, uint8_t* d_dim,
+                            uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/*
+ * Per-point payload in tree order (Sec. 7.2: whatever a point carries moves
+ * with it): record s of d_out is record d_perm[s] of d_in, records of
+ * stride_bytes bytes, for s < n, d_perm being the permutation a build wrote.
+ * d_out must not overlap d_in or d_perm.  An entry d_perm[s] >= n leaves
+ * record s unwritten and sets KDT_STATUS_INTERNAL_BIT in d_status (nullable).
+ * Records move in 16-, 4- or 1-byte units, whichever the pointers and the
+ * stride are aligned to.  Never allocates and never synchronises.
+ */
+kdt_status kdt_permute_payload(const uint32_t* d_perm, uint32_t n, const void* d_in, uint32_t stride_bytes,
+                               void* d_out, uint32_t* d_status, hipStream_t stream);
 
 /*
  * Build in place: on return (once `stream` has run the work) d_points holds
@@ -135,6 +171,12 @@ kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, u
                              uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
                              hipStream_t stream);
 
+/* kdt_build_batched for int32 coordinates (see kdt_build_ws_i32). */
+kdt_status kdt_build_batched_i32(const int32_t* d_points, const uint32_t* h_offsets, uint32_t C,
+                                 uint32_t k, int dim_mode, int32_t* d_tree, uint32_t* d_perm,
+                                 uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
 /* Free every workspace cached by kdt_build and every cached batch plan
  * (synchronises the device first). */
 void kdt_release_cached(void);
@@ -157,8 +199,9 @@ void kdt_release_cached(void);
  */
 typedef struct kdt_tuning {
     uint32_t radix_bits;   /* 0 (planner's choice) or 8..10 */
-    uint32_t level_items;  /* 0 (planner's choice), 4 (split tiles of 512 x 4 records only) or 8 (also the
-                              large split tiles, 512 x 10 records, where an iteration's subtrees fill them) */
+    uint32_t level_items;  /* records per thread of the split tiles: 0 (planner's choice), 4 (tiles of
+                              512 x 4 records only) or 10 (also tiles of 512 x 10 records, where an
+                              iteration's subtrees fill them) */
     uint32_t rank_layout;  /* 0 (planner's choice: 2 when the largest tree's rank table exceeds 128 MiB), 1 (each dimension's
                               last presort pass writes a point-major rank table) or 2 (it writes one rank array
                               per dimension, which a packing pass turns into the point-major table); never
@@ -265,15 +308,22 @@ double kdt_clock(void);
 /*
  * Measurement hook for benchmarks.  While enabled, every kernel a build
  * enqueues is bracketed by a pair of hipEvents recorded on the build's own
- * stream, tagged with the kernel's name and its algorithmic byte count (the
- * bytes the step moves by definition: e.g. a level pass reads and writes
- * 4k bytes per live point).  Enabling adds two event records per launch.
+ * stream and tagged with the kernel's name and two byte counts:
+ *   - alg_bytes: the bytes this implementation's step moves by design (e.g.
+ *     a split pass reads and writes a 4k-byte rank record per live point);
+ *   - method_bytes: the bytes the paper's method moves for the work the
+ *     step completes: each iteration reads and writes every live point's k
+ *     coordinates and 32-bit tag once, 8(k+1) bytes per live point (Sec. 3),
+ *     and the final placement moves every point once more, 8k bytes
+ *     (Sec. 5); steps that only prepare an iteration count 0.
+ * Enabling adds two event records per launch.
  */
 typedef struct kdt_kernel_stat {
-    char name[32];        /* kernel name, e.g. "k_level_pass" */
+    char name[32];        /* kernel name, e.g. "k_level_part" */
     uint64_t launches;    /* launches recorded since the last collect */
     double total_ms;      /* sum of event-measured durations */
-    double alg_bytes;     /* sum of algorithmic bytes */
+    double alg_bytes;     /* sum of the implementation's bytes */
+    double method_bytes;  /* sum of the paper method's bytes */
 } kdt_kernel_stat;
 
 kdt_status kdt_profile_enable(int on);

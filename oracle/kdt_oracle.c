@@ -38,6 +38,15 @@
  *    hi[d]-lo[d] computed in float32; ties go to the lowest dimension.
  *    Every node gets a dimension, leaves included.
  *
+ * Coordinate types: float32 (the paper's float3/float4 points) and int32
+ * (Table 1's int1 rows; Sec. 7.2 templates the builder over the point type).
+ * Every coordinate is read into a double, which holds every float32 and every
+ * int32 value exactly, so all comparisons are those of the input type.  The
+ * split-widest extent of a float32 box is the float32 subtraction of its two
+ * (exact) bounds; that of an int32 box is the exact difference hi - lo (the
+ * paper does not say how an integer extent is formed; this is the reading
+ * adopted here: an int32 subtraction could overflow).
+ *
  * Outputs: perm[s] = original index of the point stored at node s, and
  * dim[s] = split dimension of node s.  The tree's points are P[perm[s]].
  *
@@ -61,6 +70,7 @@
 #include <string.h>
 
 enum { ORACLE_RR = 0, ORACLE_WIDEST = 1 };
+enum { ORACLE_F32 = 0, ORACLE_I32 = 1 };
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -88,7 +98,22 @@ static uint64_t subtree_size(uint64_t s, uint64_t N)
     return total;
 }
 
-typedef struct { float v; uint32_t i; } item_t;
+/* The points: N*k coordinates of one type, row-major. */
+typedef struct {
+    const void* P;
+    int type;          /* ORACLE_F32 or ORACLE_I32 */
+    uint64_t N;
+    uint32_t k;
+} pts_t;
+
+/* Coordinate d of point i, exactly. */
+static double coord(const pts_t* p, uint64_t i, uint32_t d)
+{
+    if (p->type == ORACLE_I32) return (double)((const int32_t*)p->P)[i * p->k + d];
+    return (double)((const float*)p->P)[i * p->k + d];
+}
+
+typedef struct { double v; uint32_t i; } item_t;
 
 /* (coordinate, original index) total order; IEEE compare so -0 == +0. */
 static int item_cmp(const void* a, const void* b)
@@ -100,24 +125,33 @@ static int item_cmp(const void* a, const void* b)
     return (x->i > y->i) - (x->i < y->i);
 }
 
-/* Dimension of largest float32 extent hi[d]-lo[d]; lowest d wins ties. */
-static uint32_t widest_dim(const float* lo, const float* hi, uint32_t k)
+/* Dimension of largest extent hi[d]-lo[d] (float32: computed in float32;
+ * int32: exact); lowest d wins ties. */
+static uint32_t widest_dim(int type, const double* lo, const double* hi, uint32_t k)
 {
     uint32_t best = 0;
-    float best_e = hi[0] - lo[0];
-    for (uint32_t d = 1; d < k; d++) {
-        float e = hi[d] - lo[d];
-        if (e > best_e) { best_e = e; best = d; }
+    if (type == ORACLE_F32) {
+        float best_e = (float)hi[0] - (float)lo[0];
+        for (uint32_t d = 1; d < k; d++) {
+            float e = (float)hi[d] - (float)lo[d];
+            if (e > best_e) { best_e = e; best = d; }
+        }
+    } else {
+        double best_e = hi[0] - lo[0];
+        for (uint32_t d = 1; d < k; d++) {
+            double e = hi[d] - lo[d];
+            if (e > best_e) { best_e = e; best = d; }
+        }
     }
     return best;
 }
 
-static void scene_box(const float* P, uint64_t N, uint32_t k, float* lo, float* hi)
+static void scene_box(const pts_t* p, double* lo, double* hi)
 {
-    for (uint32_t d = 0; d < k; d++) { lo[d] = P[d]; hi[d] = P[d]; }
-    for (uint64_t i = 1; i < N; i++)
-        for (uint32_t d = 0; d < k; d++) {
-            float v = P[i * k + d];
+    for (uint32_t d = 0; d < p->k; d++) { lo[d] = coord(p, 0, d); hi[d] = lo[d]; }
+    for (uint64_t i = 1; i < p->N; i++)
+        for (uint32_t d = 0; d < p->k; d++) {
+            double v = coord(p, i, d);
             if (v < lo[d]) lo[d] = v;
             if (v > hi[d]) hi[d] = v;
         }
@@ -126,50 +160,59 @@ static void scene_box(const float* P, uint64_t N, uint32_t k, float* lo, float* 
 /* ------------------------------------------------------------------ build */
 
 typedef struct {
-    const float* P;
-    uint64_t N;
-    uint32_t k;
+    pts_t pts;
     int mode;
     uint32_t* perm;
     uint8_t* dim;
-    item_t* scratch;   /* N items, reused by every call on its own range */
+    uint32_t* idx0;    /* the index array every call's idx points into */
+    item_t* scratch;   /* N items: a call on idx[0..n) uses the same range of scratch */
+    uint64_t task_min; /* parallel build: subtrees of at least this many points
+                          run their two child calls as separate tasks (0: never) */
 } build_ctx;
 
 /* idx[0..n) holds the original indices of the points of subtree s. */
 static void build(build_ctx* c, uint64_t s, uint32_t* idx, uint64_t n,
-                  const float* lo, const float* hi)
+                  const double* lo, const double* hi)
 {
     if (n == 0) return;
-    const uint32_t k = c->k;
-    uint32_t d = (c->mode == ORACLE_RR) ? node_level(s) % k : widest_dim(lo, hi, k);
+    const uint32_t k = c->pts.k;
+    uint32_t d = (c->mode == ORACLE_RR) ? node_level(s) % k : widest_dim(c->pts.type, lo, hi, k);
 
-    /* sort the subtree's points along d (Observation 2.1) */
-    item_t* it = c->scratch;   /* ranges of sibling calls never overlap in time */
-    for (uint64_t j = 0; j < n; j++) { it[j].v = c->P[(uint64_t)idx[j] * k + d]; it[j].i = idx[j]; }
+    /* sort the subtree's points along d (Observation 2.1); the scratch range
+       is this call's own (the ranges of two subtrees never overlap) */
+    item_t* it = c->scratch + (idx - c->idx0);
+    for (uint64_t j = 0; j < n; j++) { it[j].v = coord(&c->pts, idx[j], d); it[j].i = idx[j]; }
     qsort(it, n, sizeof(item_t), item_cmp);
     for (uint64_t j = 0; j < n; j++) idx[j] = it[j].i;
 
     /* pivot position = size of the left child's subtree */
-    uint64_t m = subtree_size(2 * s + 1, c->N);
+    uint64_t m = subtree_size(2 * s + 1, c->pts.N);
     uint32_t p = idx[m];
     c->perm[s] = p;
     c->dim[s] = (uint8_t)d;
-    float plane = c->P[(uint64_t)p * k + d];
+    double plane = coord(&c->pts, p, d);
 
-    float lo2[4], hi2[4];
-    memcpy(lo2, lo, k * sizeof(float));
-    memcpy(hi2, hi, k * sizeof(float));
+    double lo2[4], hi2[4];
+    memcpy(lo2, lo, k * sizeof(double));
+    memcpy(hi2, hi, k * sizeof(double));
     hi2[d] = plane;                                   /* left child's domain */
-    build(c, 2 * s + 1, idx, m, lo, hi2);
     lo2[d] = plane;                                   /* right child's domain */
-    build(c, 2 * s + 2, idx + m + 1, n - m - 1, lo2, hi);
+    if (c->task_min && n >= c->task_min) {
+        /* the two subtrees touch disjoint ranges of idx, scratch, perm and
+           dim, so they can run at the same time (same results) */
+#pragma omp task default(shared) firstprivate(hi2)
+        build(c, 2 * s + 1, idx, m, lo, hi2);
+#pragma omp task default(shared) firstprivate(lo2)
+        build(c, 2 * s + 2, idx + m + 1, n - m - 1, lo2, hi);
+#pragma omp taskwait
+    } else {
+        build(c, 2 * s + 1, idx, m, lo, hi2);
+        build(c, 2 * s + 2, idx + m + 1, n - m - 1, lo2, hi);
+    }
 }
 
-/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
- * points: N*k float32, row-major (point-major).  perm: N uint32.  dim: N u8.
- * k in [1,4]. */
-int kdt_oracle_build(const float* points, uint64_t N, uint32_t k, int mode,
-                     uint32_t* perm, uint8_t* dim)
+static int build_any(const void* points, int type, uint64_t N, uint32_t k, int mode,
+                     uint32_t* perm, uint8_t* dim, int threads)
 {
     if (k < 1 || k > 4 || (mode != ORACLE_RR && mode != ORACLE_WIDEST)) return -1;
     if (N == 0) return 0;
@@ -178,34 +221,107 @@ int kdt_oracle_build(const float* points, uint64_t N, uint32_t k, int mode,
     item_t* scratch = (item_t*)malloc(N * sizeof(item_t));
     if (!idx || !scratch) { free(idx); free(scratch); return -2; }
     for (uint64_t i = 0; i < N; i++) idx[i] = (uint32_t)i;
-    float lo[4], hi[4];
-    scene_box(points, N, k, lo, hi);
-    build_ctx c = { points, N, k, mode, perm, dim, scratch };
-    build(&c, 0, idx, N, lo, hi);
+    build_ctx c = { { points, type, N, k }, mode, perm, dim, idx, scratch, 0 };
+    double lo[4], hi[4];
+    scene_box(&c.pts, lo, hi);
+    if (threads > 1) {
+        c.task_min = 1u << 14;
+#pragma omp parallel num_threads(threads)
+#pragma omp single
+        build(&c, 0, idx, N, lo, hi);
+    } else {
+        build(&c, 0, idx, N, lo, hi);
+    }
     free(idx);
     free(scratch);
     return 0;
 }
 
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
+ * points: N*k float32, row-major (point-major).  perm: N uint32.  dim: N u8.
+ * k in [1,4]. */
+int kdt_oracle_build(const float* points, uint64_t N, uint32_t k, int mode,
+                     uint32_t* perm, uint8_t* dim)
+{
+    return build_any(points, ORACLE_F32, N, k, mode, perm, dim, 1);
+}
+
+/* The same recursion with the two child calls of every subtree of at least
+ * 2^14 points run as OpenMP tasks on `threads` threads; the output is the
+ * same as kdt_oracle_build's (every call writes only its own subtree's
+ * entries).  Used to time the CPU on all host cores. */
+int kdt_oracle_build_par(const float* points, uint64_t N, uint32_t k, int mode,
+                         uint32_t* perm, uint8_t* dim, int threads)
+{
+    return build_any(points, ORACLE_F32, N, k, mode, perm, dim, threads < 1 ? 1 : threads);
+}
+
+/* kdt_oracle_build and kdt_oracle_build_par for int32 coordinates. */
+int kdt_oracle_build_i32(const int32_t* points, uint64_t N, uint32_t k, int mode,
+                         uint32_t* perm, uint8_t* dim)
+{
+    return build_any(points, ORACLE_I32, N, k, mode, perm, dim, 1);
+}
+
+int kdt_oracle_build_par_i32(const int32_t* points, uint64_t N, uint32_t k, int mode,
+                             uint32_t* perm, uint8_t* dim, int threads)
+{
+    return build_any(points, ORACLE_I32, N, k, mode, perm, dim, threads < 1 ? 1 : threads);
+}
+
 /* ---------------------------------------------------------------- checker */
 
 /* Is point a before point b in the total order along d? */
-static int before(const float* P, uint32_t k, uint32_t d, uint32_t a, uint32_t b)
+static int before(const pts_t* p, uint32_t d, uint32_t a, uint32_t b)
 {
-    float x = P[(uint64_t)a * k + d], y = P[(uint64_t)b * k + d];
+    double x = coord(p, a, d), y = coord(p, b, d);
     if (x < y) return 1;
     if (y < x) return 0;
     return a < b;
 }
 
-/* Returns 0 if (perm, dim) is the tree of `points`, otherwise a positive code
- * naming the first failed property:
- *   1 perm is not a permutation of [0,N)
- *   2 k-d order violated between a node and one of its ancestors
- *   3 a node's dim differs from the split rule
- *  -1 bad arguments, -2 allocation failure.
- * *bad_node (nullable) receives the offending node index. */
-int kdt_oracle_check(const float* points, uint64_t N, uint32_t k, int mode,
+/* The checks of one node s: k-d order against every ancestor, then the split
+ * rule.  Returns 0, 2 or 3 as kdt_oracle_check does; *at receives the node
+ * the failure names. */
+static int check_node(const pts_t* p, int mode, const uint32_t* perm, const uint8_t* dim,
+                      const double* slo, const double* shi, uint64_t s, uint64_t* at)
+{
+    const uint32_t k = p->k;
+    /* k-d order against every ancestor */
+    uint64_t c = s;
+    while (c > 0) {
+        uint64_t a = (c - 1) / 2;
+        int left = (c == 2 * a + 1);
+        uint32_t da = dim[a];
+        if (da >= k) { *at = a; return 3; }
+        int ok = left ? before(p, da, perm[s], perm[a]) : before(p, da, perm[a], perm[s]);
+        if (!ok) { *at = s; return 2; }
+        c = a;
+    }
+    /* split dimension rule */
+    uint32_t want;
+    if (mode == ORACLE_RR) {
+        want = node_level(s) % k;
+    } else {
+        double lo[4], hi[4];
+        memcpy(lo, slo, sizeof lo);
+        memcpy(hi, shi, sizeof hi);
+        c = s;
+        while (c > 0) {   /* clip by each ancestor's plane (intersection) */
+            uint64_t a = (c - 1) / 2;
+            uint32_t da = dim[a];
+            double plane = coord(p, perm[a], da);
+            if (c == 2 * a + 1) { if (plane < hi[da]) hi[da] = plane; }
+            else                { if (plane > lo[da]) lo[da] = plane; }
+            c = a;
+        }
+        want = widest_dim(p->type, lo, hi, k);
+    }
+    if (dim[s] != want) { *at = s; return 3; }
+    return 0;
+}
+
+static int check_any(const void* points, int type, uint64_t N, uint32_t k, int mode,
                      const uint32_t* perm, const uint8_t* dim, uint64_t* bad_node)
 {
     if (k < 1 || k > 4 || (mode != ORACLE_RR && mode != ORACLE_WIDEST)) return -1;
@@ -223,43 +339,43 @@ int kdt_oracle_check(const float* points, uint64_t N, uint32_t k, int mode,
     }
     free(seen);
 
-    float slo[4], shi[4];
-    scene_box(points, N, k, slo, shi);
+    const pts_t p = { points, type, N, k };
+    double slo[4], shi[4];
+    scene_box(&p, slo, shi);
+    /* nodes are independent: check them in parallel, and report the first
+       failing node in index order (what a sequential loop would report) */
+    uint64_t first = N;
+    int code = 0;
+#pragma omp parallel for schedule(dynamic, 65536) if (N >= (1u << 20))
     for (uint64_t s = 0; s < N; s++) {
-        /* k-d order against every ancestor */
-        uint64_t c = s;
-        while (c > 0) {
-            uint64_t a = (c - 1) / 2;
-            int left = (c == 2 * a + 1);
-            uint32_t da = dim[a];
-            if (da >= k) { if (bad_node) *bad_node = a; return 3; }
-            int ok = left ? before(points, k, da, perm[s], perm[a])
-                          : before(points, k, da, perm[a], perm[s]);
-            if (!ok) { if (bad_node) *bad_node = s; return 2; }
-            c = a;
+        uint64_t at = s;
+        int r = check_node(&p, mode, perm, dim, slo, shi, s, &at);
+        if (r) {
+#pragma omp critical
+            if (s < first) { first = s; code = r; if (bad_node) *bad_node = at; }
         }
-        /* split dimension rule */
-        uint32_t want;
-        if (mode == ORACLE_RR) {
-            want = node_level(s) % k;
-        } else {
-            float lo[4], hi[4];
-            memcpy(lo, slo, sizeof lo);
-            memcpy(hi, shi, sizeof hi);
-            c = s;
-            while (c > 0) {   /* clip by each ancestor's plane (intersection) */
-                uint64_t a = (c - 1) / 2;
-                uint32_t da = dim[a];
-                float plane = points[(uint64_t)perm[a] * k + da];
-                if (c == 2 * a + 1) { if (plane < hi[da]) hi[da] = plane; }
-                else                { if (plane > lo[da]) lo[da] = plane; }
-                c = a;
-            }
-            want = widest_dim(lo, hi, k);
-        }
-        if (dim[s] != want) { if (bad_node) *bad_node = s; return 3; }
     }
-    return 0;
+    return code;
+}
+
+/* Returns 0 if (perm, dim) is the tree of `points`, otherwise a positive code
+ * naming the first failed property:
+ *   1 perm is not a permutation of [0,N)
+ *   2 k-d order violated between a node and one of its ancestors
+ *   3 a node's dim differs from the split rule
+ *  -1 bad arguments, -2 allocation failure.
+ * *bad_node (nullable) receives the offending node index. */
+int kdt_oracle_check(const float* points, uint64_t N, uint32_t k, int mode,
+                     const uint32_t* perm, const uint8_t* dim, uint64_t* bad_node)
+{
+    return check_any(points, ORACLE_F32, N, k, mode, perm, dim, bad_node);
+}
+
+/* kdt_oracle_check for int32 coordinates. */
+int kdt_oracle_check_i32(const int32_t* points, uint64_t N, uint32_t k, int mode,
+                         const uint32_t* perm, const uint8_t* dim, uint64_t* bad_node)
+{
+    return check_any(points, ORACLE_I32, N, k, mode, perm, dim, bad_node);
 }
 
 /* Exposed for the oracle's own pins (direct-count subtree size). */

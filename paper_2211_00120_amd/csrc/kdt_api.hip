@@ -44,6 +44,9 @@
 #include "kdt_host.h"
 #include "kdt_plan.h"
 
+static_assert(kdt::KDT_STATUS_INTERNAL == KDT_STATUS_INTERNAL_BIT, "status bit of include/kdt.h");
+
+
 namespace {
 
 using namespace kdt;
@@ -81,8 +84,14 @@ kdt_status check_launch(const char* what)
 
 // ------------------------------------------------------------ profiling
 // While enabled, every kernel enqueued by a build is bracketed by two
-// hipEvents on the build's stream and tagged with its kind and algorithmic
-// bytes (the bytes the step must move by definition).
+// hipEvents on the build's stream and tagged with its kind and two byte
+// counts: the bytes this build's design moves in that step (`bytes`), and
+// the bytes the paper's method moves for the work the step completes
+// (`mbytes`): every iteration reads and writes each live point -- k
+// coordinates and its 32-bit tag, 8(k+1) bytes -- once (Sec. 3), and the
+// final placement moves each point once more, 8k bytes (Sec. 5).  Steps
+// that only prepare an iteration (key prep, presorts, pivot selects) do no
+// such work and count 0.
 enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
             KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_BUCKET, KIND_WINDOW, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
@@ -93,7 +102,7 @@ const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
-    double bytes;
+    double bytes, mbytes;
 };
 struct Profiler {
     std::mutex mu;
@@ -115,7 +124,7 @@ Profiler g_prof;
 
 // Enqueue one kernel (or copy) through `fn`, with profiling events when enabled.
 template <class F>
-kdt_status run_kernel(hipStream_t st, int kind, double bytes, F&& fn)
+kdt_status run_kernel(hipStream_t st, int kind, double bytes, double mbytes, F&& fn)
 {
     hipEvent_t a = nullptr, b = nullptr;
     const bool on = g_prof.on;
@@ -130,9 +139,19 @@ kdt_status run_kernel(hipStream_t st, int kind, double bytes, F&& fn)
     if (on && a && b) {
         std::lock_guard<std::mutex> lk(g_prof.mu);
         (void)hipEventRecord(b, st);
-        g_prof.recs.push_back({kind, a, b, bytes});
+        g_prof.recs.push_back({kind, a, b, bytes, mbytes});
     }
     return KDT_OK;
+}
+
+// Bytes the paper's method moves in the iterations l0 .. L-2 of an n-point
+// tree plus its final placement (see the profiling note above).
+double method_bytes(uint32_t n, uint32_t k, uint32_t l0)
+{
+    const uint32_t L = num_levels(n);
+    double b = 8.0 * k * n;
+    for (uint32_t l = l0; l + 2u <= L; ++l) b += 8.0 * (k + 1.0) * (n - full_nodes(l));
+    return b;
 }
 
 kdt_status validate_k_mode(uint32_t k, int mode)
@@ -201,7 +220,7 @@ Shares shares(const Plan& p, const std::vector<TreeStep>& steps, size_t table_of
 // Enqueue every kernel of a planned call on `st`.  h_tables: the plan's
 // share tables in pinned host memory (needed when p.tables).
 kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim, uint32_t* status,
-                   char* ws, const void* h_tables, hipStream_t st)
+                   char* ws, const void* h_tables, hipStream_t st, bool i32 = false)
 {
     const uint32_t k = p.k;
     const bool widest = p.widest;
@@ -229,8 +248,10 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     o.dimnode = (widest && dim) ? dim : (uint8_t*)(ws + p.o_dimnode);
     o.perm0 = perms;
     o.status = dstatus;
-    o.box[0] = (float*)(ws + p.o_box[0]);
-    o.box[1] = (float*)(ws + p.o_box[1]);
+    o.tstatus = (uint32_t*)(ws + p.o_tstatus);
+    o.box[0] = (uint32_t*)(ws + p.o_box[0]);
+    o.box[1] = (uint32_t*)(ws + p.o_box[1]);
+    o.i32 = i32 ? 1u : 0u;
     o.bbox = (uint32_t*)(ws + p.o_bbox);
 
     if (p.tables) {
@@ -238,7 +259,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             set_err("internal: share tables missing");
             return KDT_EINVAL;
         }
-        if (kdt_status s = run_kernel(st, KIND_TABLES, (double)p.blob.size(), [&] {
+        if (kdt_status s = run_kernel(st, KIND_TABLES, (double)p.blob.size(), 0.0, [&] {
                 (void)hipMemcpyAsync(ws + p.o_tables, h_tables, p.blob.size(), hipMemcpyHostToDevice, st);
             }))
             return s;
@@ -255,10 +276,11 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     // (free after the presorts) and the rank table (free after iteration 0)
     uint32_t* skey[2] = {keys, ranks};
 
-    if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, [&] {
+    if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, 0.0, [&] {
             launch_init(dstatus, counters, hist_rank, nlarge_trees * k * 4 * RADIX_HOST, lb[0],
                         pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, wcount,
-                        p.rank_dm ? k * RANK_MAX_WIN : 0u, o.bbox, nlarge_trees, st);
+                        p.rank_dm ? k * RANK_MAX_WIN : 0u, o.tstatus, (uint32_t)p.trees.size(), o.bbox,
+                        nlarge_trees, st);
         }))
         return s;
 
@@ -268,9 +290,12 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         a.sh = shares(p, p.small, p.t_small, ws);
         a.from_points = 1;
         a.o = o;
-        double bytes = 0;
-        for (const TreeStep& s : p.small) bytes += p.trees[s.tree].n * (8.0 * K + 4.0);
-        if (kdt_status s = run_kernel(st, KIND_WHOLE, bytes,
+        double bytes = 0, mbytes = 0;
+        for (const TreeStep& s : p.small) {
+            bytes += p.trees[s.tree].n * (8.0 * K + 4.0);
+            mbytes += method_bytes(p.trees[s.tree].n, k, 0u);
+        }
+        if (kdt_status s = run_kernel(st, KIND_WHOLE, bytes, mbytes,
                                       [&] { launch_tail((int)k, a, (uint32_t)p.small.size(), widest, st); }))
             return s;
     }
@@ -284,11 +309,11 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         pa.hist = hist_rank;
         pa.ntotal = ntotal;
         pa.o = o;
-        if (kdt_status s = run_kernel(st, KIND_PREP, nlarge * 8.0 * K,
+        if (kdt_status s = run_kernel(st, KIND_PREP, nlarge * 8.0 * K, 0.0,
                                       [&] { launch_prep((int)k, pa, p.prep_tiles, widest, st); }))
             return s;
         if (widest)
-            if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, [&] {
+            if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, 0.0, [&] {
                     launch_root_dim((int)k, shares(p, p.roots, p.t_roots, ws), o, nlarge_trees, st);
                 }))
                 return s;
@@ -354,7 +379,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                             bytes += p.trees[p.large[i]].n * (first ? 12.0 : 16.0);
                         }
                 }
-                if (kdt_status s = run_kernel(st, KIND_PRESORT, bytes,
+                if (kdt_status s = run_kernel(st, KIND_PRESORT, bytes, 0.0,
                                               [&] { launch_presort_pass(a, ps == 3, nd * p.presort_tiles, st); }))
                     return s;
             }
@@ -374,7 +399,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     b.dimnode = widest ? o.dimnode : nullptr;
                     b.dim = d;
                     b.status = dstatus;
-                    if (kdt_status s = run_kernel(st, KIND_BUCKET, nlarge * 12.0,
+                    if (kdt_status s = run_kernel(st, KIND_BUCKET, nlarge * 12.0, 0.0,
                                                   [&] { launch_rank_bucket(b, p.presort_tiles, st); }))
                         return s;
                     RankWindowArgs wa{};
@@ -385,7 +410,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     wa.nwin = p.rank_nwin;
                     wa.chunks = std::max(1u, (1u << p.rank_wbits) / RANK_WIN_CHUNK);
                     wa.ntotal = ntotal;
-                    if (kdt_status s = run_kernel(st, KIND_WINDOW, nlarge * 12.0, [&] { launch_rank_window(wa, st); }))
+                    if (kdt_status s = run_kernel(st, KIND_WINDOW, nlarge * 12.0, 0.0, [&] { launch_rank_window(wa, st); }))
                         return s;
                 }
             }
@@ -396,7 +421,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         uint32_t* rank_table = ranks;
         if (p.rank_dm) {
             rank_table = rec[1];
-            if (kdt_status s = run_kernel(st, KIND_PACK, ntotal * 8.0 * K,
+            if (kdt_status s = run_kernel(st, KIND_PACK, ntotal * 8.0 * K, 0.0,
                                           [&] { launch_rank_pack((int)k, ranks, rank_table, ntotal, st); }))
                 return s;
         }
@@ -420,6 +445,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             a.xmap = p.xmap0.empty() ? nullptr : (const uint32_t*)(ws + p.o_tables + p.t_xmap0);
             const uint32_t grid = p.xmap0.empty() ? p.prep_tiles : (uint32_t)p.xmap0.size();
             if (kdt_status s = run_kernel(st, KIND_LEVEL0, nlarge * (4.0 + 8.0 * K + (keys1 ? 4.0 : 0.0)),
+                                          nlarge * 8.0 * (K + 1.0),
                                           [&] { launch_level0((int)k, a, grid, widest, st); }))
                 return s;
         }
@@ -440,7 +466,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     sa.digit = (uint32_t)j;
                     sa.radix_bits = p.RB;
                     sa.status = dstatus;
-                    if (kdt_status s = run_kernel(st, KIND_SELECT, live * 4.0,
+                    if (kdt_status s = run_kernel(st, KIND_SELECT, live * 4.0, 0.0,
                                                   [&] { launch_level_select(sa, ll.select_tiles, st); }))
                         return s;
                 }
@@ -461,7 +487,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 double segs = 0;
                 for (const TreeStep& s : ll.psteps) segs += make_level(p.trees[s.tree].n, l).nseg;
                 const double per_seg = ll.sorted ? 4.0 * K : 4.0 * p.P * (1u << p.RB);
-                if (kdt_status s = run_kernel(st, KIND_PIVOT, segs * per_seg,
+                if (kdt_status s = run_kernel(st, KIND_PIVOT, segs * per_seg, 0.0,
                                               [&] { launch_level_pivot((int)k, pa, ll.pivot_tiles, widest, st); }))
                     return s;
             }
@@ -486,7 +512,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             a.counter = counters + q;
             a.k = k;
             a.o = o;
-            if (kdt_status s = run_kernel(st, KIND_PART, live * (8.0 * K + (keys_next ? 4.0 : 0.0)),
+            if (kdt_status s = run_kernel(st, KIND_PART, live * (8.0 * K + (keys_next ? 4.0 : 0.0)), live * 8.0 * (K + 1.0),
                                           [&] { launch_level_part((int)k, a, ll.tiles, widest, st); }))
                 return s;
             cur ^= 1;
@@ -502,14 +528,17 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         a.o = o;
         a.xmap = p.xmapt.empty() ? nullptr : (const uint32_t*)(ws + p.o_tables + p.t_xmapt);
         const uint32_t tail_grid = p.xmapt.empty() ? p.tail_groups : (uint32_t)p.xmapt.size();
-        double tail_live = 0;
-        for (const TreeStep& s : p.tail) tail_live += p.trees[s.tree].n - full_nodes(s.level);
-        if (kdt_status s = run_kernel(st, KIND_TAIL, tail_live * 4.0 * K,
+        double tail_live = 0, tail_m = 0;
+        for (const TreeStep& s : p.tail) {
+            tail_live += p.trees[s.tree].n - full_nodes(s.level);
+            tail_m += method_bytes(p.trees[s.tree].n, k, s.level);
+        }
+        if (kdt_status s = run_kernel(st, KIND_TAIL, tail_live * 4.0 * K, tail_m,
                                       [&] { launch_tail((int)k, a, tail_grid, widest, st); }))
             return s;
     }
     if (status)
-        if (kdt_status s = run_kernel(st, KIND_STATUS, 8.0, [&] { launch_copy_word(status, dstatus, st); }))
+        if (kdt_status s = run_kernel(st, KIND_STATUS, 8.0, 0.0, [&] { launch_copy_word(status, dstatus, st); }))
             return s;
     return KDT_OK;
 }
@@ -624,9 +653,9 @@ size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode)
     return workspace_bytes_any(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
 }
 
-kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
-                        uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
-                        hipStream_t stream)
+static kdt_status build_ws_any(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
+                               uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                               hipStream_t stream, bool i32)
 {
     if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
     if (n > KDT_MAX_POINTS) {
@@ -636,7 +665,40 @@ kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_m
     const Plan p = make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
     if (kdt_status s = validate_buffers(p, d_points, d_tree, d_perm, d_dim, d_status, d_ws, ws_bytes)) return s;
     if (n == 0) return write_ok_status(d_status, stream);
-    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, nullptr, stream);
+    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, nullptr, stream, i32);
+}
+
+kdt_status kdt_build_ws(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
+                        uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                        hipStream_t stream)
+{
+    return build_ws_any(d_points, n, k, dim_mode, d_tree, d_perm, d_dim, d_status, d_ws, ws_bytes, stream, false);
+}
+
+kdt_status kdt_build_ws_i32(const int32_t* d_points, uint32_t n, uint32_t k, int dim_mode, int32_t* d_tree,
+                            uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                            hipStream_t stream)
+{
+    // the kernels move coordinates as 32-bit words; only their keys differ
+    return build_ws_any((const float*)d_points, n, k, dim_mode, (float*)d_tree, d_perm, d_dim, d_status, d_ws,
+                        ws_bytes, stream, true);
+}
+
+kdt_status kdt_permute_payload(const uint32_t* d_perm, uint32_t n, const void* d_in, uint32_t stride_bytes,
+                               void* d_out, uint32_t* d_status, hipStream_t stream)
+{
+    if (n == 0 || stride_bytes == 0) return KDT_OK;
+    if (!d_perm || !d_in || !d_out) {
+        set_err("perm, payload and output must not be null");
+        return KDT_EINVAL;
+    }
+    const size_t bytes = (size_t)n * stride_bytes;
+    if (overlaps(d_in, bytes, d_out, bytes) || overlaps(d_perm, (size_t)n * 4, d_out, bytes)) {
+        set_err("the payload output must not overlap its input or the permutation");
+        return KDT_EINVAL;
+    }
+    kdt::launch_permute(d_perm, n, d_in, d_out, stride_bytes, d_status, stream);
+    return check_launch("k_permute");
 }
 
 kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipStream_t stream)
@@ -688,9 +750,9 @@ size_t kdt_batched_workspace_bytes(const uint32_t* h_offsets, uint32_t C, uint32
     return workspace_bytes_any(n, k, dim_mode == KDT_DIM_WIDEST);
 }
 
-kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
-                             int dim_mode, float* d_tree, uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status,
-                             void* d_ws, size_t ws_bytes, hipStream_t stream)
+static kdt_status build_batched_any(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
+                                    int dim_mode, float* d_tree, uint32_t* d_perm, uint8_t* d_dim,
+                                    uint32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream, bool i32)
 {
     if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
     if (kdt_status s = validate_offsets(h_offsets, C)) return s;
@@ -700,7 +762,23 @@ kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, u
     if (kdt_status s = validate_buffers(p, d_points, d_tree, d_perm, d_dim, d_status, d_ws, ws_bytes)) return s;
     if (p.ntotal == 0) return write_ok_status(d_status, stream);
     if (kdt_status s = batched_plan(h_offsets, C, k, dim_mode == KDT_DIM_WIDEST, true, cp)) return s;
-    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, cp->pinned, stream);
+    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)d_ws, cp->pinned, stream, i32);
+}
+
+kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
+                             int dim_mode, float* d_tree, uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status,
+                             void* d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    return build_batched_any(d_points, h_offsets, C, k, dim_mode, d_tree, d_perm, d_dim, d_status, d_ws, ws_bytes,
+                             stream, false);
+}
+
+kdt_status kdt_build_batched_i32(const int32_t* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k,
+                                 int dim_mode, int32_t* d_tree, uint32_t* d_perm, uint8_t* d_dim,
+                                 uint32_t* d_status, void* d_ws, size_t ws_bytes, hipStream_t stream)
+{
+    return build_batched_any((const float*)d_points, h_offsets, C, k, dim_mode, (float*)d_tree, d_perm, d_dim,
+                             d_status, d_ws, ws_bytes, stream, true);
 }
 
 kdt_status kdt_tune_batched(const float* d_points, const uint32_t* h_offsets, uint32_t C, uint32_t k, int dim_mode,
@@ -799,9 +877,10 @@ kdt_status kdt_tuning_set(uint32_t k, int dim_mode, uint32_t rank_bits, const kd
 {
     if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
     if (!t || rank_bits > 32 || (t->radix_bits && (t->radix_bits < 8 || t->radix_bits > 10)) ||
-        (t->level_items && t->level_items != 4 && t->level_items != 8) || t->rank_layout > 2 || t->presort_dims > 4) {
-        set_err("tuning must have radix_bits 0 or 8..10, level_items 0, 4 or 8, rank_layout 0..2 and "
-                "presort_dims 0..4");
+        (t->level_items && t->level_items != 4 && t->level_items != (uint32_t)PART_ITEMS) || t->rank_layout > 2 ||
+        t->presort_dims > 4) {
+        set_err("tuning must have radix_bits 0 or 8..10, level_items 0, 4 or %d, rank_layout 0..2 and "
+                "presort_dims 0..4", PART_ITEMS);
         return KDT_EINVAL;
     }
     PlanOptions o;
@@ -897,6 +976,7 @@ int kdt_profile_collect(kdt_kernel_stat* out, int max_entries)
         acc[r.kind].launches += 1;
         acc[r.kind].total_ms += ms;
         acc[r.kind].alg_bytes += r.bytes;
+        acc[r.kind].method_bytes += r.mbytes;
     }
     g_prof.recs.clear();
     g_prof.used = 0;

@@ -113,51 +113,60 @@ __device__ __forceinline__ float pickf(const float4& p, uint32_t d)
     return d == 0u ? x : (d == 1u ? y : (d == 2u ? z : w));
 }
 
+// Key of coordinate d of local point idx of tree ti (the split plane of the
+// node that point is placed at).
+template <bool I32>
+__device__ __forceinline__ uint32_t plane_key(const Outs& o, const TreeInfo& ti, uint32_t idx, uint32_t d, uint32_t k)
+{
+    const uint32_t* bits = reinterpret_cast<const uint32_t*>(o.pts);
+    return coord_key<I32>(bits[((size_t)ti.off + idx) * k + d]);
+}
+
 // Split-widest (Sec. 6): the domain of a child of subtree s is s's domain
-// bc (lo[0..3], hi[4..7]) clipped by s's plane (left child c = 0: hi =
-// plane, right child c = 1: lo = plane); the child's split dimension is its
-// domain's widest extent.  plane is the pivot's coordinate in s's split
-// dimension ds.
+// bc (keys of lo[0..3], hi[4..7]) clipped by s's plane (left child c = 0:
+// hi = plane, right child c = 1: lo = plane); the child's split dimension is
+// its domain's widest extent.  plane is the key of the pivot's coordinate in
+// s's split dimension ds.
 template <int K>
-__device__ __forceinline__ void split_box(const float* bc, float plane, uint32_t ds, uint32_t c, float (&l2)[K],
-                                          float (&h2)[K])
+__device__ __forceinline__ void split_box(const uint32_t* bc, uint32_t plane, uint32_t ds, uint32_t c,
+                                          uint32_t (&l2)[K], uint32_t (&h2)[K])
 {
 #pragma unroll
     for (int d = 0; d < K; ++d) {
         l2[d] = bc[d];
         h2[d] = bc[4 + d];
         if ((uint32_t)d == ds) {
-            if (c == 0u) h2[d] = fminf(h2[d], plane);
-            else l2[d] = fmaxf(l2[d], plane);
+            if (c == 0u) h2[d] = min(h2[d], plane);
+            else l2[d] = max(l2[d], plane);
         }
     }
 }
 
-template <int K>
-__device__ __forceinline__ uint32_t child_dim(const float* bc, float plane, uint32_t ds, uint32_t c)
+template <int K, bool I32>
+__device__ __forceinline__ uint32_t child_dim(const uint32_t* bc, uint32_t plane, uint32_t ds, uint32_t c)
 {
-    float l2[K], h2[K];
+    uint32_t l2[K], h2[K];
     split_box<K>(bc, plane, ds, c, l2, h2);
-    return widest_dim<K>(l2, h2);
+    return widest_dim<K, I32>(l2, h2);
 }
 
 // Writes the children's dimensions of subtree s (the i-th of its level in
 // tree ti, domain box_cur[box_off + i]) to dimnode and, when box_next is
 // set, their domains to box_next[box_off + 2i (+1)].
-template <int K>
-__device__ void widest_children(const Outs& o, const TreeInfo& ti, uint32_t s, uint32_t i, float plane,
-                                uint32_t ds, const float* box_cur, float* box_next)
+template <int K, bool I32>
+__device__ void widest_children(const Outs& o, const TreeInfo& ti, uint32_t s, uint32_t i, uint32_t plane,
+                                uint32_t ds, const uint32_t* box_cur, uint32_t* box_next)
 {
-    const float* bc = box_cur + ((size_t)ti.box_off + i) * 8;
+    const uint32_t* bc = box_cur + ((size_t)ti.box_off + i) * 8;
 #pragma unroll
     for (uint32_t c = 0; c < 2u; ++c) {
         const uint32_t child = 2u * s + 1u + c;
         if (child >= ti.n) continue;
-        float l2[K], h2[K];
+        uint32_t l2[K], h2[K];
         split_box<K>(bc, plane, ds, c, l2, h2);
-        o.dimnode[(size_t)ti.off + child] = (uint8_t)widest_dim<K>(l2, h2);
+        o.dimnode[(size_t)ti.off + child] = (uint8_t)widest_dim<K, I32>(l2, h2);
         if (box_next) {
-            float* bn = box_next + ((size_t)ti.box_off + 2u * i + c) * 8;
+            uint32_t* bn = box_next + ((size_t)ti.box_off + 2u * i + c) * 8;
 #pragma unroll
             for (int d = 0; d < K; ++d) {
                 bn[d] = l2[d];

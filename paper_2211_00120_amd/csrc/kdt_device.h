@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "kdt_shares.h"
+
 namespace kdt {
 
 constexpr int BLOCK = 256;
@@ -152,7 +154,7 @@ __device__ __forceinline__ uint32_t lookback(uint32_t* lb, uint32_t g, uint32_t 
         const uint32_t f = s & ~LB_VAL;
         if (f == 0u) {
             if (++polls > LB_MAX_POLLS) {
-                atomicOr(status, 0x100u);
+                atomicOr(status, KDT_STATUS_INTERNAL);
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -180,16 +182,43 @@ __device__ __forceinline__ float from_orderable(uint32_t u)
 }
 __device__ __forceinline__ bool nonfinite(uint32_t b) { return (b & 0x7F800000u) == 0x7F800000u; }
 
-// Widest float32 extent of a box; lowest dimension on ties.
-template <int K>
-__device__ __forceinline__ uint32_t widest_dim(const float (&lo)[K], const float (&hi)[K])
+// Order-preserving uint32 key of a coordinate's 32 bits: float32 (orderable
+// above) or int32 (sign bit flipped).  Only float32 can be non-finite.
+template <bool I32>
+__device__ __forceinline__ uint32_t coord_key(uint32_t b)
+{
+    return I32 ? (b ^ 0x80000000u) : orderable(b);
+}
+template <bool I32>
+__device__ __forceinline__ bool coord_bad(uint32_t b)
+{
+    return !I32 && nonfinite(b);
+}
+
+// Split-widest boxes hold the keys of their bounds, so clipping is unsigned
+// min / max for both coordinate types.  The extent hi - lo of one dimension
+// is compared as the input type defines it: float32 subtraction of the two
+// bounds (round to nearest, no flush to zero, may overflow to +inf) or, for
+// int32, the exact difference, which the difference of the keys is.
+// Widest extent of a box; lowest dimension on ties.
+template <int K, bool I32>
+__device__ __forceinline__ uint32_t widest_dim(const uint32_t (&lo)[K], const uint32_t (&hi)[K])
 {
     uint32_t best = 0;
-    float be = __fsub_rn(hi[0], lo[0]);
+    if (I32) {
+        uint32_t be = hi[0] - lo[0];
 #pragma unroll
-    for (int d = 1; d < K; ++d) {
-        const float e = __fsub_rn(hi[d], lo[d]);
-        if (e > be) { be = e; best = (uint32_t)d; }
+        for (int d = 1; d < K; ++d) {
+            const uint32_t e = hi[d] - lo[d];
+            if (e > be) { be = e; best = (uint32_t)d; }
+        }
+    } else {
+        float be = __fsub_rn(from_orderable(hi[0]), from_orderable(lo[0]));
+#pragma unroll
+        for (int d = 1; d < K; ++d) {
+            const float e = __fsub_rn(from_orderable(hi[d]), from_orderable(lo[d]));
+            if (e > be) { be = e; best = (uint32_t)d; }
+        }
     }
     return best;
 }

@@ -36,8 +36,11 @@ struct Outs {
     uint8_t* dimnode;       // split dim per node (split-widest; caller's dim or workspace)
     const uint32_t* perm0;  // per tree: rank in dimension 0 -> local index
     uint32_t* status;       // device status word
-    float* box[2];          // split-widest domains of live subtrees, [level & 1][(box_off + i)*8 + (0..3 lo, 4..7 hi)]
+    uint32_t* tstatus;      // per tree of the call (TreeStep::tree): its own status word (non-finite input)
+    uint32_t* box[2];       // split-widest domains of live subtrees as keys of their bounds,
+                            // [level & 1][(box_off + i)*8 + (0..3 lo, 4..7 hi)]
     uint32_t* bbox;         // per tree: key summary [idx*KEYSUM_WORDS + ...] (scene box, bits that vary)
+    uint32_t i32;           // coordinates are int32 (pts, tree: 32-bit words of int32 values), else float32
 };
 
 struct PrepArgs {
@@ -160,9 +163,13 @@ struct TailArgs {
 };
 
 void launch_set_word(uint32_t* dst, uint32_t value, hipStream_t st);
+// out record s = in record perm[s], records of `stride` bytes, s < n.
+void launch_permute(const uint32_t* perm, uint32_t n, const void* in, void* out, uint32_t stride, uint32_t* status,
+                    hipStream_t st);
 void launch_copy_word(uint32_t* dst, const uint32_t* src, hipStream_t st);
 void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1, uint32_t* z2, uint32_t n2,
-                 uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* bbox, uint32_t nbox, hipStream_t st);
+                 uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* z5, uint32_t n5, uint32_t* bbox,
+                 uint32_t nbox, hipStream_t st);
 void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st);
 void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st);

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kdt_common.h"
 #include "kdt_device.h"
 #include "kdt_kernels.h"
@@ -43,7 +45,8 @@ namespace kdt {
 
 __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1,
                                                 uint32_t* z2, uint32_t n2, uint32_t* z3, uint32_t n3,
-                                                uint32_t* z4, uint32_t n4, uint32_t* bbox, uint32_t nbox)
+                                                uint32_t* z4, uint32_t n4, uint32_t* z5, uint32_t n5,
+                                                uint32_t* bbox, uint32_t nbox)
 {
     const uint32_t gid = blockIdx.x * BLOCK + threadIdx.x;
     if (gid == 0) *status = 0u;
@@ -52,6 +55,7 @@ __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* coun
     zero_range(z2, n2);
     zero_range(z3, n3);
     zero_range(z4, n4);
+    zero_range(z5, n5);
     // per-tree scene boxes as running (min, max) of orderable keys
     // per-tree key summaries: running minima and ANDs start all ones, maxima
     // and ORs all zeros
@@ -63,10 +67,11 @@ __global__ void __launch_bounds__(BLOCK) k_init(uint32_t* status, uint32_t* coun
 // One tile of one tree: uint32 keys (SoA), non-finite flag, the tree's key
 // summary (scene box for split-widest; the bits that are not the same in
 // every key) and the 4 digit histograms of every dimension's presort.
+// I32: the coordinates are int32 (order-preserving key: sign bit flipped).
 #ifndef KDT_PREP_COPIES
 #define KDT_PREP_COPIES 2
 #endif
-template <int K, bool WIDEST>
+template <int K, bool WIDEST, bool I32>
 __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
 {
     // digit counters in PREP_COPIES copies, lane-interleaved: the high key
@@ -100,8 +105,8 @@ __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
 #pragma unroll
         for (int d = 0; d < K; ++d) {
             const uint32_t b = __float_as_uint(a.o.pts[gi * K + d]);
-            bad |= nonfinite(b);
-            const uint32_t u = orderable(b);
+            bad |= coord_bad<I32>(b);
+            const uint32_t u = coord_key<I32>(b);
             a.keys[(size_t)d * a.ntotal + gi] = u;
             if (WIDEST) { lo[d] = min(lo[d], u); hi[d] = max(hi[d], u); }
             kand[d] &= u;
@@ -114,7 +119,10 @@ __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
             }
         }
     }
-    if (__any(bad) && lane_id() == 0) atomicOr(a.o.status, KDT_STATUS_NONFINITE);
+    if (__any(bad) && lane_id() == 0) {
+        atomicOr(a.o.status, KDT_STATUS_NONFINITE);
+        atomicOr(&a.o.tstatus[st.tree], KDT_STATUS_NONFINITE);
+    }
 #pragma unroll
     for (int d = 0; d < K; ++d) {
         if (WIDEST) {
@@ -144,23 +152,24 @@ __global__ void __launch_bounds__(BLOCK) k_prep(PrepArgs a)
     }
 }
 
-// Split-widest: each tree's scene box back to floats (the root's domain) and
-// the root's dimension (Sec. 6).  One thread per share (one share per tree).
-template <int K>
+// Split-widest: each tree's scene box (the keys of its minima and maxima,
+// the root's domain) and the root's dimension (Sec. 6).  One thread per
+// share (one share per tree).
+template <int K, bool I32>
 __global__ void k_root_dim(Shares sh, Outs o, uint32_t ntrees)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntrees) return;
     const TreeInfo ti = sh.steps ? sh.trees[sh.steps[t].tree] : sh.tree0;
-    float lo[K], hi[K];
+    uint32_t lo[K], hi[K];
 #pragma unroll
     for (int d = 0; d < K; ++d) {
-        lo[d] = from_orderable(o.bbox[(size_t)ti.idx * KEYSUM_WORDS + d]);
-        hi[d] = from_orderable(o.bbox[(size_t)ti.idx * KEYSUM_WORDS + 4 + d]);
+        lo[d] = o.bbox[(size_t)ti.idx * KEYSUM_WORDS + d];
+        hi[d] = o.bbox[(size_t)ti.idx * KEYSUM_WORDS + 4 + d];
         o.box[0][(size_t)ti.box_off * 8 + d] = lo[d];
         o.box[0][(size_t)ti.box_off * 8 + 4 + d] = hi[d];
     }
-    o.dimnode[ti.off] = (uint8_t)widest_dim<K>(lo, hi);
+    o.dimnode[ti.off] = (uint8_t)widest_dim<K, I32>(lo, hi);
 }
 
 // ------------------------------------------------------------ presort passes
@@ -437,7 +446,7 @@ void launch_rank_pack(int k, const uint32_t* dm, uint32_t* pm, uint32_t ntotal, 
 // With keys_next, also writes each survivor's split key of iteration 1 (its
 // rank in its subtree's split dimension) and the top-digit histogram of
 // every iteration-1 subtree.
-template <int K, bool WIDEST>
+template <int K, bool WIDEST, bool I32>
 __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
 {
     __shared__ uint32_t nh[2 * MAX_BINS];
@@ -469,10 +478,10 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
         if (WIDEST && acc) {
             uint32_t idx = perm_d0[piv];
             if (!in_bounds(idx, n, a.o.status)) idx = 0;
-            const float plane = a.o.pts[(off + idx) * K + d0];
-            const float* bc = a.o.box[0] + (size_t)ti.box_off * 8;
-            c0 = child_dim<K>(bc, plane, d0, 0u);
-            c1 = child_dim<K>(bc, plane, d0, 1u);
+            const uint32_t plane = plane_key<I32>(a.o, ti, idx, d0, K);
+            const uint32_t* bc = a.o.box[0] + (size_t)ti.box_off * 8;
+            c0 = child_dim<K, I32>(bc, plane, d0, 0u);
+            c1 = child_dim<K, I32>(bc, plane, d0, 1u);
         }
         cdim[0] = c0;
         cdim[1] = c1;
@@ -487,8 +496,8 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
         if (r == piv) {
             place<K, WIDEST>(a.o, ti, 0u, idx);
             if (WIDEST && L >= 2)
-                widest_children<K>(a.o, ti, 0u, 0u, a.o.pts[(off + idx) * K + d0], d0, a.o.box[0],
-                                   L > 2 ? a.o.box[1] : nullptr);
+                widest_children<K, I32>(a.o, ti, 0u, 0u, plane_key<I32>(a.o, ti, idx, d0, K), d0, a.o.box[0],
+                                        L > 2 ? a.o.box[1] : nullptr);
             continue;
         }
         if (L == 2) {                       // N = 2 or 3: children are leaves
@@ -577,6 +586,45 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_select(LevelSelectArgs 
         if (lh[x]) atomicAdd(&dst[x], lh[x]);
 }
 
+// ------------------------------------------------------------ payload
+
+// Per-point payload in tree order: record s of out is record perm[s] of in,
+// each record `words` units of W.  An index outside [0, n) flags an internal
+// error and leaves its record unwritten.
+template <typename W>
+__global__ void __launch_bounds__(BLOCK) k_permute(const uint32_t* __restrict__ perm, uint32_t n,
+                                                  const W* __restrict__ in, W* __restrict__ out, uint32_t words,
+                                                  uint32_t* status)
+{
+    const uint64_t total = (uint64_t)n * words;
+    for (uint64_t x = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; x < total; x += (uint64_t)gridDim.x * BLOCK) {
+        const uint64_t s = x / words, w = x - s * words;
+        const uint32_t i = perm[s];
+        if (i >= n) {
+            if (status) atomicOr(status, KDT_STATUS_INTERNAL);
+            continue;
+        }
+        out[s * words + w] = in[(uint64_t)i * words + w];
+    }
+}
+
+void launch_permute(const uint32_t* perm, uint32_t n, const void* in, void* out, uint32_t stride, uint32_t* status,
+                    hipStream_t st)
+{
+    const uintptr_t align = (uintptr_t)in | (uintptr_t)out | stride;
+    uint32_t unit = (align % 16u) == 0u ? 16u : ((align % 4u) == 0u ? 4u : 1u);
+    const uint32_t words = stride / unit;
+    const uint64_t total = (uint64_t)n * words;
+    if (total == 0) return;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((total + BLOCK - 1) / BLOCK, 1u << 16);
+    if (unit == 16u)
+        k_permute<uint4><<<grid, BLOCK, 0, st>>>(perm, n, (const uint4*)in, (uint4*)out, words, status);
+    else if (unit == 4u)
+        k_permute<uint32_t><<<grid, BLOCK, 0, st>>>(perm, n, (const uint32_t*)in, (uint32_t*)out, words, status);
+    else
+        k_permute<uint8_t><<<grid, BLOCK, 0, st>>>(perm, n, (const uint8_t*)in, (uint8_t*)out, words, status);
+}
+
 __global__ void k_set_word(uint32_t* dst, uint32_t v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
@@ -592,24 +640,31 @@ void launch_set_word(uint32_t* dst, uint32_t value, hipStream_t st) { k_set_word
 void launch_copy_word(uint32_t* dst, const uint32_t* src, hipStream_t st) { k_copy_word<<<1, 64, 0, st>>>(dst, src); }
 
 void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1, uint32_t* z2, uint32_t n2,
-                 uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* bbox, uint32_t nbox, hipStream_t st)
+                 uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* z5, uint32_t n5, uint32_t* bbox,
+                 uint32_t nbox, hipStream_t st)
 {
     uint32_t big = n1 > n2 ? n1 : n2;
     big = big > n3 ? big : n3;
     big = big > n4 ? big : n4;
+    big = big > n5 ? big : n5;
     big = big > MAX_COUNTERS ? big : MAX_COUNTERS;
     big = big > nbox * KEYSUM_WORDS ? big : nbox * KEYSUM_WORDS;
     uint32_t grid = ceil_div(big, BLOCK);
     if (grid > 2048) grid = 2048;
     if (grid == 0) grid = 1;
-    k_init<<<grid, BLOCK, 0, st>>>(status, counters, z1, n1, z2, n2, z3, n3, z4, n4, bbox, nbox);
+    k_init<<<grid, BLOCK, 0, st>>>(status, counters, z1, n1, z2, n2, z3, n3, z4, n4, z5, n5, bbox, nbox);
 }
 
 template <int K>
 static void prep_k(const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st)
 {
-    if (widest) k_prep<K, true><<<tiles, BLOCK, 0, st>>>(a);
-    else k_prep<K, false><<<tiles, BLOCK, 0, st>>>(a);
+    if (a.o.i32) {
+        if (widest) k_prep<K, true, true><<<tiles, BLOCK, 0, st>>>(a);
+        else k_prep<K, false, true><<<tiles, BLOCK, 0, st>>>(a);
+    } else {
+        if (widest) k_prep<K, true, false><<<tiles, BLOCK, 0, st>>>(a);
+        else k_prep<K, false, false><<<tiles, BLOCK, 0, st>>>(a);
+    }
 }
 
 void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st)
@@ -622,14 +677,21 @@ void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStrea
     }
 }
 
-void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st)
+template <int K>
+static void root_dim_k(const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st)
 {
     const uint32_t grid = ceil_div(ntrees, 64u);
+    if (o.i32) k_root_dim<K, true><<<grid, 64, 0, st>>>(sh, o, ntrees);
+    else k_root_dim<K, false><<<grid, 64, 0, st>>>(sh, o, ntrees);
+}
+
+void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st)
+{
     switch (k) {
-    case 1: k_root_dim<1><<<grid, 64, 0, st>>>(sh, o, ntrees); break;
-    case 2: k_root_dim<2><<<grid, 64, 0, st>>>(sh, o, ntrees); break;
-    case 3: k_root_dim<3><<<grid, 64, 0, st>>>(sh, o, ntrees); break;
-    default: k_root_dim<4><<<grid, 64, 0, st>>>(sh, o, ntrees); break;
+    case 1: root_dim_k<1>(sh, o, ntrees, st); break;
+    case 2: root_dim_k<2>(sh, o, ntrees, st); break;
+    case 3: root_dim_k<3>(sh, o, ntrees, st); break;
+    default: root_dim_k<4>(sh, o, ntrees, st); break;
     }
 }
 
@@ -642,8 +704,10 @@ void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStr
 template <int K>
 static void level0_k(const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st)
 {
-    if (widest) k_level0<K, true><<<tiles, BLOCK, 0, st>>>(a);
-    else k_level0<K, false><<<tiles, BLOCK, 0, st>>>(a);
+    // round robin never reads a coordinate here: one instantiation
+    if (!widest) k_level0<K, false, false><<<tiles, BLOCK, 0, st>>>(a);
+    else if (a.o.i32) k_level0<K, true, true><<<tiles, BLOCK, 0, st>>>(a);
+    else k_level0<K, true, false><<<tiles, BLOCK, 0, st>>>(a);
 }
 
 void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st)

@@ -35,13 +35,25 @@
 
 namespace kdt {
 
+// Every shift count below 32 and every clz argument non-zero, for every
+// argument value: the edges (n = 0, l >= L - 1, s = 2^32 - 1, l >= 32) get
+// defined results instead of undefined behaviour.
 KDT_HD uint32_t num_levels(uint32_t n) { return n ? 32u - (uint32_t)__builtin_clz(n) : 0u; }
-KDT_HD uint32_t level_of(uint32_t s) { return 31u - (uint32_t)__builtin_clz(s + 1u); }
-KDT_HD uint32_t full_nodes(uint32_t l) { return (1u << l) - 1u; }            // F(l)
-KDT_HD uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
-KDT_HD uint32_t clamp_sub(uint32_t r, uint32_t x, uint32_t cap)             // clamp(r - x, 0, cap)
+KDT_HD uint32_t level_of(uint32_t s)                                         // 32 for s = 2^32 - 1
 {
-    return r > x ? umin(r - x, cap) : 0u;
+    return s == 0xFFFFFFFFu ? 32u : 31u - (uint32_t)__builtin_clz(s + 1u);
+}
+KDT_HD uint32_t full_nodes(uint32_t l) { return l >= 32u ? 0xFFFFFFFFu : (1u << l) - 1u; }   // F(l)
+KDT_HD uint32_t pow2(uint32_t e) { return e >= 32u ? 0u : 1u << e; }       // 2^e, 0 once it overflows
+KDT_HD uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+// clamp(r - x, 0, cap), written without a branch: the guarded form
+// `r > x ? min(r - x, cap) : 0` let the gfx950 compiler (ROCm 7.2 LLVM)
+// hoist the min out of its branch with the no-wrap facts of the guarded
+// subtraction still attached, and then fold an unrelated min(x, r) that
+// follows (the one in seg_offset) to x.
+KDT_HD uint32_t clamp_sub(uint32_t r, uint32_t x, uint32_t cap)
+{
+    return umin(r - umin(r, x), cap);
 }
 // Bits needed to write every rank 0..n-1.
 KDT_HD uint32_t rank_bits(uint32_t n) { return n > 1 ? 32u - (uint32_t)__builtin_clz(n - 1u) : 0u; }
@@ -63,9 +75,10 @@ KDT_HD Level make_level(uint32_t n, uint32_t l)
     v.n = n;
     v.l = l;
     v.L = num_levels(n);
-    v.W = 1u << (v.L - l - 1u);
-    v.R = n - full_nodes(v.L - 1u);
-    v.nseg = 1u << l;
+    // levels l >= L have no subtrees: W = 0 (only l <= L - 2 is ever split)
+    v.W = l < v.L ? pow2(v.L - l - 1u) : 0u;
+    v.R = v.L ? n - full_nodes(v.L - 1u) : 0u;
+    v.nseg = pow2(l);
     v.Fl = full_nodes(l);
     return v;
 }
@@ -79,10 +92,13 @@ KDT_HD uint32_t seg_left_size(const Level& v, uint32_t i)                   // s
 }
 KDT_HD uint32_t seg_pivot(const Level& v, uint32_t i) { return seg_offset(v, i) + seg_left_size(v, i); }
 
-// Live position -> subtree index on level l (inverse of seg_offset).
-// Requires W >= 2 (levels 0..L-2), so every subtree is non-empty.
+// Live position -> subtree index on level l (inverse of seg_offset).  On
+// levels 0..L-2 (W >= 2) every subtree is non-empty; on level L-1 (W = 1)
+// the subtrees are single nodes and position p is subtree p; a level below
+// the tree (W = 0) has none, and 0 is returned.
 KDT_HD uint32_t seg_of_pos(const Level& v, uint32_t p)
 {
+    if (v.W < 2u) return v.W ? p : 0u;
     uint32_t big = 2u * v.W - 1u;
     uint32_t a = v.R / v.W;                // number of full subtrees
     if (a >= v.nseg) return p / big;
@@ -130,7 +146,7 @@ KDT_HD SegTiles tiles_single(uint32_t n, uint32_t tile) { return make_tiles(1u, 
 // The subtrees of iteration l.
 KDT_HD SegTiles tiles_level(const Level& v, uint32_t tile)
 {
-    uint32_t a = v.R / v.W;
+    uint32_t a = v.W ? v.R / v.W : 0u;
     uint32_t mid = (v.W - 1u) + (a < v.nseg ? v.R - a * v.W : 0u);
     return make_tiles(v.nseg, a, 2u * v.W - 1u, mid, v.W - 1u, tile);
 }

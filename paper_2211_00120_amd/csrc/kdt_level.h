@@ -30,7 +30,7 @@ namespace kdt {
 // Digit of the split pass: 0 smaller key, 1 the pivot, 2 larger key.
 constexpr int PART_RB = 2;
 
-template <int K, bool WIDEST>
+template <int K, bool WIDEST, bool I32>
 __global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs a)
 {
     TreeStep st;
@@ -45,11 +45,8 @@ __global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs 
     const uint32_t s = v.Fl + seg;
     uint32_t p = 0;
     if (a.sorted) {
-        // the pivot's position: segment start from the segment-size
-        // arithmetic the split pass uses (the equivalent seg_offset form,
-        // next to seg_left_size in this kernel, lost its min() to the
-        // optimiser)
-        const uint32_t pos = tiles_seg_offset(tiles_level(v, 1u), seg) + ls;
+        // the pivot's position in the live array
+        const uint32_t pos = seg_offset(v, seg) + ls;
         p = pick4(load_rec4<K>(a.rin, off + pos), d);
     } else {
         const uint32_t RBv = a.radix_bits;
@@ -66,11 +63,11 @@ __global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs 
     place<K, WIDEST>(a.o, ti, s, idx);
     uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;
     if (WIDEST) {
-        const float plane = a.o.pts[(off + idx) * K + d];
-        const float* bc = a.o.box[st.level & 1u] + ((size_t)ti.box_off + seg) * 8;
-        c0 = child_dim<K>(bc, plane, d, 0u);
-        c1 = child_dim<K>(bc, plane, d, 1u);
-        widest_children<K>(a.o, ti, s, seg, plane, d, a.o.box[st.level & 1u], a.o.box[(st.level + 1u) & 1u]);
+        const uint32_t plane = plane_key<I32>(a.o, ti, idx, d, K);
+        const uint32_t* bc = a.o.box[st.level & 1u] + ((size_t)ti.box_off + seg) * 8;
+        c0 = child_dim<K, I32>(bc, plane, d, 0u);
+        c1 = child_dim<K, I32>(bc, plane, d, 1u);
+        widest_children<K, I32>(a.o, ti, s, seg, plane, d, a.o.box[st.level & 1u], a.o.box[(st.level + 1u) & 1u]);
     }
     a.piv[st.piv + 2u * seg] = p;
     a.piv[st.piv + 2u * seg + 1u] = c0 | (c1 << 8);
@@ -176,8 +173,10 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
 template <int K>
 void launch_level_pivot_k(const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st)
 {
-    if (widest) k_level_pivot<K, true><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
-    else k_level_pivot<K, false><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
+    // round robin never reads a coordinate here: one instantiation
+    if (!widest) k_level_pivot<K, false, false><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
+    else if (a.o.i32) k_level_pivot<K, true, true><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
+    else k_level_pivot<K, true, false><<<tiles, 64 * PIVOT_SEGS, 0, st>>>(a);
 }
 
 template <int K, int ITEMS>

@@ -16,10 +16,11 @@ namespace kdt {
 namespace {
 
 // Records per thread of an iteration's split tiles (tile = SWEEP_THREADS * items): the
-// largest tile that the iteration's biggest subtree still fills.
+// largest tile, up to `cap` records per thread, that the iteration's biggest
+// subtree still fills.
 uint32_t level_items(uint32_t big, uint32_t cap)
 {
-    const uint32_t large = cap >= 8u ? (uint32_t)PART_ITEMS : 4u;
+    const uint32_t large = cap == (uint32_t)PART_ITEMS ? (uint32_t)PART_ITEMS : 4u;
     return big >= (uint32_t)SWEEP_THREADS * large ? large : 4u;
 }
 
@@ -54,7 +55,7 @@ std::vector<PlanOptions> tuning_candidates()
 {
     std::vector<PlanOptions> c;
     for (uint32_t rb : {8u, 9u, 10u})
-        for (uint32_t items : {4u, 8u})
+        for (uint32_t items : {4u, (uint32_t)PART_ITEMS})
             for (uint32_t dims : {1u, PRESORT_GROUP}) {
                 PlanOptions o;
                 o.radix_bits = rb;
@@ -106,7 +107,7 @@ bool load_tuning(const char* path)
     int r;
     bool ok = true;
     while ((r = fscanf(f, "%u %u %u %u %u %u %u", &k, &w, &bits, &rb, &items, &layout, &dims)) == 7) {
-        if (k < 1 || k > 4 || w > 1 || bits > 32 || (rb && (rb < 8 || rb > 10)) || (items && items != 4 && items != 8) ||
+        if (k < 1 || k > 4 || w > 1 || bits > 32 || (rb && (rb < 8 || rb > 10)) || (items && items != 4 && items != (unsigned)PART_ITEMS) ||
             layout > 2 || dims > 4) {
             ok = false;
             break;
@@ -199,7 +200,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
         if (opt.radix_bits >= 8 && opt.radix_bits <= 10) p.RB = opt.radix_bits;
         p.P = (p.B + p.RB - 1u) / p.RB;
     }
-    const uint32_t items_cap = (opt.max_items == 4 || opt.max_items == 8) ? opt.max_items : 8u;
+    const uint32_t items_cap = opt.max_items == 4u ? 4u : (uint32_t)PART_ITEMS;
     // rank table layout (k = 1 scatters nothing: the only dimension is the
     // root's); the tiles of one tree run together, so the largest tree's
     // table is what the scatters of a pass spread over
@@ -425,6 +426,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_piv = take((size_t)p.piv_words * 4);
     p.o_tables = take(p.tables ? p.blob.size() : 0);
     p.o_wcount = take((size_t)k * RANK_MAX_WIN * 4);
+    p.o_tstatus = take((size_t)T * 4);        // a status word per tree
     p.total = o;
     return p;
 }

@@ -24,7 +24,7 @@ constexpr uint32_t NO_HIST = 0xFFFFFFFFu;
 // Choices the planner otherwise makes itself (0 = automatic).
 struct PlanOptions {
     uint32_t radix_bits = 0;   // digit width of the pivot selects: 8, 9 or 10
-    uint32_t max_items = 0;    // split tiles: 4 (512 x 4 only) or 8 (also 512 x PART_ITEMS)
+    uint32_t max_items = 0;    // records per thread of the split tiles: 4 (512 x 4 only) or PART_ITEMS (also 512 x PART_ITEMS)
     uint32_t rank_layout = 0;  // 1: point-major rank table, 2: per-dimension rank arrays + packing pass
     uint32_t presort_dims = 0; // dimensions whose presort digit passes share a launch: 1..4 (clamped to k)
 };
@@ -91,7 +91,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_status = 0, o_counters = 0, o_hist_rank = 0, o_hist = 0, o_lb[2] = {0, 0}, o_keys = 0, o_perms = 0,
            o_ranks = 0, o_rec = 0, o_nodeperm = 0, o_dimnode = 0, o_box[2] = {0, 0}, o_bbox = 0, o_piv = 0, o_tables = 0,
-           o_wcount = 0, total = 0;
+           o_wcount = 0, o_tstatus = 0, total = 0;
     size_t rec_words = 0;            // words per record buffer
 };
 

@@ -7,7 +7,8 @@
 //   2. while a batch slot is free, asks choose_batch for the next batch of
 //      queued requests that fits the pool, carves its blocks and enqueues it
 //      on the slot's stream: copy-in of every request's points, the batched
-//      build, copy-back of the status word, completion event.
+//      build, copy-back of the batch's status word and of each request's own
+//      status word, completion event.
 // Submitters, pollers and releasers only touch the queue and the request
 // table under the server mutex; the worker enqueues device work outside it.
 #include <hip/hip_runtime.h>
@@ -76,7 +77,8 @@ struct Slot {
     hipEvent_t start = nullptr, done = nullptr;
     void* pinned = nullptr;                // share tables of the running batch
     size_t pinned_bytes = 0;
-    uint32_t* h_status = nullptr;          // pinned copy of the batch status word
+    uint32_t* h_status = nullptr;          // pinned: the batch status word, then one word per request
+    size_t h_status_words = 0;
     std::shared_ptr<Batch> batch;          // running batch, if any
 };
 
@@ -121,6 +123,14 @@ void kdt_server::launch(Slot& sl, const std::shared_ptr<Batch>& b)
     const Plan& p = b->plan;
     hipStream_t st = sl.stream;
     bool ok = hipEventRecord(sl.start, st) == hipSuccess;
+    if (ok && sl.h_status_words < 1 + b->reqs.size()) {
+        // the slot has no batch in flight, so its status words are free
+        if (sl.h_status) (void)hipHostFree(sl.h_status);
+        sl.h_status = nullptr;
+        sl.h_status_words = 0;
+        ok = hipHostMalloc((void**)&sl.h_status, (1 + b->reqs.size()) * 4, hipHostMallocDefault) == hipSuccess;
+        if (ok) sl.h_status_words = 1 + b->reqs.size();
+    }
     for (auto& r : b->reqs)
         if (ok && r->n)
             ok = hipMemcpyAsync(b->points() + r->off * p.k, r->h_points, (size_t)r->n * r->k * 4,
@@ -141,7 +151,12 @@ void kdt_server::launch(Slot& sl, const std::shared_ptr<Batch>& b)
         rc = enqueue_plan(p, b->points(), b->tree(), b->perm(), b->dim(), b->status(), b->base + b->ws_off,
                           sl.pinned, st);
     if (rc == KDT_OK) {
+        // the batch's status word, then each request's own (tree t of the
+        // plan is request t of the batch), read by retire()
+        const size_t nt = p.trees.size();
         ok = hipMemcpyAsync(sl.h_status, b->status(), 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
+             hipMemcpyAsync(sl.h_status + 1, b->base + b->ws_off + p.o_tstatus, nt * 4, hipMemcpyDeviceToHost,
+                            st) == hipSuccess &&
              hipEventRecord(sl.done, st) == hipSuccess;
         if (!ok) rc = KDT_EDEVICE;
     }
@@ -163,10 +178,16 @@ void kdt_server::retire(Slot& sl)
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, sl.start, sl.done);
     b->device_ms = ms;
-    const uint32_t dev_status = *sl.h_status;
+    // each request's result is its own build's: non-finite input is
+    // reported per request; an internal failure of the batch fails them all
+    const uint32_t dev_status = sl.h_status[0];
     const double t = now_s();
-    for (auto& r : b->reqs) {
-        r->status = (dev_status & KDT_ENONFINITE) ? KDT_ENONFINITE : (dev_status ? KDT_EDEVICE : KDT_OK);
+    for (size_t j = 0; j < b->reqs.size(); ++j) {
+        auto& r = b->reqs[j];
+        const uint32_t own = sl.h_status[1 + j];
+        r->status = (dev_status & KDT_STATUS_INTERNAL) ? KDT_EDEVICE
+                    : (own & KDT_ENONFINITE)          ? KDT_ENONFINITE
+                                                       : KDT_OK;
         r->state = DONE;
         r->t_done = t;
     }
@@ -319,7 +340,8 @@ kdt_status kdt_server_create(const kdt_server_config* cfg, kdt_server** out)
     for (Slot& sl : s->slots) {
         bool ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreate(&sl.start) == hipSuccess && hipEventCreate(&sl.done) == hipSuccess &&
-                  hipHostMalloc((void**)&sl.h_status, 4, hipHostMallocDefault) == hipSuccess;
+                  hipHostMalloc((void**)&sl.h_status, 2 * 4, hipHostMallocDefault) == hipSuccess;
+        if (ok) sl.h_status_words = 2;
         if (!ok) {
             (void)hipGetLastError();
             set_last_error("could not create the server's streams or events");

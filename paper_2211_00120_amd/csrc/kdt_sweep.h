@@ -155,7 +155,7 @@ __device__ __forceinline__ uint32_t find_bucket(const uint32_t (&c)[FIND_BPT], u
     uint32_t rest = sel[1];
     __syncthreads();
     if (bk == 0xFFFFFFFFu) {
-        if (threadIdx.x == 0) atomicOr(status, 0x100u);
+        if (threadIdx.x == 0) atomicOr(status, KDT_STATUS_INTERNAL);
         bk = 0u;
         rest = 0u;
     }
@@ -181,7 +181,7 @@ __device__ __forceinline__ uint32_t wave_find_bucket(const uint32_t* h, uint32_t
     const uint32_t ex = wave_incl_scan(sum) - sum;
     const uint64_t hit = __ballot(kk >= ex && kk - ex < sum);
     if (hit == 0u) {
-        if (lane == 0) atomicOr(status, 0x100u);
+        if (lane == 0) atomicOr(status, KDT_STATUS_INTERNAL);
         kk = 0u;
         return 0u;
     }
@@ -246,7 +246,7 @@ __device__ __forceinline__ bool lookback_round(const uint32_t* lb, uint32_t NB, 
         uint32_t polls = 0;
         while ((s & ~LB_VAL) == 0u) {
             if (++polls > LB_MAX_POLLS) {
-                atomicOr(status, 0x100u);
+                atomicOr(status, KDT_STATUS_INTERNAL);
                 return true;
             }
             __builtin_amdgcn_s_sleep(1);

@@ -25,8 +25,9 @@
 //
 // A whole tree of at most TAIL_CAP points is built the same way straight
 // from its points (from_points): the per-dimension orders come from a stable
-// radix sort of the order-preserving float keys starting in index order, so
-// equal coordinates keep index order, and the loop starts at iteration 0.
+// radix sort of the order-preserving coordinate keys (float32 or int32)
+// starting in index order, so equal coordinates keep index order, and the
+// loop starts at iteration 0.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,10 +42,12 @@ namespace kdt {
 constexpr uint32_t DONE = 0xFFFFu;
 
 // Domain of local node (t, q) for split-widest: the subtree root's box
-// clipped by the planes of its local ancestors (stored per local node).
+// clipped by the planes of its local ancestors (stored per local node); all
+// bounds and planes are coordinate keys (see widest_dim).
 template <int K>
-__device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, const float (*rootbox)[8],
-                                          const uint8_t* ndim, const float* nplane, float (&lo)[K], float (&hi)[K])
+__device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, const uint32_t (*rootbox)[8],
+                                          const uint8_t* ndim, const uint32_t* nplane, uint32_t (&lo)[K],
+                                          uint32_t (&hi)[K])
 {
     const uint32_t r = q >> t;
 #pragma unroll
@@ -57,12 +60,12 @@ __device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, c
         const uint32_t pq = qq >> 1;
         const uint32_t idx = gc * ((1u << (tt - 1u)) - 1u) + pq;
         const uint32_t da = ndim[idx];
-        const float plane = nplane[idx];
+        const uint32_t plane = nplane[idx];
 #pragma unroll
         for (int d = 0; d < K; ++d) {
             if ((uint32_t)d == da) {
-                if ((qq & 1u) == 0u) hi[d] = fminf(hi[d], plane);
-                else lo[d] = fmaxf(lo[d], plane);
+                if ((qq & 1u) == 0u) hi[d] = min(hi[d], plane);
+                else lo[d] = max(lo[d], plane);
             }
         }
         qq = pq;
@@ -228,7 +231,7 @@ __device__ __forceinline__ bool tail_bucket_sort(const uint32_t (&key)[ITEMS], c
     return true;
 }
 
-template <int K, bool WIDEST>
+template <int K, bool WIDEST, bool I32>
 __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 {
     constexpr int ITEMS = TAIL_ITEMS;
@@ -260,8 +263,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     __shared__ uint16_t wl[WIDEST ? C : 1];        // split-widest: the iteration's walk list
     __shared__ uint32_t lcnt[WIDEST ? K : 1][NW];  // split-widest: walk-list slots per (dimension, wave)
     __shared__ uint8_t ndim[NODES];
-    __shared__ float nplane[NODES];
-    __shared__ float rootbox[2][8];
+    __shared__ uint32_t nplane[NODES];             // keys of the fixed local nodes' planes
+    __shared__ uint32_t rootbox[2][8];             // keys of the group roots' domains
     __shared__ uint32_t bxk[8];                    // from_points split-widest: scene box keys
 
     const Outs& o = a.o;
@@ -314,8 +317,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 #pragma unroll
             for (int d = 0; d < K; ++d) {
                 const uint32_t bits = __float_as_uint(cf[d]);
-                bad |= ok[i] && nonfinite(bits);
-                kk[d] = orderable(bits);
+                bad |= ok[i] && coord_bad<I32>(bits);
+                kk[d] = coord_key<I32>(bits);
             }
             rec[i] = ok[i] ? make_uint4(kk[0], kk[1], kk[2], kk[3]) : make_uint4(0u, 0u, 0u, 0u);
             seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
@@ -341,9 +344,12 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
         }
     }
     if (FP) {
-        if (__any(bad) && lane == 0) atomicOr(o.status, KDT_STATUS_NONFINITE);
+        if (__any(bad) && lane == 0) {
+            atomicOr(o.status, KDT_STATUS_NONFINITE);
+            atomicOr(&o.tstatus[stp.tree], KDT_STATUS_NONFINITE);
+        }
         if (WIDEST) {
-            // scene box of the tree (as orderable keys, then floats)
+            // scene box of the tree (keys)
             if (threadIdx.x < 8) bxk[threadIdx.x] = threadIdx.x < 4 ? 0xFFFFFFFFu : 0u;
             __syncthreads();
 #pragma unroll
@@ -357,15 +363,15 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             }
             __syncthreads();
             if (threadIdx.x == 0) {
-                float lo[K], hi[K];
+                uint32_t lo[K], hi[K];
 #pragma unroll
                 for (int d = 0; d < K; ++d) {
-                    lo[d] = from_orderable(bxk[d]);
-                    hi[d] = from_orderable(bxk[4 + d]);
+                    lo[d] = bxk[d];
+                    hi[d] = bxk[4 + d];
                     rootbox[0][d] = lo[d];
                     rootbox[0][4 + d] = hi[d];
                 }
-                const uint32_t d0 = widest_dim<K>(lo, hi);
+                const uint32_t d0 = widest_dim<K, I32>(lo, hi);
                 segdim[0][0] = (uint8_t)d0;
                 o.dimnode[off] = (uint8_t)d0;
             }
@@ -376,7 +382,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     if (!FP && WIDEST && threadIdx.x < gc) {
         // domain of each group root, written by its parent's pivot
         const uint32_t q = threadIdx.x;
-        const float* bx = o.box[l0 & 1u] + ((size_t)ti.box_off + i0 + q) * 8;
+        const uint32_t* bx = o.box[l0 & 1u] + ((size_t)ti.box_off + i0 + q) * 8;
 #pragma unroll
         for (int d = 0; d < 8; ++d) rootbox[q][d] = bx[d];
         segdim[0][q] = o.dimnode[off + v0.Fl + i0 + q];
@@ -556,7 +562,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
                     const uint32_t ds = segdim[cur][q];
                     const uint32_t nidx = gc * ((1u << t) - 1u) + q;
                     ndim[nidx] = (uint8_t)ds;
-                    nplane[nidx] = pickf(pc[i], ds);
+                    nplane[nidx] = coord_key<I32>(__float_as_uint(pickf(pc[i], ds)));
                 }
                 seg[e] = (uint16_t)DONE;
             } else {
@@ -578,24 +584,24 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
                 const uint32_t sn = vl.Fl + gq;
                 const uint32_t nidx = gc * ((1u << t) - 1u) + q;
                 const uint32_t ds = ndim[nidx];
-                const float plane = nplane[nidx];
-                float lo[K], hi[K];
+                const uint32_t plane = nplane[nidx];
+                uint32_t lo[K], hi[K];
                 local_box<K>(t, q, gc, rootbox, ndim, nplane, lo, hi);
 #pragma unroll
                 for (uint32_t c = 0; c < 2u; ++c) {
                     const uint32_t child = 2u * sn + 1u + c;
                     if (child >= ti.n) continue;
-                    float l2[K], h2[K];
+                    uint32_t l2[K], h2[K];
 #pragma unroll
                     for (int dd = 0; dd < K; ++dd) {
                         l2[dd] = lo[dd];
                         h2[dd] = hi[dd];
                         if ((uint32_t)dd == ds) {
-                            if (c == 0u) h2[dd] = fminf(hi[dd], plane);
-                            else l2[dd] = fmaxf(lo[dd], plane);
+                            if (c == 0u) h2[dd] = min(hi[dd], plane);
+                            else l2[dd] = max(lo[dd], plane);
                         }
                     }
-                    const uint32_t cd = widest_dim<K>(l2, h2);
+                    const uint32_t cd = widest_dim<K, I32>(l2, h2);
                     o.dimnode[off + child] = (uint8_t)cd;
                     if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
                 }
@@ -609,8 +615,15 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 template <int K>
 static void tail_k(const TailArgs& a, uint32_t groups, bool widest, hipStream_t st)
 {
-    if (widest) k_tail<K, true><<<groups, TAIL_THREADS, 0, st>>>(a);
-    else k_tail<K, false><<<groups, TAIL_THREADS, 0, st>>>(a);
+    // a coordinate is read as a key only by whole trees and split-widest
+    const bool i32 = a.o.i32 && (widest || a.from_points);
+    if (i32) {
+        if (widest) k_tail<K, true, true><<<groups, TAIL_THREADS, 0, st>>>(a);
+        else k_tail<K, false, true><<<groups, TAIL_THREADS, 0, st>>>(a);
+    } else {
+        if (widest) k_tail<K, true, false><<<groups, TAIL_THREADS, 0, st>>>(a);
+        else k_tail<K, false, false><<<groups, TAIL_THREADS, 0, st>>>(a);
+    }
 }
 
 void launch_tail(int k, const TailArgs& a, uint32_t groups, bool widest, hipStream_t st)

@@ -22,6 +22,8 @@ ENONFINITE = 4
 EBUSY = 5
 ENOTFOUND = 6
 
+STATUS_INTERNAL_BIT = 0x100   # device status: an internal check failed (include/kdt.h)
+
 ROUND_ROBIN = 0
 WIDEST = 1
 MAX_POINTS = (1 << 30) - 1
@@ -35,6 +37,14 @@ _SIGS = {
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "kdt_build": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                  ctypes.c_void_p]),
+    "kdt_build_ws_i32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "kdt_build_batched_i32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                             ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "kdt_permute_payload": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "kdt_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                                       ctypes.c_int]),
     "kdt_build_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
@@ -67,7 +77,8 @@ _SIGS = {
 
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
-                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("method_bytes", ctypes.c_double)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -137,24 +148,27 @@ def workspace_bytes(n: int, k: int, mode: int = ROUND_ROBIN) -> int:
 
 
 def _check_points(points):
+    """The points' entry-point suffix: "" for float32, "_i32" for int32."""
     import torch
-    if points.dtype != torch.float32 or points.dim() != 2 or not points.is_contiguous():
-        raise ValueError("points must be a contiguous (N, k) float32 tensor")
+    if points.dtype not in (torch.float32, torch.int32) or points.dim() != 2 or not points.is_contiguous():
+        raise ValueError("points must be a contiguous (N, k) float32 or int32 tensor")
     if not points.is_cuda:
         raise ValueError("points must live on the GPU")
+    return "_i32" if points.dtype == torch.int32 else ""
 
 
 def build_ws(points, mode: int = ROUND_ROBIN, *, tree=None, perm=None, dim=None, status=None,
              workspace=None, stream=None, want_tree=True, want_perm=True, want_dim=True):
-    """kdt_build_ws over torch tensors.  Missing outputs are allocated (unless
-    want_* is False); returns (tree, perm, dim, status) with status a 1-element
-    int32 device tensor holding KDT_OK or KDT_ENONFINITE."""
+    """kdt_build_ws (float32 points) or kdt_build_ws_i32 (int32 points) over
+    torch tensors.  Missing outputs are allocated (unless want_* is False);
+    returns (tree, perm, dim, status) with status a 1-element int32 device
+    tensor holding KDT_OK or KDT_ENONFINITE."""
     import torch
-    _check_points(points)
+    suffix = _check_points(points)
     n, k = points.shape
     dev = points.device
     if tree is None and want_tree:
-        tree = torch.empty((n, k), dtype=torch.float32, device=dev)
+        tree = torch.empty((n, k), dtype=points.dtype, device=dev)
     if perm is None and want_perm:
         perm = torch.empty(n, dtype=torch.int32, device=dev)
     if dim is None and want_dim:
@@ -164,16 +178,35 @@ def build_ws(points, mode: int = ROUND_ROBIN, *, tree=None, perm=None, dim=None,
     nbytes = workspace_bytes(n, k, mode)
     if workspace is None:
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    rc = lib().kdt_build_ws(_ptr(points), n, k, mode, _ptr(tree), _ptr(perm), _ptr(dim), _ptr(status),
-                            _ptr(workspace), workspace.numel() * workspace.element_size(), _stream(stream))
+    rc = getattr(lib(), "kdt_build_ws" + suffix)(_ptr(points), n, k, mode, _ptr(tree), _ptr(perm), _ptr(dim),
+                                                _ptr(status), _ptr(workspace),
+                                                workspace.numel() * workspace.element_size(), _stream(stream))
     if rc != OK:
-        raise KdtError(rc, "kdt_build_ws")
+        raise KdtError(rc, "kdt_build_ws" + suffix)
     return tree, perm, dim, status
+
+
+def permute_payload(perm, payload, out=None, status=None, stream=None):
+    """kdt_permute_payload: out[s] = payload[perm[s]] for a device tensor
+    whose first dimension indexes the points (any dtype, any trailing shape,
+    contiguous)."""
+    import torch
+    if not payload.is_contiguous() or not payload.is_cuda or payload.shape[0] != perm.shape[0]:
+        raise ValueError("payload must be a contiguous device tensor with one row per point")
+    n = payload.shape[0]
+    stride = payload.element_size() * (payload.numel() // max(n, 1))
+    if out is None:
+        out = torch.empty_like(payload)
+    rc = lib().kdt_permute_payload(_ptr(perm), n, _ptr(payload), stride, _ptr(out), _ptr(status), _stream(stream))
+    if rc != OK:
+        raise KdtError(rc, "kdt_permute_payload")
+    return out
 
 
 def build(points, mode: int = ROUND_ROBIN, stream=None):
     """kdt_build: replace `points` by its tree in level order (in place)."""
-    _check_points(points)
+    if _check_points(points):
+        raise ValueError("this entry point takes float32 points")
     n, k = points.shape
     rc = lib().kdt_build(_ptr(points), n, k, mode, _stream(stream))
     if rc != OK:
@@ -204,14 +237,14 @@ def build_batched(points, offsets, mode: int = ROUND_ROBIN, *, tree=None, perm=N
     Missing outputs are allocated (unless want_* is False); returns
     (tree, perm, dim, status), with perm local to each cloud."""
     import torch
-    _check_points(points)
+    suffix = _check_points(points)
     n, k = points.shape
     o = _offsets(offsets)
     if int(o[-1]) != n:
         raise ValueError(f"offsets end at {int(o[-1])} but points has {n} rows")
     dev = points.device
     if tree is None and want_tree:
-        tree = torch.empty((n, k), dtype=torch.float32, device=dev)
+        tree = torch.empty((n, k), dtype=points.dtype, device=dev)
     if perm is None and want_perm:
         perm = torch.empty(n, dtype=torch.int32, device=dev)
     if dim is None and want_dim:
@@ -221,11 +254,12 @@ def build_batched(points, offsets, mode: int = ROUND_ROBIN, *, tree=None, perm=N
     if workspace is None:
         nbytes = batched_workspace_bytes(o, k, mode)
         workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-    rc = lib().kdt_build_batched(_ptr(points), o.ctypes.data_as(ctypes.c_void_p), o.size - 1, k, mode, _ptr(tree),
-                                 _ptr(perm), _ptr(dim), _ptr(status), _ptr(workspace),
-                                 workspace.numel() * workspace.element_size(), _stream(stream))
+    rc = getattr(lib(), "kdt_build_batched" + suffix)(_ptr(points), o.ctypes.data_as(ctypes.c_void_p), o.size - 1,
+                                                     k, mode, _ptr(tree), _ptr(perm), _ptr(dim), _ptr(status),
+                                                     _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                                     _stream(stream))
     if rc != OK:
-        raise KdtError(rc, "kdt_build_batched")
+        raise KdtError(rc, "kdt_build_batched" + suffix)
     return tree, perm, dim, status
 
 
@@ -234,7 +268,8 @@ def tune_batched(points, offsets, mode: int = ROUND_ROBIN, reps: int = 3, worksp
     choice on this batch and record the fastest; returns (radix_bits,
     level_items, presort_dims, ms)."""
     import torch
-    _check_points(points)
+    if _check_points(points):
+        raise ValueError("this entry point takes float32 points")
     n, k = points.shape
     o = _offsets(offsets)
     if workspace is None:
@@ -292,13 +327,15 @@ def profile_enable(on: bool = True):
 
 
 def profile_collect():
-    """Per-kernel {launches, total_ms, alg_bytes} recorded since the last call."""
+    """Per-kernel {launches, total_ms, alg_bytes, method_bytes} recorded since
+    the last call."""
     arr = (KernelStat * 32)()
     m = lib().kdt_profile_collect(ctypes.cast(arr, ctypes.c_void_p), 32)
     if m < 0:
         raise RuntimeError(f"kdt_profile_collect failed: {last_error()}")
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms),
-                                   "alg_bytes": float(arr[i].alg_bytes)} for i in range(m)}
+                                   "alg_bytes": float(arr[i].alg_bytes),
+                                   "method_bytes": float(arr[i].method_bytes)} for i in range(m)}
 
 
 def clock() -> float:

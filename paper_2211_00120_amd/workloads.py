@@ -42,6 +42,27 @@ def signed_mix(n: int, k: int, seed: int) -> np.ndarray:
     return np.where(mask, picks, base).astype(np.float32)
 
 
+def int_uniform(n: int, k: int, seed: int) -> np.ndarray:
+    """n points i.i.d. uniform over all int32 values (Table 1's int1 rows:
+    the paper does not state their distribution), int32."""
+    return _rng(seed).integers(-(2 ** 31), 2 ** 31, size=(n, k), dtype=np.int64).astype(np.int32)
+
+
+def int_grid(n: int, k: int, seed: int, levels: int = 8) -> np.ndarray:
+    """int32 points from a small range around 0 (heavy ties, both signs)."""
+    return (_rng(seed).integers(0, levels, size=(n, k)) - levels // 2).astype(np.int32)
+
+
+def int_extremes(n: int, k: int, seed: int) -> np.ndarray:
+    """int32 values with the extremes, 0 and -1 mixed into uniform ones, so
+    that the key transform and exact extents see both ends of the range."""
+    r = _rng(seed)
+    base = r.integers(-(2 ** 31), 2 ** 31, size=(n, k), dtype=np.int64)
+    specials = np.array([-(2 ** 31), 2 ** 31 - 1, 0, -1, 1, -(2 ** 31) + 1, 2 ** 31 - 2], dtype=np.int64)
+    mask = r.random((n, k)) < 0.3
+    return np.where(mask, specials[r.integers(0, len(specials), size=(n, k))], base).astype(np.int32)
+
+
 def cfg_small(seed: int = 1) -> np.ndarray:
     """N=1024 3D points uniform in [0,1)^3 (single build, round robin)."""
     return uniform(1024, 3, seed)

@@ -94,8 +94,54 @@ static int check_n(uint32_t n, bool full)
     return 0;
 }
 
+// Arguments at and beyond the edges of the arithmetic: every function must
+// return a defined value (the sanitizer build of this file traps on an
+// undefined shift, a clz of 0 or a division by zero).
+static int check_edges()
+{
+    if (num_levels(0) != 0) return fail("num_levels(0)", 0, 0, 0, num_levels(0), 0);
+    if (level_of(0xFFFFFFFFu) != 32) return fail("level_of(2^32-1)", 0, 0, 0, level_of(0xFFFFFFFFu), 32);
+    if (level_of(0xFFFFFFFEu) != 31) return fail("level_of(2^32-2)", 0, 0, 0, level_of(0xFFFFFFFEu), 31);
+    if (full_nodes(32) != 0xFFFFFFFFu || full_nodes(40) != 0xFFFFFFFFu || full_nodes(31) != 0x7FFFFFFFu)
+        return fail("full_nodes", 0, 32, 0, full_nodes(32), 0xFFFFFFFFu);
+    if (rank_bits(0) != 0 || rank_bits(1) != 0 || rank_bits(2) != 1 || rank_bits(0xFFFFFFFFu) != 32)
+        return fail("rank_bits", 0, 0, 0, rank_bits(0xFFFFFFFFu), 32);
+    // n = 0: no levels, no subtrees
+    for (uint32_t l : {0u, 1u, 31u, 32u, 33u}) {
+        const Level v = make_level(0, l);
+        if (v.L != 0 || v.W != 0 || v.R != 0) return fail("make_level(0)", 0, l, 0, v.W, 0);
+        (void)seg_of_pos(v, 0);
+        (void)tiles_level(v, 64);
+    }
+    const uint32_t ns[] = {1u, 2u, 3u, 7u, 8u, 1000u, 0x3FFFFFFFu, 0x7FFFFFFFu, 0x80000000u, 0xFFFFFFFFu};
+    for (uint32_t n : ns) {
+        const uint32_t L = num_levels(n);
+        for (uint32_t l = (L >= 2 ? L - 2 : 0); l <= L + 2 && l < 40; ++l) {
+            const Level v = make_level(n, l);
+            if (l + 1 == L) {
+                // the last level: single-node subtrees, position p is subtree p
+                if (v.W != 1 || v.R != n - full_nodes(L - 1)) return fail("last level", n, l, 0, v.W, 1);
+                for (uint32_t p : {0u, v.R > 0 ? v.R - 1 : 0u})
+                    if (seg_of_pos(v, p) != p) return fail("seg_of_pos last level", n, l, p, seg_of_pos(v, p), p);
+                if (seg_size(v, 0) != 1) return fail("seg_size last level", n, l, 0, seg_size(v, 0), 1);
+            }
+            if (l >= L && v.W != 0) return fail("below the tree", n, l, 0, v.W, 0);
+            (void)seg_of_pos(v, 0);
+            (void)tiles_level(v, 4096);
+            (void)seg_offset(v, v.nseg ? v.nseg - 1 : 0);
+            (void)seg_left_size(v, 0);
+        }
+    }
+    // clamp_sub at the wrap edges
+    if (clamp_sub(5, 7, 3) != 0 || clamp_sub(7, 5, 3) != 2 || clamp_sub(0xFFFFFFFFu, 0, 9) != 9 ||
+        clamp_sub(0, 0xFFFFFFFFu, 9) != 0)
+        return fail("clamp_sub", 0, 0, 0, clamp_sub(5, 7, 3), 0);
+    return 0;
+}
+
 int main()
 {
+    if (check_edges()) return 1;
     for (uint32_t n = 1; n <= 3000; ++n)
         if (check_n(n, true)) return 1;
     const uint32_t big[] = {4095, 4096, 4097, 65535, 65536, 65537, 100003, 1000000, 1048575, 1048576, 3333333};

@@ -325,7 +325,8 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
         {p.o_ranks, N * k * 4, "ranks"}, {p.o_rec, std::max(p.rec_words * 2, (size_t)4 * G * N) * 4, "rec"}, {p.o_nodeperm, N * 4, "nodeperm"},
         {p.o_dimnode, N, "dimnode"}, {p.o_box[0], (size_t)p.box_entries * 32, "box0"},
         {p.o_box[1], (size_t)p.box_entries * 32, "box1"}, {p.o_bbox, p.large.size() * KEYSUM_WORDS * 4, "keysum"}, {p.o_piv, (size_t)p.piv_words * 4, "piv"},
-        {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}, {p.o_wcount, (size_t)k * RANK_MAX_WIN * 4, "wcount"}};
+        {p.o_tables, p.tables ? p.blob.size() : 0, "tables"}, {p.o_wcount, (size_t)k * RANK_MAX_WIN * 4, "wcount"},
+        {p.o_tstatus, p.trees.size() * 4, "tstatus"}};
     size_t end = 0;
     for (const R& r : regs) {
         CHECK(r.off % WS_ALIGN == 0 && r.off >= end, "region %s at %zu (previous end %zu)", r.name, r.off, end);

@@ -1,68 +1,78 @@
-"""A direct model of the paper's tag/sort loop, for tests only.
+"""An independent model of the paper's tag/sort construction, for tests only.
 
-This is a second, independent way of computing the tree, used to pin the
-oracle (they must agree) and to replay the printed states of the Sec. 5
-walkthrough.  It follows the algorithm as the paper states it, not the
-oracle's recursion:
+It computes the tree a second way, used to pin the oracle (they must agree)
+and to replay the printed states of the Sec. 5 walkthrough.  Where the oracle
+recurses over point lists, this model keeps one tag per point and repeats,
+for every level, a global sort followed by a tag update, as Sec. 3
+describes.  It is written from the definitions, not from the printed code:
 
-* every point carries a tag, initially 0 (Sec. 3);
-* for l = 0 .. L-2: sort all (tag, point) pairs by tag, then by the point's
-  coordinate in the split dimension (Sec. 3.1), then by original index (the
-  tie-break reading adopted for this build); then update every array entry
-  i >= F(l) from its tag s and the pivot position sb(s,l) + ss(2s+1) (Sec. 3.2);
-* a final sort by tag puts every point at its node (Sec. 5);
-* sb and ss are the O(1) closed forms of Sec. 4 with the published errata
-  (L = 32 - clz(N)), read as mathematics: the inner-node term is
-  2^(L-l-1) - 1, not the C-precedence reading 1 << (L-l-2);
-* split-widest (Sec. 6): each subtree's dimension is the widest float32 extent
-  of its domain, obtained by starting from the scene box, clipping by the new
-  parent's plane and then by every already-fixed ancestor's plane while
-  walking up to the root.
+* the level-order tree of Sec. 2: node s has children 2s+1 and 2s+2; the
+  subtree of s is the set of node indices below s that exist for N nodes, so
+  its size is found by counting that set (no closed form);
+* the sort of Sec. 3.1 orders the points by tag and, within one tag, by the
+  coordinate in that subtree's split dimension -- with the original index as
+  the tie-break this build adopts;
+* after the sort, the points of one level-l subtree s form a run; by
+  Observation 2.1 the run's member whose rank equals the left child's size
+  becomes node s, the members before it get tag 2s+1 and those after it tag
+  2s+2 (Sec. 3.2); tags of fixed nodes never change;
+* after the last level a sort by tag puts every point at its node (Sec. 5);
+* split-widest (Sec. 6): a subtree's domain is its parent's domain with the
+  parent's plane as the new upper (left child) or lower (right child) bound
+  in the parent's split dimension, starting from the scene box at the root;
+  its dimension is the one of widest float32 extent, lowest on ties.
 
-Pure Python, O(N log^2 N) with large constants: use for N up to a few
-thousand.
+The segment-begin position of Sec. 4.2 is provided as its definition (the
+fixed nodes, then every earlier subtree of the same level) for the pins of
+the closed forms.
+
+Pure Python: use for N up to a few thousand.
 """
 from __future__ import annotations
+
+from functools import lru_cache
 
 import numpy as np
 
 
 def num_levels(n: int) -> int:
-    """L = 32 - clz(N) (Sec. 4.2 after the revision-3 erratum); 0 for N = 0."""
-    return int(n).bit_length()
+    """Levels of a complete tree of n nodes: depth of node n-1 plus one (0 for
+    an empty tree)."""
+    return 0 if n == 0 else level(n - 1) + 1
 
 
 def level(s: int) -> int:
-    """level(s) = 31 - clz(s+1) (Sec. 2)."""
-    return (s + 1).bit_length() - 1
+    """Depth of node s: the number of times s can be replaced by its parent
+    (s-1)//2 before reaching the root."""
+    d = 0
+    while s > 0:
+        s = (s - 1) // 2
+        d += 1
+    return d
 
 
 def F(l: int) -> int:
-    """Number of nodes in the top l full levels, 2^l - 1 (Sec. 2)."""
-    return (1 << l) - 1
+    """Nodes on the levels above level l: 1 + 2 + ... + 2^(l-1)."""
+    return sum(2 ** j for j in range(l))
 
 
+@lru_cache(maxsize=None)
 def ss(s: int, n: int) -> int:
-    """Subtree size in O(1) (Sec. 4.1)."""
-    L = num_levels(n)
-    l = level(s)
-    sh = L - l - 1
-    fllc = ~((~s) << sh)                     # first lowest-level child
-    return ((1 << sh) - 1) + min(max(0, n - fllc), 1 << sh)
+    """Nodes in the subtree of s when the tree has n nodes, by counting: s
+    itself (if it exists) and the subtrees of its two children."""
+    return 0 if s >= n else 1 + ss(2 * s + 1, n) + ss(2 * s + 2, n)
 
 
 def sb(s: int, l: int, n: int) -> int:
-    """Segment begin of subtree s in iteration l (Sec. 4.2)."""
-    L = num_levels(n)
-    nls = s - F(l)
-    sh = L - l - 1
-    return F(l) + nls * ((1 << sh) - 1) + min(nls * (1 << sh), n - F(L - 1))
+    """Where the points of level-l subtree s begin after the level-l sort:
+    behind the F(l) fixed nodes and the points of the earlier subtrees of
+    level l."""
+    return F(l) + sum(ss(t, n) for t in range(F(l), s))
 
 
 @np.errstate(over="ignore")
 def _widest(lo, hi) -> int:
-    # float32 extents; an extent may overflow to +inf, which compares as
-    # larger than every finite extent
+    # float32 extents (an extent may overflow to +inf, larger than any finite one)
     ext = (np.asarray(hi, np.float32) - np.asarray(lo, np.float32)).astype(np.float32)
     best = 0
     for d in range(1, len(ext)):
@@ -72,75 +82,64 @@ def _widest(lo, hi) -> int:
 
 
 def paper_build(points, widest: bool = False, trace=None):
-    """Run the tag/sort loop.  Returns (perm, dim) like the oracle.
+    """Run the per-level sort + tag update.  Returns (perm, dim) like the
+    oracle.
 
     trace, if given, is called as trace(label, tags, order) after every sort
-    and every update (labels 'sort<l>', 'update<l>', 'final'); order[i] is the
-    original index of the point at array position i."""
+    and every update (labels 'sort<l>', 'update<l>', 'final'): order[i] is the
+    original index of the point at array position i, tags[i] its tag."""
     P = np.asarray(points, dtype=np.float32)
     n, k = P.shape
     if n == 0:
         return np.zeros(0, np.uint32), np.zeros(0, np.uint8)
-    L = num_levels(n)
-    tags = [0] * n
-    order = list(range(n))
-    dims = {}
+    tag = [0] * n                      # tag[i]: subtree or node of point i
+    split = {}                         # subtree -> split dimension
+    box = {}                           # subtree -> (lo, hi), split-widest only
     if widest:
-        dims[0] = _widest(P.min(axis=0), P.max(axis=0))
+        box[0] = (P.min(axis=0).copy(), P.max(axis=0).copy())
+        split[0] = _widest(*box[0])
 
-    def dim_of(tag, l):
-        return dims[tag] if widest else l % k
+    def dim_of(t: int) -> int:
+        return split[t] if widest else level(t) % k
 
-    for l in range(L - 1):
-        pairs = sorted(zip(tags, order),
-                       key=lambda ti: (ti[0], P[ti[1], dim_of(ti[0], l)], ti[1]))
-        tags = [t for t, _ in pairs]
-        order = [i for _, i in pairs]
+    order = list(range(n))
+    for l in range(num_levels(n) - 1):
+        # Sec. 3.1: by tag, then coordinate in the tag's split dimension, then index
+        order = sorted(range(n), key=lambda i: (tag[i], float(P[i, dim_of(tag[i])]), i))
         if trace:
-            trace(f"sort{l}", list(tags), list(order))
-        new = list(tags)
-        for i in range(F(l), n):
-            s = tags[i]
-            piv = sb(s, l, n) + ss(2 * s + 1, n)
-            if i == piv:
-                continue
-            child = 2 * s + 1 if i < piv else 2 * s + 2
-            new[i] = child
+            trace(f"sort{l}", [tag[i] for i in order], list(order))
+        # Sec. 3.2 with Observation 2.1: walk the runs of the level-l subtrees
+        runs = {}
+        for i in order:
+            if tag[i] >= F(l):
+                runs.setdefault(tag[i], []).append(i)
+        for s, members in runs.items():
+            m = ss(2 * s + 1, n)       # rank of the pivot in its run
+            for rank, i in enumerate(members):
+                if rank != m:
+                    tag[i] = 2 * s + 1 if rank < m else 2 * s + 2
             if widest:
-                # domain of the new subtree: scene box clipped by s's plane
-                # (its pivot sits at array position piv), then by every fixed
-                # ancestor of s (ancestor a sits at array position a).
-                lo = P.min(axis=0).copy()
-                hi = P.max(axis=0).copy()
-                ds = dims[s]
-                plane = P[order[piv], ds]
-                if child == 2 * s + 1:
-                    hi[ds] = min(hi[ds], plane)
-                else:
-                    lo[ds] = max(lo[ds], plane)
-                c = s
-                while c > 0:
-                    a = (c - 1) // 2
-                    da = dims[a]
-                    plane = P[order[a], da]
-                    if c == 2 * a + 1:
-                        hi[da] = min(hi[da], plane)
+                d = split[s]
+                plane = P[members[m], d]
+                lo, hi = box[s]
+                for child, is_left in ((2 * s + 1, True), (2 * s + 2, False)):
+                    clo, chi = lo.copy(), hi.copy()
+                    if is_left:
+                        chi[d] = min(chi[d], plane)
                     else:
-                        lo[da] = max(lo[da], plane)
-                    c = a
-                dims[child] = _widest(lo, hi)
-        tags = new
+                        clo[d] = max(clo[d], plane)
+                    box[child] = (clo, chi)
+                    split[child] = _widest(clo, chi)
         if trace:
-            trace(f"update{l}", list(tags), list(order))
-    pairs = sorted(zip(tags, order))
-    tags = [t for t, _ in pairs]
-    order = [i for _, i in pairs]
+            trace(f"update{l}", [tag[i] for i in order], list(order))
+    # Sec. 5: every tag is now a node index; a sort by tag places the points
+    order = sorted(range(n), key=lambda i: tag[i])
     if trace:
-        trace("final", list(tags), list(order))
-    assert tags == list(range(n))
+        trace("final", [tag[i] for i in order], list(order))
+    assert [tag[i] for i in order] == list(range(n))
     perm = np.asarray(order, dtype=np.uint32)
     if widest:
-        dim = np.asarray([dims[s] for s in range(n)], dtype=np.uint8)
+        dim = np.asarray([split[s] for s in range(n)], dtype=np.uint8)
     else:
         dim = np.asarray([level(s) % k for s in range(n)], dtype=np.uint8)
     return perm, dim

@@ -290,7 +290,7 @@ def test_tuner_choices_give_identical_trees():
         ref = _run_batched(pts, offsets, kdt.ROUND_ROBIN)
         bits = int(np.ceil(np.log2(max(sizes))))
         for rb in (8, 9, 10):
-            for items in (4, 8):
+            for items in (4, 10):
                 for pdims in (1, 2, 4):
                     _say(f"case tuner: radix {rb} items {items} presort dims {pdims}")
                     kdt.tuning_set(3, kdt.ROUND_ROBIN, bits, rb, items, 0, pdims)

@@ -175,13 +175,15 @@ def test_tuning_table_round_trip(tmp_path):
     try:
         assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (0, 0, 0, 0)
         kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 10, 4)
-        kdt.tuning_set(4, kdt.WIDEST, 27, 8, 8, 2, 1)
+        kdt.tuning_set(4, kdt.WIDEST, 27, 8, 10, 2, 1)
         kdt.tuning_set(2, kdt.WIDEST, 20, 0, 0, 1, 4)
         assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0, 0)
         with pytest.raises(kdt.KdtError):
             kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 11, 4)
         with pytest.raises(kdt.KdtError):
             kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 5)
+        with pytest.raises(kdt.KdtError):
+            kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 8)         # only 4 or 10 records per thread
         with pytest.raises(kdt.KdtError):
             kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 4, 3)
         with pytest.raises(kdt.KdtError):
@@ -191,7 +193,7 @@ def test_tuning_table_round_trip(tmp_path):
         kdt.tuning_clear()
         assert kdt.tuning_get(4, kdt.WIDEST, 27) == (0, 0, 0, 0)
         kdt.tuning_load(path)
-        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (8, 8, 2, 1)
+        assert kdt.tuning_get(4, kdt.WIDEST, 27) == (8, 10, 2, 1)
         assert kdt.tuning_get(2, kdt.WIDEST, 20) == (0, 0, 1, 4)
         assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0, 0)
         for text in ("3 0 24 12 4 0 0\n", "3 0 24 8 4 3 0\n", "3 0 24 8 4 0 5\n", "3 0 24 8 4 0\n"):
@@ -202,7 +204,35 @@ def test_tuning_table_round_trip(tmp_path):
             assert kdt.tuning_get(3, kdt.ROUND_ROBIN, 24) == (10, 4, 0, 0)     # unchanged by the failed load
         # sizes hold every choice: setting a tuning never grows them
         before = kdt.workspace_bytes(10_000_000, 3, kdt.ROUND_ROBIN)
-        kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 8)
+        kdt.tuning_set(3, kdt.ROUND_ROBIN, 24, 8, 10)
         assert kdt.workspace_bytes(10_000_000, 3, kdt.ROUND_ROBIN) == before
     finally:
         kdt.tuning_clear()
+
+
+SANITIZE = ["-O1", "-g", "-fsanitize=undefined,address", "-fno-sanitize-recover=all"]
+
+
+@pytest.mark.parametrize("prog", ["layout_check", "plan_check", "admit_check", "oracle_check"])
+def test_host_code_under_sanitizers(prog, tmp_path):
+    """The host-side arithmetic the kernels share (kdt_layout.h, including
+    its edges: n = 0, levels at and below the last one, s = 2^32 - 1), the
+    planner, the server's pool and admission, and the CPU oracle, built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (any report aborts the
+    program)."""
+    inc = os.path.join(ROOT, "paper_2211_00120_amd", "csrc")
+    exe = str(tmp_path / prog)
+    if prog == "oracle_check":
+        cmd = ["gcc", "-std=c11", "-fopenmp", *SANITIZE, os.path.join(ROOT, "tests", "host", "oracle_check.c"),
+               os.path.join(ROOT, "oracle", "kdt_oracle.c"), "-o", exe]
+    else:
+        srcs = [os.path.join(ROOT, "tests", "host", prog + ".cpp")]
+        if prog != "layout_check":
+            srcs.append(os.path.join(inc, "kdt_plan.cpp"))
+        cmd = ["g++", "-std=c++17", *SANITIZE, "-I", inc, *srcs, "-o", exe]
+    subprocess.run(cmd, check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=1", UBSAN_OPTIONS="print_stacktrace=1")
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=900, env=env)
+    assert out.returncode == 0, out.stdout[-2000:] + out.stderr[-4000:]
+    assert out.stdout.strip().endswith("ok")
+    assert "runtime error" not in out.stderr

@@ -176,15 +176,24 @@ def test_subtree_size_and_closed_forms(n):
 
 
 def test_literal_c_precedence_reading_is_rejected():
-    # `1<<(L-l-1) - 1` parses in C as 1 << (L-l-2); with that reading the
-    # root's left subtree of the walkthrough would have 5 nodes, but the
-    # printed step-0 update puts 6 points into subtree 1.
+    # Sec. 4.1 counts a subtree as its inner nodes plus its nodes on the
+    # lowest level.  Read with C operator precedence, the printed inner-node
+    # term is 2^(L-l-2) instead of 2^(L-l-1) - 1.  For the walkthrough (N =
+    # 10, L = 4) node 1 (level 1) has 2^2 - 1 = 3 inner nodes and 3 of the 3
+    # lowest-level nodes, 6 in all -- the C reading would give 2 + 3 = 5, but
+    # the printed step-0 update puts 6 points into subtree 1.
     n, s = 10, 1
     L, l = num_levels(n), level(s)
-    sh = L - l - 1
-    fllc = ~((~s) << sh)
-    c_reading = (1 << (sh - 1)) + min(max(0, n - fllc), 1 << sh)
-    assert c_reading == 5 and ss(1, n) == 6
+    lowest = [x for x in range(F(L - 1), n) if _is_below(x, s)]
+    assert len(lowest) == 3
+    assert (2 ** (L - l - 1) - 1) + len(lowest) == ss(1, n) == 6
+    assert 2 ** (L - l - 2) + len(lowest) == 5
+
+
+def _is_below(x, s):
+    while x > s:
+        x = (x - 1) // 2
+    return x == s
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3])
@@ -334,3 +343,139 @@ def test_checker_rejects_planted_errors(widest):
     d2[300] = (d2[300] + 1) % 3
     assert oracle.check(P, perm, d2, mode)[0] in (2, 3)
     assert not brute_ok(P, perm, d2, widest)
+
+
+# ---------------------------------------------------------------- int32 points
+# Table 1's int1 rows build over 32-bit integers (Sec. 7.2 templates the
+# builder over the point type).  Integers compare exactly; the split-widest
+# extent of an integer domain is the exact difference hi - lo.
+
+I32_MIN, I32_MAX = -(2 ** 31), 2 ** 31 - 1
+
+
+def _i32_points(n, k, seed, levels=None):
+    r = np.random.default_rng(seed)
+    if levels:
+        P = r.integers(-levels // 2, levels - levels // 2, size=(n, k))
+    else:
+        P = r.integers(I32_MIN, I32_MAX, size=(n, k), endpoint=True)
+        # now and then the extremes and values near 0
+        m = r.random((n, k)) < 0.2
+        P[m] = r.choice([I32_MIN, I32_MAX, 0, -1, 1], size=int(m.sum()))
+    return P.astype(np.int32)
+
+
+def brute_ok_i32(P, perm, dim, widest):
+    """brute_ok for int32 points: every (ancestor, descendant) pair under the
+    (value, index) order, and every node's dim from its domain with exact
+    (int64) extents."""
+    P = np.asarray(P, np.int64)
+    n, k = P.shape
+    perm = np.asarray(perm, np.int64)
+    if sorted(perm.tolist()) != list(range(n)):
+        return False
+    if n == 0:
+        return True
+    lo = np.empty((n, k), np.int64)
+    hi = np.empty((n, k), np.int64)
+    lo[0], hi[0] = P.min(axis=0), P.max(axis=0)
+    for a in range(n):
+        d = int(dim[a])
+        ext = hi[a] - lo[a]
+        want = int(np.flatnonzero(ext == ext.max())[0]) if widest else level(a) % k
+        if d != want:
+            return False
+        pv, pi = P[perm[a], d], perm[a]
+        for child, is_left in ((2 * a + 1, True), (2 * a + 2, False)):
+            if child < n:
+                lo[child], hi[child] = lo[a], hi[a]
+                if is_left:
+                    hi[child, d] = pv
+                else:
+                    lo[child, d] = pv
+            first, last = child, child + 1
+            while first < n:
+                idx = perm[first:min(last, n)]
+                v = P[idx, d]
+                good = ((v < pv) | ((v == pv) & (idx < pi))) if is_left else ((v > pv) | ((v == pv) & (idx > pi)))
+                if not good.all():
+                    return False
+                first, last = 2 * first + 1, 2 * last + 1
+    return True
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 100, 1023, 1024, 3000])
+def test_i32_k1_is_breadth_first_layout_of_sorted_list(n):
+    P = _i32_points(n, 1, seed=n, levels=max(2, n // 7) if n % 2 else None)
+    perm, dim = oracle.build(P, oracle.RR)
+    srt = sorted(range(n), key=lambda i: (int(P[i, 0]), i))   # stable sort by (x, index)
+    want = np.empty(n, np.int64)
+    for rank, node in enumerate(_inorder(n)):
+        want[node] = srt[rank]
+    assert perm.tolist() == want.tolist()
+    assert not dim.any()
+
+
+@pytest.mark.parametrize("mode", [oracle.RR, oracle.WIDEST])
+@pytest.mark.parametrize("value", [I32_MIN, -1, 0, 7, I32_MAX])
+def test_i32_identical_points(mode, value):
+    n, k = 300, 3
+    P = np.full((n, k), value, np.int32)
+    perm, dim = oracle.build(P, mode)
+    assert [int(perm[s]) for s in _inorder(n)] == list(range(n))
+    if mode == oracle.WIDEST:
+        assert not dim.any()
+    else:
+        assert dim.tolist() == [level(s) % k for s in range(n)]
+
+
+@pytest.mark.parametrize("mode", [oracle.RR, oracle.WIDEST])
+@pytest.mark.parametrize("seed", range(4))
+def test_i32_equals_float_on_exactly_representable_values(mode, seed):
+    """Integers of magnitude below 2^23 are exact float32 values whose
+    differences are exact too: the int32 and float32 builds coincide."""
+    r = np.random.default_rng(seed)
+    P = r.integers(-(2 ** 23), 2 ** 23, size=(2000 + seed, 1 + seed % 4)).astype(np.int32)
+    if seed % 2:
+        P //= 1 << 18                                   # ties
+    pi, di = oracle.build(P, mode)
+    pf, df = oracle.build(P.astype(np.float32), mode)
+    assert np.array_equal(pi, pf) and np.array_equal(di, df)
+
+
+@pytest.mark.parametrize("widest", [False, True])
+@pytest.mark.parametrize("n,k,seed", [(37, 2, 1), (300, 3, 2), (1000, 4, 3), (2047, 3, 4)])
+def test_i32_bruteforce_invariants(n, k, seed, widest):
+    P = _i32_points(n, k, seed, levels=9 if seed % 2 else None)
+    mode = oracle.WIDEST if widest else oracle.RR
+    perm, dim = oracle.build(P, mode)
+    assert brute_ok_i32(P, perm, dim, widest)
+    assert oracle.check(P, perm, dim, mode) == (0, 0)
+
+
+def test_i32_widest_extent_is_exact():
+    """Extents that float32 rounding or int32 overflow would get wrong.
+    Root domain: x spans 2^24, y spans 2^24 + 1 (both 2^24 in float32, a tie
+    the lowest dimension would win): the exact extent picks y.  Second set:
+    x spans the whole int32 range (an int32 subtraction would wrap to -1),
+    y a small range: x."""
+    P = np.array([[0, 0], [2 ** 24, 2 ** 24 + 1], [5, 6]], np.int32)
+    _, dim = oracle.build(P, oracle.WIDEST)
+    assert dim[0] == 1
+    _, dimf = oracle.build(P.astype(np.float32), oracle.WIDEST)
+    assert dimf[0] == 0                                   # float32 reading: a tie
+    P = np.array([[I32_MIN, 0], [I32_MAX, 10], [3, 4]], np.int32)
+    _, dim = oracle.build(P, oracle.WIDEST)
+    assert dim[0] == 0
+
+
+def test_i32_checker_rejects_planted_errors():
+    P = _i32_points(500, 3, 77)
+    for mode in (oracle.RR, oracle.WIDEST):
+        perm, dim = oracle.build(P, mode)
+        bad = perm.copy()
+        bad[[3, 9]] = bad[[9, 3]]
+        assert oracle.check(P, bad, dim, mode)[0] == 2
+        d2 = dim.copy()
+        d2[10] = (d2[10] + 1) % 3
+        assert oracle.check(P, perm, d2, mode)[0] in (2, 3)

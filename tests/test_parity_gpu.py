@@ -211,14 +211,16 @@ def test_optional_outputs():
 
 
 def _check_full(pts, mode, label):
+    """Full-size parity: the oracle's checker on every node (k-d order against
+    every ancestor, split rule, permutation), which by the uniqueness of the
+    tree is equality with the oracle's tree, and the tree's coordinates
+    compared byte for byte with the points in perm order."""
     _say(f"case {label}: n={pts.shape[0]} k={pts.shape[1]} mode={mode} (checker)")
     tree, perm, dim, status = _gpu_build(pts, mode)
     assert status == kdt.OK, f"device status {status:#x}"
     code, node = oracle.check(pts, perm, dim, _omode(mode))
     assert code == 0, f"{label}: checker code {code} at node {node}"
-    # the tree's coordinates are the points in perm order
-    samp = np.random.default_rng(0).integers(0, pts.shape[0], 100000)
-    assert np.array_equal(tree[samp], pts[perm[samp]])
+    assert tree.tobytes() == np.ascontiguousarray(pts[perm]).tobytes(), f"{label}: tree bytes differ"
 
 
 def test_config_mixture_10m():
@@ -228,3 +230,13 @@ def test_config_mixture_10m():
 @pytest.mark.skipif(os.environ.get("KDT_SKIP_100M") == "1", reason="100M case disabled by KDT_SKIP_100M")
 def test_config_cluster_100m_widest():
     _check_full(workloads.cfg_cluster4d(), kdt.WIDEST, "cfg-100M-widest")
+
+
+@pytest.mark.parametrize("n", [1_000_000, 10_000_000,
+                               pytest.param(100_000_000, marks=pytest.mark.skipif(
+                                   os.environ.get("KDT_SKIP_100M") == "1",
+                                   reason="100M case disabled by KDT_SKIP_100M"))])
+def test_uniform4d_round_robin_table1(n):
+    """The workload of the paper's Table 1 (uniform points in [0,1)^4, round
+    robin) at 1e6, 1e7 and 1e8 points."""
+    _check_full(workloads.uniform(n, 4, seed=7), kdt.ROUND_ROBIN, f"uniform4d-{n}")

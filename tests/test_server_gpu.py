@@ -133,3 +133,38 @@ def test_server_status_empty_and_reject():
             srv.release(t)
         with pytest.raises(kdt.KdtError):
             srv.release(t_ok)
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_server_nonfinite_request_does_not_fail_its_batch(mode):
+    """A request with a NaN coordinate batched with finite requests of the same
+    k and split rule: it alone reports KDT_ENONFINITE; the others report
+    KDT_OK and equal their builds alone.  One batch slot, held by a large
+    first request, makes the later requests queue and start as one batch."""
+    _say(f"case server-nonfinite-in-batch mode={mode}")
+    blocker = workloads.uniform(3_000_000, 4, 21)
+    bad = workloads.uniform(6000, 3, 22)
+    bad[4321, 2] = np.nan
+    goods = [workloads.uniform(n, 3, 23 + i) for i, n in enumerate((5000, 70000, 2100))]
+    with kdt.Server(2 << 30, max_inflight=1, max_batch_requests=8) as srv:
+        t_block = srv.submit(blocker, kdt.ROUND_ROBIN)
+        t_bad = srv.submit(bad, mode)
+        t_goods = [srv.submit(g, mode) for g in goods]
+        assert srv.wait(t_block).status == kdt.OK
+        rb = srv.wait(t_bad)
+        assert rb.status == kdt.ENONFINITE
+        shared = 0
+        for t, g in zip(t_goods, goods):
+            r = srv.wait(t)
+            assert r.status == kdt.OK, f"finite request reported {r.status}"
+            shared += r.t_admit == rb.t_admit
+            tree, perm, dim = srv.fetch(t)
+            torch.cuda.synchronize()
+            ta, pa, da, sa = _alone(g, mode)
+            assert sa == kdt.OK
+            assert np.array_equal(perm.cpu().numpy(), pa) and np.array_equal(dim.cpu().numpy(), da)
+            assert tree.cpu().numpy().tobytes() == ta.tobytes()
+        # the finite requests ran in the non-finite request's batch
+        assert shared == len(goods) and rb.batch_requests == 1 + len(goods)
+        for t in [t_block, t_bad, *t_goods]:
+            srv.release(t)
