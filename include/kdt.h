@@ -171,6 +171,30 @@ kdt_status kdt_build_batched(const float* d_points, const uint32_t* h_offsets, u
                              uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
                              hipStream_t stream);
 
+/*
+ * kdt_build_ws for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The workspace is a fixed device array of KDT_STATIC_WS_BYTES bytes that
+ * the library holds on every device it runs on until the process ends (its
+ * address is looked up once per device, on the first call with that device
+ * current).  Arguments, outputs and status word as for kdt_build_ws; the
+ * caller still provides the points and every output buffer.
+ *
+ *   - Builds whose kdt_workspace_bytes(n, k, dim_mode) exceeds
+ *     KDT_STATIC_WS_BYTES are rejected with KDT_EINVAL before anything is
+ *     enqueued (about 0.5M points at k = 4, 0.67M at k = 3, 1.4M at k = 1).
+ *   - Allocates no device or pinned memory and never synchronises.
+ *   - Every call on one device shares that device's array, and each call
+ *     starts by clearing what it needs cleared: calls ordered on one stream
+ *     are fine, but calls that overlap in time on one device (other streams,
+ *     other threads) race and corrupt each other's trees.
+ */
+#define KDT_STATIC_WS_BYTES (64u << 20)
+
+kdt_status kdt_build_static(const float* d_points, uint32_t n, uint32_t k, int dim_mode,
+                            float* d_tree, uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status,
+                            hipStream_t stream);
+
 /* kdt_build_batched for int32 coordinates (see kdt_build_ws_i32). */
 kdt_status kdt_build_batched_i32(const int32_t* d_points, const uint32_t* h_offsets, uint32_t C,
                                  uint32_t k, int dim_mode, int32_t* d_tree, uint32_t* d_perm,

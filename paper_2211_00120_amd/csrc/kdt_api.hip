@@ -46,6 +46,12 @@
 
 static_assert(kdt::KDT_STATUS_INTERNAL == KDT_STATUS_INTERNAL_BIT, "status bit of include/kdt.h");
 
+// The workspace of kdt_build_static: a fixed array on every device the
+// library runs on.  In host code this name is only a handle for the
+// symbol lookup below; host code never passes it to a kernel or a copy, only
+// the per-device address hipGetSymbolAddress returns.
+static __device__ __align__(256) uint8_t scratch[KDT_STATIC_WS_BYTES];
+static_assert(kdt::KDT_STATUS_NONFINITE == (uint32_t)KDT_ENONFINITE, "status code of include/kdt.h");
 
 namespace {
 
@@ -625,6 +631,36 @@ kdt_status write_ok_status(uint32_t* d_status, hipStream_t stream)
     return check_launch("status");
 }
 
+// Device address of `scratch` on the current device, looked up on the first
+// call with that device current and kept (each device holds its own copy of
+// the array at its own address).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+kdt_status scratch_address(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_err("device %d out of range for the static workspace", dev);
+        return KDT_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_err("hipGetSymbolAddress of the static workspace failed: %s", hipGetErrorString(e));
+            return KDT_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KDT_OK;
+}
+
 }  // namespace
 
 namespace kdt {
@@ -699,6 +735,30 @@ kdt_status kdt_permute_payload(const uint32_t* d_perm, uint32_t n, const void* d
     }
     kdt::launch_permute(d_perm, n, d_in, d_out, stride_bytes, d_status, stream);
     return check_launch("k_permute");
+}
+
+kdt_status kdt_build_static(const float* d_points, uint32_t n, uint32_t k, int dim_mode, float* d_tree,
+                            uint32_t* d_perm, uint8_t* d_dim, uint32_t* d_status, hipStream_t stream)
+{
+    if (kdt_status s = validate_k_mode(k, dim_mode)) return s;
+    if (n > KDT_MAX_POINTS) {
+        set_err("n = %u exceeds KDT_MAX_POINTS", n);
+        return KDT_EINVAL;
+    }
+    const Plan p = make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
+    const size_t need = workspace_bytes_any(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
+    if (need > KDT_STATIC_WS_BYTES) {
+        set_err("kdt_build_static: n = %u, k = %u needs %zu bytes of workspace, more than the %u-byte static "
+                "workspace holds",
+                n, k, need, KDT_STATIC_WS_BYTES);
+        return KDT_EINVAL;
+    }
+    void* ws = nullptr;
+    if (kdt_status s = scratch_address(&ws)) return s;
+    if (kdt_status s = validate_buffers(p, d_points, d_tree, d_perm, d_dim, d_status, ws, KDT_STATIC_WS_BYTES))
+        return s;
+    if (n == 0) return write_ok_status(d_status, stream);
+    return enqueue(p, d_points, d_tree, d_perm, d_dim, d_status, (char*)ws, nullptr, stream);
 }
 
 kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipStream_t stream)

@@ -26,6 +26,7 @@ STATUS_INTERNAL_BIT = 0x100   # device status: an internal check failed (include
 
 ROUND_ROBIN = 0
 WIDEST = 1
+STATIC_WS_BYTES = 64 << 20    # workspace of kdt_build_static (include/kdt.h)
 MAX_POINTS = (1 << 30) - 1
 
 _lib = None
@@ -45,6 +46,9 @@ _SIGS = {
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "kdt_permute_payload": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "kdt_build_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "kdt_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                                       ctypes.c_int]),
     "kdt_build_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
@@ -201,6 +205,31 @@ def permute_payload(perm, payload, out=None, status=None, stream=None):
     if rc != OK:
         raise KdtError(rc, "kdt_permute_payload")
     return out
+
+
+def build_static(points, mode: int = ROUND_ROBIN, *, tree=None, perm=None, dim=None, status=None, stream=None):
+    """kdt_build_static over torch tensors: kdt_build_ws with the library's
+    fixed per-device workspace (no device allocation by the library).
+    Outputs not given are allocated here by torch; pass them all in to keep
+    the call allocation-free.  Returns (tree, perm, dim, status)."""
+    import torch
+    if _check_points(points):
+        raise ValueError("this entry point takes float32 points")
+    n, k = points.shape
+    dev = points.device
+    if tree is None:
+        tree = torch.empty((n, k), dtype=torch.float32, device=dev)
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    if dim is None:
+        dim = torch.empty(n, dtype=torch.uint8, device=dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    rc = lib().kdt_build_static(_ptr(points), n, k, mode, _ptr(tree), _ptr(perm), _ptr(dim), _ptr(status),
+                                _stream(stream))
+    if rc != OK:
+        raise KdtError(rc, "kdt_build_static")
+    return tree, perm, dim, status
 
 
 def build(points, mode: int = ROUND_ROBIN, stream=None):
