@@ -32,6 +32,9 @@ Workloads (--workload):
   small1024    N=1024 3D uniform, round robin
   uniform      --n points, --k dims, uniform [0,1)^k, round robin (the
                paper's Table 1 workload with k=4)
+  int1         --n int32 points (default 1e8) with k = 1, uniform over all
+               int32 values, round robin (Table 1's int1 rows; the paper does
+               not state their distribution)
   batched4096  4096 independent 3D clouds, sizes log-uniform in [64, 262144],
                each uniform in its own random box, round robin: one step is
                one kdt_build_batched of all clouds, captured once into a HIP
@@ -106,6 +109,11 @@ def make_workload(name: str, n: int, k: int):
         pts = workloads.uniform(n or 10_000_000, k, seed=7)
         return pts, kdt.ROUND_ROBIN, {"workload": f"uniform{k}d", "n": int(pts.shape[0]), "k": k,
                                       "dim_mode": "round_robin", "distribution": f"uniform [0,1)^{k}", "seed": 7}
+    if name == "int1":
+        pts = workloads.int_uniform(n or 100_000_000, 1, seed=11)
+        return pts, kdt.ROUND_ROBIN, {"workload": "int1", "n": int(pts.shape[0]), "k": 1,
+                                      "dim_mode": "round_robin", "coords": "int32",
+                                      "distribution": "uniform over all int32 values", "seed": 11}
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -632,12 +640,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d_pts = torch.from_numpy(pts).to(dev)
-    tree = torch.empty((n, k), dtype=torch.float32, device=dev)
+    tree = torch.empty((n, k), dtype=d_pts.dtype, device=dev)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     dim = torch.empty(n, dtype=torch.uint8, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     ws = torch.empty(kdt.workspace_bytes(n, k, mode), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    i32 = pts.dtype == np.int32
 
     calibration_copy(args, dev)
 
@@ -709,7 +718,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 in, u32 ranks",
+        "dtype": "i32 in, u32 ranks" if i32 else "f32 in, u32 ranks",
         "data": "synthetic",
         "config": cfg,
         "roofline": roofline,

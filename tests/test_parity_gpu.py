@@ -240,3 +240,20 @@ def test_uniform4d_round_robin_table1(n):
     """The workload of the paper's Table 1 (uniform points in [0,1)^4, round
     robin) at 1e6, 1e7 and 1e8 points."""
     _check_full(workloads.uniform(n, 4, seed=7), kdt.ROUND_ROBIN, f"uniform4d-{n}")
+
+
+_RUN_1E9 = os.environ.get("KDT_RUN_1E9") == "1"
+
+
+@pytest.mark.skipif(not _RUN_1E9, reason="1e9-point builds take minutes of host time: set KDT_RUN_1E9=1")
+@pytest.mark.parametrize("kind", ["float4", "int1"])
+def test_one_billion_points(kind):
+    """Table 1's last column: 10^9 points, round robin (uniform [0,1)^4
+    float32, and int32 with k = 1).  Checked by the oracle's checker on every
+    node and the tree's bytes against the points in perm order."""
+    n = 1_000_000_000
+    if kind == "float4":
+        pts = workloads.uniform(n, 4, seed=7)
+    else:
+        pts = workloads.int_uniform(n, 1, seed=11)
+    _check_full(pts, kdt.ROUND_ROBIN, f"1e9-{kind}")
