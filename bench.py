@@ -586,6 +586,10 @@ def main():
     ap.add_argument("--workload", default="cluster100m")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--variant", choices=["ws", "inplace"], default="ws",
+                    help="ws: kdt_build_ws (default); inplace: the low-memory in-place build kdt_build_inplace "
+                         "(one int per point; each step first restores the input with a device copy, which "
+                         "HIP events leave out of the timed build)")
     ap.add_argument("--no-check", action="store_true", help="skip the full-tree bit-exactness check")
     ap.add_argument("--no-per-cloud", action="store_true",
                     help="batched: skip the comparison with one single build per cloud (for counter runs)")
@@ -640,20 +644,38 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d_pts = torch.from_numpy(pts).to(dev)
+    inplace = args.variant == "inplace"
     tree = torch.empty((n, k), dtype=d_pts.dtype, device=dev)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     dim = torch.empty(n, dtype=torch.uint8, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
-    ws = torch.empty(kdt.workspace_bytes(n, k, mode), dtype=torch.uint8, device=dev)
+    if inplace:
+        ws = torch.empty(max(kdt.inplace_workspace_bytes(n, k, mode), 1), dtype=torch.uint8, device=dev)
+        cfg["variant"] = "inplace (kdt_build_inplace: one int per point, swap-only)"
+        cfg["workspace_bytes"] = int(ws.numel())
+    else:
+        ws = torch.empty(kdt.workspace_bytes(n, k, mode), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     i32 = pts.dtype == np.int32
 
     calibration_copy(args, dev)
 
-    def step():
-        kdt.build_ws(d_pts, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws, stream=stream)
+    if inplace:
+        ev = []
 
-    if args.autotune:
+        def step():
+            tree.copy_(d_pts)                       # restore the input; not part of the timed build
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            kdt.build_inplace(tree, mode, perm=perm, dim=dim, status=status, workspace=ws, stream=stream)
+            b.record(stream)
+            ev.append((a, b))
+    else:
+        def step():
+            kdt.build_ws(d_pts, mode, tree=tree, perm=perm, dim=dim, status=status, workspace=ws, stream=stream)
+
+    if args.autotune and not inplace:
         import numpy as np
         rb, items, pdims, tms = kdt.tune_batched(d_pts, np.array([0, n], np.uint32), mode, reps=3, workspace=ws)
         cfg["tuned"] = {"radix_bits": rb, "level_items": items, "presort_dims": pdims}
@@ -665,11 +687,16 @@ def main():
     print(f"# warmup done: n={n} k={k} mode={mode}", file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
+    if inplace:
+        ev.clear()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if inplace:
+        # the builds alone, by the events around each (the restore copies between them excluded)
+        elapsed = sum(a.elapsed_time(b) for a, b in ev) / 1e3
     st = int(status.item())
     print(f"# timed {args.steps} steps in {elapsed:.3f} s, status {st}", file=sys.stderr, flush=True)
     ms_per_step = elapsed * 1e3 / args.steps

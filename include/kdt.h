@@ -129,6 +129,39 @@ kdt_status kdt_permute_payload(const uint32_t* d_perm, uint32_t n, const void* d
                                void* d_out, uint32_t* d_status, hipStream_t stream);
 
 /*
+ * Low-memory in-place build (Sec. 7: the method needs one int per node of
+ * temporary storage, and a sort made only of swaps, such as bitonic sort,
+ * needs no more).  On completion d_points holds the tree in level order and
+ * d_perm[s] the original index of the point at node s.  d_perm is the one
+ * int per node: during the build it carries each point's original index
+ * (the tie-break of the order), so it is required.  Every data movement is
+ * a compare-exchange or a swap of (point, index) pairs; the tree, perm and
+ * dims are the same as kdt_build_ws's.  Slower than kdt_build_ws (whose
+ * workspace is about 95-130 bytes per point), for callers short of memory.
+ *
+ *   d_points   n*k float32, read and overwritten; 4-, 8- or 16-byte aligned
+ *              for k = 1 or 3, 2, 4.
+ *   d_perm     n uint32 (required).
+ *   d_dim      nullable; n uint8, as in kdt_build_ws.
+ *   d_status   nullable; as in kdt_build_ws (KDT_OK, KDT_ENONFINITE, plus
+ *              KDT_STATUS_INTERNAL_BIT if an internal bound check failed).
+ *   d_ws       at least kdt_inplace_workspace_bytes(n,k,mode) bytes,
+ *              256-byte aligned: a 256-byte header plus one byte (round
+ *              robin) or 33 bytes (split-widest) per subtree of the level
+ *              whose subtrees first fit 2047 points, i.e. about n/1024
+ *              subtrees.
+ * Buffers must not overlap.  Never allocates and never synchronises.
+ */
+size_t kdt_inplace_workspace_bytes(uint32_t n, uint32_t k, int dim_mode);
+kdt_status kdt_build_inplace(float* d_points, uint32_t n, uint32_t k, int dim_mode, uint32_t* d_perm,
+                             uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                             hipStream_t stream);
+/* The same for int32 coordinates (as kdt_build_ws_i32). */
+kdt_status kdt_build_inplace_i32(int32_t* d_points, uint32_t n, uint32_t k, int dim_mode, uint32_t* d_perm,
+                                 uint8_t* d_dim, uint32_t* d_status, void* d_ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/*
  * Build in place: on return (once `stream` has run the work) d_points holds
  * the tree in level order.  The library keeps one cached workspace per
  * (device, stream) pair, allocated on first use and grown when needed, so

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["kdt_kernels.hip", "kdt_tail.hip", "kdt_level_k1.hip", "kdt_level_k2.hip", "kdt_level_k3.hip",
-           "kdt_level_k4.hip", "kdt_api.hip", "kdt_plan.cpp", "kdt_server.hip"]
+           "kdt_level_k4.hip", "kdt_api.hip", "kdt_plan.cpp", "kdt_server.hip", "kdt_inplace.hip"]
 LIB = os.path.join(HERE, "libkdt.so")
 
 HIPCC_FLAGS = [

@@ -31,6 +31,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -98,12 +99,11 @@ kdt_status check_launch(const char* what)
 // final placement moves each point once more, 8k bytes (Sec. 5).  Steps
 // that only prepare an iteration (key prep, presorts, pivot selects) do no
 // such work and count 0.
-enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
-            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_BUCKET, KIND_WINDOW, KIND_COUNT };
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
                                             "k_level0", "k_level_select", "k_level_pivot", "k_level_part",
                                             "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_pack",
-                                            "k_rank_bucket", "k_rank_window"};
+                                            "k_rank_bucket", "k_rank_window", "k_ip_init", "k_ip_setup",
+                                            "k_ip_block", "k_ip_mirror", "k_ip_group", "k_ip_deep", "k_ip_perm"};
 
 struct ProfRec {
     int kind;
@@ -669,6 +669,11 @@ kdt_status enqueue_plan(const Plan& p, const float* pts, float* tree, uint32_t* 
                         uint32_t* status, char* ws, const void* h_tables, hipStream_t st)
 {
     return enqueue(p, pts, tree, perm, dim, status, ws, h_tables, st);
+}
+
+kdt_status launch_profiled(hipStream_t st, int kind, double bytes, double mbytes, const std::function<void()>& fn)
+{
+    return run_kernel(st, kind, bytes, mbytes, fn);
 }
 
 void set_last_error(const char* fmt, ...)

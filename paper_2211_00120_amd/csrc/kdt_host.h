@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+
 #include "../../include/kdt.h"
 #include "kdt_plan.h"
 
@@ -16,6 +18,18 @@ namespace kdt {
 // p.tables), read by an asynchronous copy on `st`.
 kdt_status enqueue_plan(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim,
                         uint32_t* status, char* ws, const void* h_tables, hipStream_t st);
+
+// Kernels as the profiler (kdt_profile_collect) names them.
+enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
+            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_BUCKET, KIND_WINDOW,
+            KIND_IP_INIT, KIND_IP_SETUP, KIND_IP_BLOCK, KIND_IP_MIRROR, KIND_IP_GROUP, KIND_IP_DEEP, KIND_IP_PERM,
+            KIND_COUNT };
+
+// Enqueue one launch through fn on st; while profiling is enabled it is
+// bracketed by two events and recorded under `kind` with `bytes` (moved by
+// this implementation) and `mbytes` (moved by the paper's method for the
+// work the launch completes).  Returns KDT_EDEVICE if the launch failed.
+kdt_status launch_profiled(hipStream_t st, int kind, double bytes, double mbytes, const std::function<void()>& fn);
 
 // Message of kdt_last_error() for the calling thread.
 void set_last_error(const char* fmt, ...);

@@ -49,6 +49,13 @@ _SIGS = {
     "kdt_build_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p]),
+    "kdt_inplace_workspace_bytes": (ctypes.c_size_t, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int]),
+    "kdt_build_inplace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p]),
+    "kdt_build_inplace_i32": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]),
     "kdt_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                                       ctypes.c_int]),
     "kdt_build_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
@@ -241,6 +248,38 @@ def build(points, mode: int = ROUND_ROBIN, stream=None):
     if rc != OK:
         raise KdtError(rc, "kdt_build")
     return points
+
+
+def inplace_workspace_bytes(n: int, k: int, mode: int = ROUND_ROBIN) -> int:
+    return int(lib().kdt_inplace_workspace_bytes(n, k, mode))
+
+
+def build_inplace(points, mode: int = ROUND_ROBIN, *, perm=None, dim=None, status=None, workspace=None,
+                  stream=None, want_dim=True):
+    """kdt_build_inplace (float32) or kdt_build_inplace_i32 (int32): replace
+    `points` by its tree in level order, with perm (one int32 per point, the
+    build's only per-point storage) receiving the original indices.  Missing
+    outputs and the (small) workspace are allocated here.  Returns
+    (points, perm, dim, status)."""
+    import torch
+    suffix = _check_points(points)
+    n, k = points.shape
+    dev = points.device
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+    if dim is None and want_dim:
+        dim = torch.empty(n, dtype=torch.uint8, device=dev)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+    nbytes = inplace_workspace_bytes(n, k, mode)
+    if workspace is None:
+        workspace = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    rc = getattr(lib(), "kdt_build_inplace" + suffix)(_ptr(points), n, k, mode, _ptr(perm), _ptr(dim),
+                                                     _ptr(status), _ptr(workspace),
+                                                     workspace.numel() * workspace.element_size(), _stream(stream))
+    if rc != OK:
+        raise KdtError(rc, "kdt_build_inplace" + suffix)
+    return points, perm, dim, status
 
 
 def _offsets(offsets):

@@ -213,10 +213,12 @@ def test_tuning_table_round_trip(tmp_path):
 SANITIZE = ["-O1", "-g", "-fsanitize=undefined,address", "-fno-sanitize-recover=all"]
 
 
-@pytest.mark.parametrize("prog", ["layout_check", "plan_check", "admit_check", "oracle_check"])
+@pytest.mark.parametrize("prog", ["layout_check", "inplace_check", "plan_check", "admit_check", "oracle_check"])
 def test_host_code_under_sanitizers(prog, tmp_path):
     """The host-side arithmetic the kernels share (kdt_layout.h, including
-    its edges: n = 0, levels at and below the last one, s = 2^32 - 1), the
+    its edges: n = 0, levels at and below the last one, s = 2^32 - 1; the
+    in-place build's in-order layout, sort schedule and swap-only
+    permutation to level order, kdt_inplace.h), the
     planner, the server's pool and admission, and the CPU oracle, built with
     AddressSanitizer and UndefinedBehaviorSanitizer (any report aborts the
     program)."""
@@ -227,7 +229,7 @@ def test_host_code_under_sanitizers(prog, tmp_path):
                os.path.join(ROOT, "oracle", "kdt_oracle.c"), "-o", exe]
     else:
         srcs = [os.path.join(ROOT, "tests", "host", prog + ".cpp")]
-        if prog != "layout_check":
+        if prog not in ("layout_check", "inplace_check"):
             srcs.append(os.path.join(inc, "kdt_plan.cpp"))
         cmd = ["g++", "-std=c++17", *SANITIZE, "-I", inc, *srcs, "-o", exe]
     subprocess.run(cmd, check=True)

@@ -1,0 +1,162 @@
+"""GPU parity of the low-memory in-place build (kdt_build_inplace) with the
+CPU oracle.
+
+The in-place build sorts every subtree's range of an in-order array with a
+swap-only bitonic network and permutes the result to level order with swaps;
+its tree is the unique tree of the (coordinate, index) order, so perm, dim
+and the overwritten points must equal the oracle's bit for bit.  Sizes cover
+the LDS-only path (n < 2048), the first levels that need global passes
+(2048 .. a few blocks), several global stages and the partial blocks of the
+final unshuffles, both coordinate types, all k and both split rules.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2211_00120_amd import kdt, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _omode(mode):
+    return oracle.WIDEST if mode == kdt.WIDEST else oracle.RR
+
+
+def _inplace(pts, mode):
+    t = torch.from_numpy(np.ascontiguousarray(pts)).to(DEV)
+    _, perm, dim, status = kdt.build_inplace(t, mode)
+    torch.cuda.synchronize()
+    return t.cpu().numpy(), perm.cpu().numpy().astype(np.uint32), dim.cpu().numpy(), int(status.item())
+
+
+def _assert_same(pts, mode, label):
+    _say(f"case inplace {label}: n={pts.shape[0]} k={pts.shape[1]} mode={mode} dtype={pts.dtype}")
+    tree, perm, dim, status = _inplace(pts, mode)
+    assert status == kdt.OK, f"{label}: device status {status:#x}"
+    perm_o, dim_o = oracle.build(pts, _omode(mode))
+    bad = np.flatnonzero(perm != perm_o)
+    assert bad.size == 0, f"{label}: perm differs at {bad.size} nodes, first {bad[:5]}"
+    assert np.array_equal(dim, dim_o), f"{label}: dim differs"
+    assert tree.tobytes() == np.ascontiguousarray(pts[perm_o]).tobytes(), f"{label}: tree bytes differ"
+
+
+GENS = {
+    "uniform": lambda n, k, s: workloads.uniform(n, k, s),
+    "grid": lambda n, k, s: workloads.grid(n, k, s, levels=7),
+    "signed": lambda n, k, s: workloads.signed_mix(n, k, s),
+    "int": lambda n, k, s: workloads.int_grid(n, k, s, levels=9),
+    "intx": lambda n, k, s: workloads.int_extremes(n, k, s),
+}
+
+SMALL_N = [1, 2, 3, 4, 5, 7, 10, 16, 17, 31, 63, 64, 100, 255, 256, 257, 1000, 1023, 1024, 1025, 2046, 2047]
+EDGE_N = [2048, 2049, 3000, 4095, 4096, 4097, 6143, 8191, 8192, 8193, 12345]
+MID_N = [65535, 65536, 65537, 100003, 262145]
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", SMALL_N)
+def test_inplace_small(n, k, mode):
+    gen = ["uniform", "grid", "signed", "int", "intx"][(n + k) % 5]
+    _assert_same(GENS[gen](n, k, 4000 + 7 * n + k), mode, f"small-{gen}")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("n", EDGE_N)
+def test_inplace_block_edges(n, k, mode):
+    gen = ["uniform", "grid", "signed", "int", "intx"][(n + k) % 5]
+    _assert_same(GENS[gen](n, k, 5000 + n + k), mode, f"edge-{gen}")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+@pytest.mark.parametrize("k", [2, 3, 4])
+@pytest.mark.parametrize("n", MID_N)
+def test_inplace_mid(n, k, mode):
+    gen = ["uniform", "grid", "signed", "int"][(n + k) % 4]
+    _assert_same(GENS[gen](n, k, 6000 + n + k), mode, f"mid-{gen}")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_inplace_large(mode):
+    n, k = 2_000_001, 4 if mode == kdt.WIDEST else 3
+    _assert_same(workloads.grid(n, k, 71, levels=11), mode, "large-grid")
+
+
+@pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
+def test_inplace_identical_points(mode):
+    _assert_same(np.full((9000, 3), -0.0, np.float32), mode, "identical")
+
+
+def test_inplace_equals_build_ws():
+    """The in-place build and kdt_build_ws give the same tree, perm and dims
+    (the cluster workload's shape, split-widest, at 3M points)."""
+    pts = workloads.cfg_cluster4d(n=3_000_000, seed=3, cluster=1 << 16)
+    _say("case inplace vs build_ws: cluster 3M")
+    t = torch.from_numpy(pts).to(DEV)
+    tree, perm, dim, status = kdt.build_ws(t, kdt.WIDEST)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    got_tree, got_perm, got_dim, got_status = _inplace(pts, kdt.WIDEST)
+    assert got_status == 0
+    assert np.array_equal(got_perm, perm.cpu().numpy().astype(np.uint32))
+    assert np.array_equal(got_dim, dim.cpu().numpy())
+    assert got_tree.tobytes() == tree.cpu().numpy().tobytes()
+
+
+@pytest.mark.parametrize("kind", ["uniform4d-rr", "mixture-rr"])
+def test_inplace_10m(kind):
+    """Full-size check at 10M points: the oracle's checker on every node
+    plus the overwritten points against the input in perm order."""
+    if kind == "uniform4d-rr":
+        pts, mode = workloads.uniform(10_000_000, 4, seed=7), kdt.ROUND_ROBIN
+    else:
+        pts, mode = workloads.cfg_mixture(), kdt.ROUND_ROBIN
+    _say(f"case inplace {kind} (checker)")
+    tree, perm, dim, status = _inplace(pts, mode)
+    assert status == kdt.OK
+    code, node = oracle.check(pts, perm, dim, _omode(mode))
+    assert code == 0, f"checker code {code} at node {node}"
+    assert tree.tobytes() == np.ascontiguousarray(pts[perm]).tobytes()
+
+
+def test_inplace_nonfinite_and_empty():
+    _say("case inplace nonfinite / empty")
+    pts = workloads.uniform(5000, 3, 8)
+    pts[77, 2] = np.inf
+    *_, status = _inplace(pts, kdt.WIDEST)
+    assert status & kdt.ENONFINITE
+    t = torch.zeros((0, 2), dtype=torch.float32, device=DEV)
+    _, perm, dim, status = kdt.build_inplace(t, kdt.ROUND_ROBIN)
+    torch.cuda.synchronize()
+    assert perm.numel() == 0 and int(status.item()) == 0
+
+
+def test_inplace_argument_errors():
+    _say("case inplace argument errors")
+    t = torch.zeros((100, 3), dtype=torch.float32, device=DEV)
+    ws = torch.empty(kdt.inplace_workspace_bytes(100, 3, kdt.ROUND_ROBIN), dtype=torch.uint8, device=DEV)
+    lib = kdt.lib()
+    stream = kdt._stream(None)
+    rc = lib.kdt_build_inplace(kdt._ptr(t), 100, 3, kdt.ROUND_ROBIN, None, None, None, kdt._ptr(ws),
+                               ws.numel(), stream)
+    assert rc == kdt.EINVAL                                  # perm is required
+    perm = torch.empty(100, dtype=torch.int32, device=DEV)
+    rc = lib.kdt_build_inplace(kdt._ptr(t), 100, 3, kdt.ROUND_ROBIN, kdt._ptr(perm), None, None, kdt._ptr(ws),
+                               ws.numel() - 1, stream)
+    assert rc == kdt.EINVAL                                  # workspace too small
+    rc = lib.kdt_build_inplace(kdt._ptr(t), 100, 5, kdt.ROUND_ROBIN, kdt._ptr(perm), None, None, kdt._ptr(ws),
+                               ws.numel(), stream)
+    assert rc == kdt.EINVAL                                  # k out of range
+    torch.cuda.synchronize()
