@@ -282,6 +282,20 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     // (free after the presorts) and the rank table (free after iteration 0)
     uint32_t* skey[2] = {keys, ranks};
 
+    // a single tree of at most TAIL_CAP points: one launch, which zeroes the
+    // status words itself and reports into the caller's (and the tree's own)
+    if (p.large.empty() && p.small.size() == 1 && !p.tables) {
+        o.status = status ? status : dstatus;
+        TailArgs a{};
+        a.sh = shares(p, p.small, p.t_small, ws);
+        a.from_points = 1;
+        a.init_status = 1;
+        a.o = o;
+        const uint32_t n1 = p.trees[p.small[0].tree].n;
+        return run_kernel(st, KIND_WHOLE, n1 * (8.0 * K + 4.0), method_bytes(n1, k, 0u),
+                          [&] { launch_tail((int)k, a, 1u, widest, st); });
+    }
+
     if (kdt_status s = run_kernel(st, KIND_INIT, 0.0, 0.0, [&] {
             launch_init(dstatus, counters, hist_rank, nlarge_trees * k * 4 * RADIX_HOST, lb[0],
                         pw.empty() ? 0u : pw[0], hist + p.hist_words, hist12_words, wcount,

@@ -60,6 +60,32 @@ KDT_HD uint32_t io_begin(const Level& v, uint32_t i) { return seg_offset(v, i) +
 // In-order position of that subtree's pivot (levels 0..L-2).
 KDT_HD uint32_t io_pivot(const Level& v, uint32_t i) { return io_begin(v, i) + seg_left_size(v, i); }
 
+// Subtree of level l (l <= L-2) whose in-order range holds position P (the
+// inverse of io_begin): its index, or 0xFFFFFFFF for a position holding a
+// node of the levels above.  The subtrees come in the three sizes of
+// kdt_layout.h, each followed by one such node.
+KDT_HD uint32_t io_seg_of(const Level& v, uint32_t P)
+{
+    const uint32_t a = v.R / v.W;                  // subtrees of the larger size (levels <= L-2: W >= 2)
+    const uint32_t big = 2u * v.W - 1u, small = v.W - 1u;
+    if (a >= v.nseg) {
+        const uint32_t i = P / (big + 1u);
+        return P - i * (big + 1u) < big ? i : 0xFFFFFFFFu;
+    }
+    const uint32_t head = a * (big + 1u);
+    if (P < head) {
+        const uint32_t i = P / (big + 1u);
+        return P - i * (big + 1u) < big ? i : 0xFFFFFFFFu;
+    }
+    const uint32_t mid = (v.W - 1u) + (v.R - a * v.W);
+    const uint32_t q = P - head;
+    if (q < mid) return a;
+    if (q == mid) return 0xFFFFFFFFu;
+    const uint32_t r = q - mid - 1u;
+    const uint32_t i = r / (small + 1u);
+    return r - i * (small + 1u) < small ? a + 1u + i : 0xFFFFFFFFu;
+}
+
 // First level whose subtrees (at most 2^(L-l) - 1 nodes) fit one LDS block.
 KDT_HD uint32_t deep_level(uint32_t L) { return L > BLK_LOG ? L - BLK_LOG : 0u; }
 
@@ -173,7 +199,7 @@ KDT_HD void plan_to_level_order(uint32_t n, F&& emit)
 // +infinity, ascending, without direction flips: stage e (blocks of 2^e)
 // first compares entry w of every block with entry 2^e - 1 - w (mirrored
 // pairs), then runs half-cleaners of strides 2^(e-2) .. 1 (entry i against
-// i + stride inside every block of twice the stride).  A compare-exchange
+// i + stride inside every block of twice the stride; stride 2^ls).  A compare-exchange
 // whose upper entry lies in the padding does nothing, so padding is never
 // stored.  Pair q of a step:
 KDT_HD void mirror_pair(uint32_t q, uint32_t e, uint32_t& lo, uint32_t& hi)
@@ -184,10 +210,10 @@ KDT_HD void mirror_pair(uint32_t q, uint32_t e, uint32_t& lo, uint32_t& hi)
     lo = b0 + w;
     hi = b0 + S - 1u - w;
 }
-KDT_HD void half_pair(uint32_t q, uint32_t stride, uint32_t& lo, uint32_t& hi)
+KDT_HD void half_pair(uint32_t q, uint32_t ls, uint32_t& lo, uint32_t& hi)   // stride 2^ls
 {
-    lo = (q / stride) * 2u * stride + (q % stride);
-    hi = lo + stride;
+    lo = ((q >> ls) << (ls + 1u)) | (q & ((1u << ls) - 1u));
+    hi = lo + (1u << ls);
 }
 
 // The passes of one iteration's sort over subtrees longer than one block:

@@ -293,12 +293,16 @@ __global__ __launch_bounds__(256) void k_ip_setup(const uint32_t* __restrict__ p
 
 // One LDS block (BLK entries) of one subtree of iteration l: SORT runs the
 // whole bitonic network of the block, MERGE the strides BLK/2 .. 1 of the
-// current stage.
+// current stage.  The network runs on (key, slot) pairs in LDS; then every
+// thread reads the records its output positions receive (all reads before
+// any write) and stores them.
 template <int K, bool I32, bool SORT>
 __global__ __launch_bounds__(256) void k_ip_block(uint32_t* __restrict__ pts, uint32_t* __restrict__ perm, uint32_t n,
                                                   uint32_t l, uint32_t dimrr, const uint8_t* segdim, uint32_t* hdr)
 {
-    __shared__ Lds<K> s;
+    constexpr uint32_t E = BLK / THREADS;
+    __shared__ uint64_t key[BLK];
+    __shared__ uint16_t slot[BLK];
     const Level v = make_level(n, l);
     const SegTiles t = tiles_level(v, BLK);
     uint32_t seg, u;
@@ -311,23 +315,49 @@ __global__ __launch_bounds__(256) void k_ip_block(uint32_t* __restrict__ pts, ui
         return;
     }
     const uint32_t d = seg_dim(segdim, dimrr, seg);
-    lds_load<K>(s, pts, perm, base, cnt);
+    for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
+        key[p] = rkey<I32>(pts[(size_t)(base + p) * K + d], perm[base + p]);
+        slot[p] = (uint16_t)p;
+    }
     __syncthreads();
     for (uint32_t e = SORT ? 1u : BLK_LOG; e <= BLK_LOG; ++e) {
-        for (uint32_t st = 1u << (e - 1u); st >= 1u; st >>= 1) {
-            const bool mirrored = SORT && st == (1u << (e - 1u));
+        for (int ls = (int)e - 1; ls >= 0; --ls) {
+            const bool mirrored = SORT && ls == (int)e - 1;
             for (uint32_t q = threadIdx.x; q < BLK / 2; q += THREADS) {
                 uint32_t lo, hi;
                 if (mirrored)
                     mirror_pair(q, e, lo, hi);
                 else
-                    half_pair(q, st, lo, hi);
-                if (hi < cnt) lds_cmpx<K, I32>(s, lo, hi, d);
+                    half_pair(q, (uint32_t)ls, lo, hi);
+                if (hi < cnt) {
+                    const uint64_t a = key[lo], b = key[hi];
+                    if (a > b) {
+                        key[lo] = b;
+                        key[hi] = a;
+                        const uint16_t ts = slot[lo];
+                        slot[lo] = slot[hi];
+                        slot[hi] = ts;
+                    }
+                }
             }
             __syncthreads();
         }
     }
-    lds_store<K>(s, pts, perm, base, cnt);
+    uint32_t rc[E][K];
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) {
+        const uint32_t p = threadIdx.x + j * THREADS;
+        if (p < cnt && slot[p] != p) ld_pt<K>(pts, base + slot[p], rc[j]);
+    }
+    __syncthreads();                        // every read of the block done before any write
+#pragma unroll
+    for (uint32_t j = 0; j < E; ++j) {
+        const uint32_t p = threadIdx.x + j * THREADS;
+        if (p < cnt && slot[p] != p) {
+            st_pt<K>(pts, base + p, rc[j]);
+            perm[base + p] = (uint32_t)key[p];
+        }
+    }
 }
 
 // First step of stage S = 2^e of iteration l over global memory: entry w of
@@ -421,13 +451,18 @@ __global__ __launch_bounds__(256) void k_ip_group(uint32_t* __restrict__ pts, ui
 }
 
 // The iterations lg .. L-2 of one level-lg subtree (at most BLK - 1 nodes)
-// in LDS, and the split dimensions of its nodes (levels lg .. L-1).
+// in LDS, and the split dimensions of its nodes (levels lg .. L-1).  Each
+// iteration sorts (key, slot) pairs of every sub-segment with the bitonic
+// network, then moves the records to their new slots.
 template <int K, bool I32, bool WIDE>
 __global__ __launch_bounds__(256) void k_ip_deep(uint32_t* __restrict__ pts, uint32_t* __restrict__ perm, uint32_t n,
                                                  uint32_t lg, const uint32_t* hdr, const uint32_t* boxes,
                                                  uint8_t* dim, uint32_t* hdr_w)
 {
+    constexpr uint32_t E = BLK / THREADS;
     __shared__ Lds<K> s;
+    __shared__ uint64_t key[BLK];
+    __shared__ uint16_t slot[BLK];
     __shared__ uint8_t sdim[BLK / 2];
     const uint32_t L = num_levels(n);
     const uint32_t i0 = blockIdx.x;
@@ -468,11 +503,11 @@ __global__ __launch_bounds__(256) void k_ip_deep(uint32_t* __restrict__ pts, uin
                     const Level va = make_level(n, a);
                     const uint32_t ia = ig >> (lp - a);
                     const uint32_t d = widest_dim<K, I32>(lo, hi);
-                    const uint32_t key = coord_key<I32>(s.c[d][io_pivot(va, ia) - base0]);
+                    const uint32_t kk = coord_key<I32>(s.c[d][io_pivot(va, ia) - base0]);
                     if ((ig >> (lp - a - 1u)) & 1u)
-                        set_at<K>(lo, d, key);
+                        set_at<K>(lo, d, kk);
                     else
-                        set_at<K>(hi, d, key);
+                        set_at<K>(hi, d, kk);
                 }
                 dd = widest_dim<K, I32>(lo, hi);
             } else {
@@ -483,30 +518,68 @@ __global__ __launch_bounds__(256) void k_ip_deep(uint32_t* __restrict__ pts, uin
         }
         if (last) break;
         __syncthreads();
+        // keys of this iteration: (coordinate in the sub-segment's dimension, index)
+        for (uint32_t p = threadIdx.x; p < cnt; p += THREADS) {
+            const uint32_t sg = io_seg_of(v, base0 + p);
+            const uint32_t dd = sg == 0xFFFFFFFFu ? 0u : (uint32_t)sdim[sg - (i0 << rel)];
+            key[p] = rkey<I32>(s.c[dd][p], s.id[p]);
+            slot[p] = (uint16_t)p;
+        }
+        __syncthreads();
         const uint32_t P = net_len(v);
         const uint32_t logP = log2_exact(P);
         const uint32_t pairs = nsub << (logP - 1u);
         for (uint32_t e = 1; e <= logP; ++e) {
-            const uint32_t H = 1u << (e - 1u);
-            for (uint32_t st = H; st >= 1u; st >>= 1) {
+            for (int ls = (int)e - 1; ls >= 0; --ls) {
                 for (uint32_t g = threadIdx.x; g < pairs; g += THREADS) {
                     const uint32_t j = g >> (logP - 1u);
                     const uint32_t q = g & ((P >> 1) - 1u);
                     const uint32_t ig = (i0 << rel) | j;
                     const uint32_t size = seg_size(v, ig);
                     uint32_t lo, hi;
-                    if (st == H)
+                    if (ls == (int)e - 1)
                         mirror_pair(q, e, lo, hi);
                     else
-                        half_pair(q, st, lo, hi);
+                        half_pair(q, (uint32_t)ls, lo, hi);
                     if (hi < size) {
                         const uint32_t pb = io_begin(v, ig) - base0;
-                        lds_cmpx<K, I32>(s, pb + lo, pb + hi, sdim[j]);
+                        const uint64_t a = key[pb + lo], b = key[pb + hi];
+                        if (a > b) {
+                            key[pb + lo] = b;
+                            key[pb + hi] = a;
+                            const uint16_t ts = slot[pb + lo];
+                            slot[pb + lo] = slot[pb + hi];
+                            slot[pb + hi] = ts;
+                        }
                     }
                 }
                 __syncthreads();
             }
         }
+        // records to their new slots: read every moved record, then write
+        uint32_t rc[E][K];
+        uint32_t rid[E];
+#pragma unroll
+        for (uint32_t j = 0; j < E; ++j) {
+            const uint32_t p = threadIdx.x + j * THREADS;
+            if (p < cnt && slot[p] != p) {
+                const uint32_t src = slot[p];
+#pragma unroll
+                for (int d = 0; d < K; ++d) rc[j][d] = s.c[d][src];
+                rid[j] = s.id[src];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t j = 0; j < E; ++j) {
+            const uint32_t p = threadIdx.x + j * THREADS;
+            if (p < cnt && slot[p] != p) {
+#pragma unroll
+                for (int d = 0; d < K; ++d) s.c[d][p] = rc[j][d];
+                s.id[p] = rid[j];
+            }
+        }
+        __syncthreads();
     }
     __syncthreads();
     lds_store<K>(s, pts, perm, base0, cnt);

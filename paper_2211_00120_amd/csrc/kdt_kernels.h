@@ -159,6 +159,7 @@ struct TailArgs {
     const uint32_t* xmap;   // null, or per workgroup its group (0xFFFFFFFF: none), trees grouped by XCD
     const uint32_t* rin[2]; // the two record buffers (share.buf selects; from_points: unused)
     uint32_t from_points;   // whole trees of at most TAIL_CAP points, built from the points
+    uint32_t init_status;   // a single workgroup that first zeroes o.status itself (no init launch)
     Outs o;
 };
 

@@ -268,6 +268,13 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     __shared__ uint32_t bxk[8];                    // from_points split-widest: scene box keys
 
     const Outs& o = a.o;
+    if (a.init_status) {                           // one workgroup, one tree: it clears its status words itself
+        if (threadIdx.x == 0) {
+            *o.status = 0u;
+            o.tstatus[0] = 0u;
+        }
+        __syncthreads();
+    }
     // with an XCD map, workgroup b (on XCD b mod 8) takes the group the map
     // gives it: a tree's groups all on one XCD, whose L2 then holds the
     // tree's index list and points for the gathers; padding takes none

@@ -85,6 +85,14 @@ static void check_layout(uint32_t n)
             if (l + 2 <= L) CHECK(io_pivot(v, i) == t.pos[s], "io_pivot n=%u l=%u i=%u", n, l, i);
         }
         if (l + 2 <= L) {
+            // io_seg_of inverts io_begin: every position of a subtree's range maps to it,
+            // the nodes of the levels above to 0xFFFFFFFF
+            std::vector<uint32_t> want(n, 0xFFFFFFFFu);
+            for (uint32_t i = 0; i < v.nseg; ++i)
+                for (uint32_t p = io_begin(v, i); p < io_begin(v, i) + seg_size(v, i); ++p) want[p] = i;
+            for (uint32_t p = 0; p < n; ++p) CHECK(io_seg_of(v, p) == want[p], "io_seg_of n=%u l=%u p=%u", n, l, p);
+        }
+        if (l + 2 <= L) {
             uint32_t mx = 0;
             for (uint32_t i = 0; i < v.nseg; ++i) mx = std::max(mx, seg_size(v, i));
             CHECK(mx == seg_size(v, 0), "largest subtree is subtree 0, n=%u l=%u", n, l);
@@ -153,13 +161,13 @@ static void block_pass(std::vector<uint64_t>& k, uint32_t len, bool sort)
     for (uint32_t u = 0; u * BLK < len; ++u) {
         const uint32_t base = u * BLK, cnt = std::min(BLK, len - base);
         for (uint32_t e = sort ? 1u : BLK_LOG; e <= BLK_LOG; ++e)
-            for (uint32_t st = 1u << (e - 1); st >= 1; st >>= 1)
+            for (int ls = (int)e - 1; ls >= 0; --ls)
                 for (uint32_t q = 0; q < BLK / 2; ++q) {
                     uint32_t lo, hi;
-                    if (sort && st == (1u << (e - 1)))
+                    if (sort && ls == (int)e - 1)
                         mirror_pair(q, e, lo, hi);
                     else
-                        half_pair(q, st, lo, hi);
+                        half_pair(q, (uint32_t)ls, lo, hi);
                     if (hi < cnt) cmpx(k, base + lo, base + hi);
                 }
     }
@@ -232,6 +240,13 @@ int main()
         check_ops(n);
     }
     check_groups();
+    for (uint32_t q = 0; q < (1u << 16); q += 7)
+        for (uint32_t ls = 0; ls < 12; ++ls) {
+            uint32_t lo, hi;
+            half_pair(q, ls, lo, hi);
+            const uint32_t st = 1u << ls;
+            CHECK(lo == (q / st) * 2 * st + q % st && hi == lo + st, "half_pair q=%u ls=%u", q, ls);
+        }
     for (uint32_t len : {1u, 2u, 3u, 100u, 2047u, 2048u, 2049u, 3000u, 4095u, 4096u, 4097u, 8191u, 9000u, 16384u,
                          20000u, 40000u, 65536u, 70001u})
         check_sort(len, log2_exact(ceil_pow2(len)), rng);
