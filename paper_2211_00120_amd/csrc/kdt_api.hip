@@ -160,6 +160,14 @@ double method_bytes(uint32_t n, uint32_t k, uint32_t l0)
     return b;
 }
 
+// method_bytes over the trees built by digit passes.
+double method_bytes_large(const Plan& p, uint32_t k)
+{
+    double b = 0;
+    for (uint32_t t : p.large) b += method_bytes(p.trees[t].n, k, 0u);
+    return b;
+}
+
 kdt_status validate_k_mode(uint32_t k, int mode)
 {
     if (k < 1 || k > 4) {
@@ -252,7 +260,6 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
     o.dim = widest ? nullptr : dim;
     o.nodeperm = perm ? perm : (uint32_t*)(ws + p.o_nodeperm);
     o.dimnode = (widest && dim) ? dim : (uint8_t*)(ws + p.o_dimnode);
-    o.perm0 = perms;
     o.status = dstatus;
     o.tstatus = (uint32_t*)(ws + p.o_tstatus);
     o.box[0] = (uint32_t*)(ws + p.o_box[0]);
@@ -386,6 +393,8 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 a.dimnode = widest ? o.dimnode : nullptr;
                 a.ntotal = ntotal;
                 a.status = dstatus;
+                a.place1 = (k == 1 && ps == 3) ? 1u : 0u;
+                a.o = o;
                 double bytes = 0;
                 if (g_prof.on) {
                     for (uint32_t d = d0; d < d0 + nd; ++d)
@@ -399,12 +408,15 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                             bytes += p.trees[p.large[i]].n * (first ? 12.0 : 16.0);
                         }
                 }
-                if (kdt_status s = run_kernel(st, KIND_PRESORT, bytes, 0.0,
+                // with k = 1 the last pass places the trees: it completes
+                // every iteration of the method
+                const double mb = a.place1 ? method_bytes_large(p, k) : 0.0;
+                if (kdt_status s = run_kernel(st, KIND_PRESORT, bytes, mb,
                                               [&] { launch_presort_pass(a, ps == 3, nd * p.presort_tiles, st); }))
                     return s;
             }
             ++q;
-            if (p.rank_dm && ps == 3) {
+            if (p.rank_dm && ps == 3 && k > 1) {
                 // the dimensions' ranks into their arrays, window by window;
                 // the buckets take the ping-pong of the dimension just sorted
                 for (uint32_t d = d0; d < d0 + nd; ++d) {
@@ -434,6 +446,15 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                         return s;
                 }
             }
+        }
+
+        if (k == 1) {
+            // one dimension: the last presort pass has placed every large
+            // tree (the sorted order is the tree's in-order sequence)
+            if (status)
+                if (kdt_status s = run_kernel(st, KIND_STATUS, 8.0, 0.0, [&] { launch_copy_word(status, dstatus, st); }))
+                    return s;
+            return KDT_OK;
         }
 
         // per-dimension ranks -> point-major records in rec[1], which is free
@@ -486,6 +507,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     sa.digit = (uint32_t)j;
                     sa.radix_bits = p.RB;
                     sa.status = dstatus;
+                    sa.dimnode = widest ? o.dimnode : nullptr;
                     if (kdt_status s = run_kernel(st, KIND_SELECT, live * 4.0, 0.0,
                                                   [&] { launch_level_select(sa, ll.select_tiles, st); }))
                         return s;

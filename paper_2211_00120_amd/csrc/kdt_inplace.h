@@ -98,26 +98,6 @@ KDT_HD uint32_t log2_exact(uint32_t p) { return 31u - (uint32_t)__builtin_clz(p)
 // Subtree 0 is the level's largest.
 KDT_HD uint32_t net_len(const Level& v) { return ceil_pow2(seg_size(v, 0)); }
 
-// In-order position -> level-order node of a left-balanced complete tree of
-// n nodes (n >= 1).
-KDT_HD uint32_t inorder_to_level(uint32_t p, uint32_t n)
-{
-    const uint32_t L = num_levels(n);
-    const uint32_t U = full_nodes(L - 1u);        // nodes above the last level
-    const uint32_t m = n - U;                      // leaves on the last level
-    uint32_t u;                                    // in-order index inside the upper perfect tree
-    if (p < 2u * m) {
-        if ((p & 1u) == 0u) return U + (p >> 1);
-        u = p >> 1;
-    } else {
-        u = p - m;
-    }
-    // perfect tree of L-1 levels: in-order index u -> level order
-    const uint32_t z = (uint32_t)__builtin_ctz(u + 1u);    // height above the bottom
-    const uint32_t lev = (L - 2u) - z;
-    return full_nodes(lev) + ((u + 1u) >> (z + 1u));
-}
-
 // One step of the in-order -> level-order permutation.
 enum OpKind : uint32_t {
     OP_UNSHUF_LDS = 0,   // blocks of BLK entries of [a, a+n): odd offsets first, then even ones

@@ -34,7 +34,6 @@ struct Outs {
     uint8_t* dim;           // nullable (round robin)
     uint32_t* nodeperm;     // original (local) index per node (the caller's perm or workspace)
     uint8_t* dimnode;       // split dim per node (split-widest; caller's dim or workspace)
-    const uint32_t* perm0;  // per tree: rank in dimension 0 -> local index
     uint32_t* status;       // device status word
     uint32_t* tstatus;      // per tree of the call (TreeStep::tree): its own status word (non-finite input)
     uint32_t* box[2];       // split-widest domains of live subtrees as keys of their bounds,
@@ -83,6 +82,10 @@ struct PresortArgs {
     size_t rank_dstride;
     uint32_t ntotal;
     uint32_t* status;
+    // k = 1: the last pass places every tree (its sorted order is the tree's
+    // in-order sequence), with o's outputs; no iteration follows
+    uint32_t place1;
+    Outs o;
 };
 
 struct Level0Args {
@@ -111,16 +114,18 @@ struct LevelSelectArgs {
     uint32_t digit;         // digit counted by this launch (0 = lowest)
     uint32_t radix_bits;
     uint32_t* status;
+    const uint8_t* dimnode; // split-widest: node dims; subtrees split in the root's dimension are skipped
+                            // (their pivot is the point at position ss(2s+1))
 };
 
 // The pivot of every subtree of iteration l, one wave per subtree: its key
-// (from the digit histograms, or, when `sorted`, the key at its position),
+// (from the digit histograms, or, in the root's dimension, its position),
 // its node's point (placed here) and, for split-widest, its children's
 // dimensions and domains.  Writes piv[share.piv + 2*seg] = key and
 // piv[share.piv + 2*seg + 1] = child dimensions (left | right << 8).
 struct LevelPivotArgs {
     Shares sh;              // shares of one iteration, workgroups of PIVOT_SEGS subtrees
-    const uint32_t* rin;    // records (read when `sorted`)
+    const uint32_t* rin;    // records (the pivot record of segments split in the root's dimension)
     const uint32_t* hist;   // histogram region; share.hist word offsets
     uint32_t* piv;
     const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]

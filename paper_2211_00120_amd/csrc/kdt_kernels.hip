@@ -288,6 +288,24 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         [&](const uint4& r) { return (r.x >> shift) & 0xFFu; },
         [&](uint32_t, uint32_t pos, const uint4& r) {
             if (!in_bounds(pos, n, a.status) || !in_bounds(r.y, n, a.status)) return;
+            if (LAST && a.place1) {
+                // k = 1: with one dimension every iteration after the first
+                // finds its subtrees already sorted, and the update only
+                // renumbers tags, so the point of rank pos ends at the node
+                // the in-order position pos has in the tree
+                const size_t at = off + inorder_to_level(pos, n);
+                if (a.o.tree) {
+                    uint32_t b;
+                    if (a.o.i32) b = r.x ^ 0x80000000u;                     // int32 key: sign flip
+                    else if (r.x == 0x80000000u) b = ((const uint32_t*)a.o.pts)[off + r.y];   // +-0: the point's own bits
+                    else b = (r.x & 0x80000000u) ? (r.x ^ 0x80000000u) : ~r.x;
+                    ((uint32_t*)a.o.tree)[at] = b;
+                }
+                a.o.nodeperm[at] = r.y;
+                if (a.o.dim) a.o.dim[at] = 0u;
+                if (a.o.dimnode) a.o.dimnode[at] = 0u;
+                return;
+            }
             if (LAST) {
                 perm_out[off + pos] = r.y;
                 if (to_table && a.rank_table)
@@ -505,13 +523,20 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
             continue;
         }
         uint4 rec = load_rec4<K>(a.rank_table, off + idx);
-        set4(rec, d0, r);                   // the root dimension's rank is the position
+        // the root dimension's rank is the position (every later segment
+        // keeps the root dimension's order), so its slot carries the index
+        set4(rec, d0, idx);
         const uint32_t side = r > piv ? 1u : 0u;
         store_rec4<K>(a.rout, off + r - side, rec);
         if (acc) {
-            const uint32_t kv = pick4(rec, side ? cd1 : cd0);
-            a.kout[off + r - side] = kv;
-            atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+            // no split key for a child split in the root's dimension: its
+            // pivot is found by position
+            const uint32_t cd = side ? cd1 : cd0;
+            if (cd != d0) {
+                const uint32_t kv = pick4(rec, cd);
+                a.kout[off + r - side] = kv;
+                atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+            }
         }
     }
     if (acc) {
@@ -549,6 +574,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_select(LevelSelectArgs 
     const SegTiles tl = tiles_level(v, HIST_TILE);
     uint32_t seg, u;
     tile_locate(tl, blockIdx.x - st.tile0, seg, u);
+    // a subtree split in the root's dimension needs no select (its keys are
+    // positions, and its pivot the point at position ss(2s+1))
+    if (a.dimnode && a.dimnode[ti.off + v.Fl + seg] == a.dimnode[ti.off]) return;
     const uint32_t soff = tiles_seg_offset(tl, seg);
     const uint32_t sz = tiles_seg_size(tl, seg);
     const uint32_t start = u * HIST_TILE;

@@ -110,6 +110,30 @@ KDT_HD uint32_t seg_of_pos(const Level& v, uint32_t p)
     return a + 1u + (q - mid) / (v.W - 1u);
 }
 
+// In-order position -> level-order node of a left-balanced complete tree of
+// n nodes (n >= 1).  With U = F(L-1) nodes above the last level and m = n - U
+// leaves, the in-order sequence interleaves the first m in-order nodes of the
+// upper perfect tree with the leaves (leaf j directly precedes upper node j),
+// then lists the remaining upper nodes; an upper node's level and index follow
+// from the trailing zeros of its in-order index plus one.
+KDT_HD uint32_t inorder_to_level(uint32_t p, uint32_t n)
+{
+    const uint32_t L = num_levels(n);
+    const uint32_t U = full_nodes(L - 1u);        // nodes above the last level
+    const uint32_t m = n - U;                      // leaves on the last level
+    uint32_t u;                                    // in-order index inside the upper perfect tree
+    if (p < 2u * m) {
+        if ((p & 1u) == 0u) return U + (p >> 1);
+        u = p >> 1;
+    } else {
+        u = p - m;
+    }
+    // perfect tree of L-1 levels: in-order index u -> level order
+    const uint32_t z = (uint32_t)__builtin_ctz(u + 1u);    // height above the bottom
+    const uint32_t lev = (L - 2u) - z;
+    return full_nodes(lev) + ((u + 1u) >> (z + 1u));
+}
+
 // Subtrees of a level come in three sizes (see the header comment); a
 // segment-aligned tiling cuts each one into tiles of at most `tile` points.
 struct SegTiles {

@@ -43,11 +43,15 @@ __global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs 
     const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[off + v.Fl + seg] : st.level % a.k;
     const uint32_t ls = seg_left_size(v, seg);
     const uint32_t s = v.Fl + seg;
+    // the root's dimension: every segment is in its order, so the pivot is
+    // the record at position ls, which carries the point's index in that
+    // dimension's slot; its key for the split is that live position
+    const uint32_t d0 = WIDEST ? (uint32_t)a.o.dimnode[off] : 0u;
     uint32_t p = 0;
-    if (a.sorted) {
-        // the pivot's position in the live array
-        const uint32_t pos = seg_offset(v, seg) + ls;
-        p = pick4(load_rec4<K>(a.rin, off + pos), d);
+    uint32_t idx = 0;
+    if (d == d0) {
+        p = seg_offset(v, seg) + ls;
+        idx = pick4(load_rec4<K>(a.rin, off + p), d0);
     } else {
         const uint32_t RBv = a.radix_bits;
         const uint32_t NB = 1u << RBv;
@@ -57,8 +61,7 @@ __global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs 
             p = (p << RBv) | wave_find_bucket(h + (size_t)jj * NB, NB, kk, a.o.status);
     }
     if (lane_id() != 0) return;
-    uint32_t idx = 0;
-    if (in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
+    if (d != d0 && in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
     if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
     place<K, WIDEST>(a.o, ti, s, idx);
     uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;
@@ -97,6 +100,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
     const uint32_t cnt = min(T, ssz - start);
     const size_t off = ti.off;
     const uint32_t d = WIDEST ? (uint32_t)a.o.dimnode[off + v.Fl + seg] : st.level % a.k;
+    const uint32_t d0 = WIDEST ? (uint32_t)a.o.dimnode[off] : 0u;   // the root's dimension
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     const uint32_t live = v.n - v.Fl;
     const uint32_t RBv = a.radix_bits;
@@ -131,12 +135,19 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         segc[3] = 0u;
     }
 
+    // the comparison with the pivot: by key, or in the root's dimension (the
+    // segment's own order, whose slot holds the index) by position
+    const bool bypos = d == d0;
     uint32_t dig[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t x = pick4(rec[i], d);
-        dig[i] = x < p ? 0u : (x == p ? 1u : 2u);
+        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+        const uint32_t x = bypos ? start + j : pick4(rec[i], d);
+        const uint32_t y = bypos ? ls : p;
+        dig[i] = x < y ? 0u : (x == y ? 1u : 2u);
     }
+    // (the split pass stores from registers: sweep_tile never re-derives a
+    // digit from a record, which for the root's dimension it could not)
     auto digit_of = [&](const uint4& r) {
         const uint32_t x = pick4(r, d);
         return x < p ? 0u : (x == p ? 1u : 2u);
@@ -149,9 +160,14 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_level_part(LevelPartArgs a)
         if (!in_bounds(pos, live, a.o.status) || !in_bounds(nxt, live - v.nseg, a.o.status)) return;
         store_rec4<K>(a.rout, off + nxt, r);
         if (keys) {
-            const uint32_t kv = K == 1 ? r.x : (side ? pick4(r, cd1) : pick4(r, cd0));
-            a.kout[off + nxt] = kv;
-            atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+            // no split key for a child split in the root's dimension: its
+            // pivot is found by position
+            const uint32_t cd = side ? cd1 : cd0;
+            if (cd != d0) {
+                const uint32_t kv = pick4(r, cd);
+                a.kout[off + nxt] = kv;
+                atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+            }
         }
     };
     sweep_tile<PART_RB, ITEMS, K, decltype(digit_of), decltype(store), false>(

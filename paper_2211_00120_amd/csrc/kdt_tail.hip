@@ -331,9 +331,9 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
         }
     } else {
-        // the records, then each slot's index (rank 0 -> index): the loads of
-        // each kind go out together, and the index gathers complete while the
-        // group sorts (the points follow after the sorts)
+        // the records (the root dimension's slot holds the point's index:
+        // the segments are in that dimension's order), then the segment of
+        // every slot (the points follow after the sorts)
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
@@ -344,11 +344,9 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
             seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
         }
+        const uint32_t d0 = WIDEST ? (uint32_t)o.dimnode[off] : 0u;
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const bool in = rec[i].x < ti.n;
-            idx[i] = (ok[i] && in) ? o.perm0[off + rec[i].x] : 0xFFFFFFFFu;
-        }
+        for (int i = 0; i < ITEMS; ++i) idx[i] = ok[i] ? pick4(rec[i], d0) : 0xFFFFFFFFu;
     }
     if (FP) {
         if (__any(bad) && lane == 0) {
