@@ -103,7 +103,7 @@ const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k
                                             "k_level0", "k_level_select", "k_level_pivot", "k_level_part",
                                             "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_pack",
                                             "k_rank_bucket", "k_rank_window", "k_ip_init", "k_ip_setup",
-                                            "k_ip_block", "k_ip_mirror", "k_ip_group", "k_ip_deep", "k_ip_perm"};
+                                            "k_ip_block", "k_ip_mgroup", "k_ip_group", "k_ip_deep", "k_ip_perm"};
 
 struct ProfRec {
     int kind;

@@ -53,6 +53,9 @@ constexpr uint32_t BLK_LOG = 11;
 constexpr uint32_t BLK = 1u << BLK_LOG;   // records of one LDS block (2048 x (k+1) words)
 constexpr uint32_t THREADS = 256;         // threads of the LDS kernels
 constexpr uint32_t GROUP_MAX = 4;         // strides one global compare-exchange pass applies
+constexpr uint32_t SBLK_LOG = 12;
+constexpr uint32_t SBLK = 1u << SBLK_LOG; // entries of one LDS block of an iteration's sort
+constexpr uint32_t MGROUP_MAX = 3;        // first strides of a stage (the mirrored one first) in one pass
 
 // In-order begin of the i-th subtree of level l (levels 0..L-1; on level
 // L-1 only the R existing leaves, i < R).
@@ -197,27 +200,39 @@ KDT_HD void half_pair(uint32_t q, uint32_t ls, uint32_t& lo, uint32_t& hi)   // 
 }
 
 // The passes of one iteration's sort over subtrees longer than one block:
-// stages up to BLK inside LDS blocks, then per larger stage one pass of
-// mirrored pairs, the half-cleaner strides down to BLK in groups of up to
-// GROUP_MAX per pass (largest first), and the strides below BLK in LDS.
-enum StepKind : uint32_t { ST_BLOCK_SORT = 0, ST_MIRROR = 1, ST_GROUP = 2, ST_BLOCK_MERGE = 3 };
+// stages up to SBLK inside LDS blocks, then per larger stage e one pass of
+// its first strides (the mirrored one, 2^(e-1), and half-cleaners down to
+// 2^(e-c)), the remaining half-cleaner strides down to SBLK in groups of up
+// to GROUP_MAX per pass (largest first), and the strides below SBLK in LDS.
+enum StepKind : uint32_t { ST_BLOCK_SORT = 0, ST_MGROUP = 1, ST_GROUP = 2, ST_BLOCK_MERGE = 3 };
 struct Step {
-    uint32_t kind, e, e0, c;   // ST_MIRROR: stage e; ST_GROUP: strides 2^e0 .. 2^(e0+c-1)
+    uint32_t kind, e, e0, c;   // ST_MGROUP: stage e, strides 2^(e-1) .. 2^(e-c); ST_GROUP: strides 2^e0 .. 2^(e0+c-1)
 };
 template <class F>
 KDT_HD void plan_level_sort(uint32_t logP, F&& emit)
 {
     emit(Step{ST_BLOCK_SORT, 0u, 0u, 0u});
-    for (uint32_t e = BLK_LOG + 1u; e <= logP; ++e) {
-        emit(Step{ST_MIRROR, e, 0u, 0u});
-        uint32_t top = e - 2u;                            // largest half-cleaner stride exponent
-        while (top + 1u > BLK_LOG) {
-            const uint32_t c = umin(GROUP_MAX, top - BLK_LOG + 1u);
+    for (uint32_t e = SBLK_LOG + 1u; e <= logP; ++e) {
+        const uint32_t cm = umin(MGROUP_MAX, e - SBLK_LOG);
+        emit(Step{ST_MGROUP, e, e - cm, cm});
+        uint32_t top = e - 1u - cm;                       // largest half-cleaner stride exponent left
+        while (top + 1u > SBLK_LOG) {
+            const uint32_t c = umin(GROUP_MAX, top - SBLK_LOG + 1u);
             emit(Step{ST_GROUP, e, top - c + 1u, c});
             top -= c;
         }
         emit(Step{ST_BLOCK_MERGE, e, 0u, 0u});
     }
+}
+
+// A mirrored group pass over stage e with c strides takes two groups of 2^c
+// entries per thread: A with base b, B with base b ^ (2^e0 - 1) (e0 = e - c),
+// entries b | x << e0; entry x of A and entry 2^c - 1 - x of B are mirrored
+// in their 2^e-block.  Pair h of a network of length 2^logP has zeros in bits
+// [e0 - 1, e0 + c) of its A base (e0 >= 1).
+KDT_HD uint32_t mgroup_base(uint32_t h, uint32_t e0, uint32_t c)
+{
+    return ((h >> (e0 - 1u)) << (e0 + c)) | (h & ((1u << (e0 - 1u)) - 1u));
 }
 
 // Position (relative to the range start) of element e of a compare-exchange

@@ -11,10 +11,11 @@
 //   k_ip_clear, k_ip_init             perm = identity, non-finite flag, scene box
 //   iterations l = 0 .. lg-1          (subtrees larger than one LDS block)
 //     [k_ip_setup]                    split-widest: every subtree's domain and dim
-//     k_ip_block<SORT>                bitonic sort of every BLK-block of every subtree
-//     per stage S = 2 BLK .. P:       k_ip_mirror (stride S/2, mirrored pairs),
-//                                     k_ip_group (strides S/4 .. BLK, up to 4 per pass),
-//                                     k_ip_block<MERGE> (strides BLK/2 .. 1 in LDS)
+//     k_ip_block<SORT>                bitonic sort of every SBLK-block of every subtree
+//     per stage S = 2 SBLK .. P:      k_ip_mgroup (the mirrored stride S/2 and the
+//                                     next up to two, two mirrored groups per thread),
+//                                     k_ip_group (strides down to SBLK, up to 4 per pass),
+//                                     k_ip_block<MERGE> (strides SBLK/2 .. 1 in LDS)
 //   [k_ip_setup]                      split-widest: domains of the level-lg subtrees
 //   k_ip_deep                         one workgroup per level-lg subtree: its
 //                                     remaining iterations in LDS
@@ -291,8 +292,8 @@ __global__ __launch_bounds__(256) void k_ip_setup(const uint32_t* __restrict__ p
     }
 }
 
-// One LDS block (BLK entries) of one subtree of iteration l: SORT runs the
-// whole bitonic network of the block, MERGE the strides BLK/2 .. 1 of the
+// One LDS block (SBLK entries) of one subtree of iteration l: SORT runs the
+// whole bitonic network of the block, MERGE the strides SBLK/2 .. 1 of the
 // current stage.  The network runs on (key, slot) pairs in LDS; then every
 // thread reads the records its output positions receive (all reads before
 // any write) and stores them.
@@ -300,17 +301,17 @@ template <int K, bool I32, bool SORT>
 __global__ __launch_bounds__(256) void k_ip_block(uint32_t* __restrict__ pts, uint32_t* __restrict__ perm, uint32_t n,
                                                   uint32_t l, uint32_t dimrr, const uint8_t* segdim, uint32_t* hdr)
 {
-    constexpr uint32_t E = BLK / THREADS;
-    __shared__ uint64_t key[BLK];
-    __shared__ uint16_t slot[BLK];
+    constexpr uint32_t E = SBLK / THREADS;
+    __shared__ uint64_t key[SBLK];
+    __shared__ uint16_t slot[SBLK];
     const Level v = make_level(n, l);
-    const SegTiles t = tiles_level(v, BLK);
+    const SegTiles t = tiles_level(v, SBLK);
     uint32_t seg, u;
     tile_locate(t, blockIdx.x, seg, u);
     const uint32_t size = seg_size(v, seg);
-    const uint32_t base = io_begin(v, seg) + u * BLK;
-    const uint32_t cnt = umin(BLK, size - u * BLK);
-    if (u * BLK >= size || base + cnt > n) {
+    const uint32_t base = io_begin(v, seg) + u * SBLK;
+    const uint32_t cnt = umin(SBLK, size - u * SBLK);
+    if (u * SBLK >= size || base + cnt > n) {
         if (threadIdx.x == 0) atomicOr(&hdr[HDR_STATUS], KDT_STATUS_INTERNAL);
         return;
     }
@@ -320,10 +321,10 @@ __global__ __launch_bounds__(256) void k_ip_block(uint32_t* __restrict__ pts, ui
         slot[p] = (uint16_t)p;
     }
     __syncthreads();
-    for (uint32_t e = SORT ? 1u : BLK_LOG; e <= BLK_LOG; ++e) {
+    for (uint32_t e = SORT ? 1u : SBLK_LOG; e <= SBLK_LOG; ++e) {
         for (int ls = (int)e - 1; ls >= 0; --ls) {
             const bool mirrored = SORT && ls == (int)e - 1;
-            for (uint32_t q = threadIdx.x; q < BLK / 2; q += THREADS) {
+            for (uint32_t q = threadIdx.x; q < SBLK / 2; q += THREADS) {
                 uint32_t lo, hi;
                 if (mirrored)
                     mirror_pair(q, e, lo, hi);
@@ -360,33 +361,78 @@ __global__ __launch_bounds__(256) void k_ip_block(uint32_t* __restrict__ pts, ui
     }
 }
 
-// First step of stage S = 2^e of iteration l over global memory: entry w of
-// every S-block against entry S-1-w, inside every subtree (network length
-// 2^logP per subtree, entries past the subtree's end are +infinity).
-template <int K, bool I32>
-__global__ __launch_bounds__(256) void k_ip_mirror(uint32_t* __restrict__ pts, uint32_t* __restrict__ perm, uint32_t n,
+// The first c steps of stage e of iteration l over global memory: the
+// mirrored step (entry w of every 2^e-block against entry 2^e - 1 - w), then
+// half-cleaners of strides 2^(e-2) .. 2^(e-c), on two mirrored groups of 2^c
+// entries per thread (see mgroup_base).  The network runs on keys and slots;
+// the moved records are read, then written.
+template <int K, bool I32, int C>
+__global__ __launch_bounds__(256) void k_ip_mgroup(uint32_t* __restrict__ pts, uint32_t* __restrict__ perm, uint32_t n,
                                                    uint32_t l, uint32_t logP, uint32_t e, uint32_t dimrr,
                                                    const uint8_t* segdim)
 {
+    constexpr int G = 1 << C;
+    const uint32_t e0 = e - C;
     const Level v = make_level(n, l);
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (v.nseg << (logP - 1u))) return;
-    const uint32_t seg = g >> (logP - 1u);
-    uint32_t lo, hi;
-    mirror_pair(g & ((1u << (logP - 1u)) - 1u), e, lo, hi);
+    if (g >= (v.nseg << (logP - C - 1))) return;
+    const uint32_t seg = g >> (logP - C - 1);
+    const uint32_t ba = mgroup_base(g & ((1u << (logP - C - 1)) - 1u), e0, C);
+    const uint32_t bb = ba ^ ((1u << e0) - 1u);
     const uint32_t size = seg_size(v, seg);
-    if (hi >= size) return;
+    if (ba >= size) return;                 // both groups lie past the subtree's end
     const uint32_t base = io_begin(v, seg);
     const uint32_t d = seg_dim(segdim, dimrr, seg);
-    uint32_t a[K], b[K];
-    ld_pt<K>(pts, base + lo, a);
-    ld_pt<K>(pts, base + hi, b);
-    const uint32_t ia = perm[base + lo], ib = perm[base + hi];
-    if (rkey<I32>(pick<K>(a, d), ia) > rkey<I32>(pick<K>(b, d), ib)) {
-        st_pt<K>(pts, base + lo, b);
-        st_pt<K>(pts, base + hi, a);
-        perm[base + lo] = ib;
-        perm[base + hi] = ia;
+    uint64_t key[2 * G];
+    uint32_t slot[2 * G];
+#pragma unroll
+    for (int j = 0; j < 2 * G; ++j) {
+        const uint32_t r = group_pos(j < G ? ba : bb, (uint32_t)(j & (G - 1)), e0);
+        slot[j] = (uint32_t)j;
+        key[j] = ~0ull;                     // past the subtree's end: +infinity
+        if (r < size) key[j] = rkey<I32>(pts[(size_t)(base + r) * K + d], perm[base + r]);
+    }
+    auto cmpx = [&](int lo, int hi) {
+        if (key[lo] > key[hi]) {
+            const uint64_t tk = key[lo];
+            key[lo] = key[hi];
+            key[hi] = tk;
+            const uint32_t ts = slot[lo];
+            slot[lo] = slot[hi];
+            slot[hi] = ts;
+        }
+    };
+    // mirrored step: A[x] against B[G-1-x], the lower position first
+#pragma unroll
+    for (int x = 0; x < G; ++x) {
+        const int a = x, b = G + (G - 1 - x);
+        if (x >> (C - 1)) cmpx(b, a);
+        else cmpx(a, b);
+    }
+    // half-cleaners inside each group
+#pragma unroll
+    for (int sb = C - 2; sb >= 0; --sb) {
+#pragma unroll
+        for (int half = 0; half < 2 * G; half += G) {
+#pragma unroll
+            for (int p = 0; p < G / 2; ++p) {
+                const int x = ((p >> sb) << (sb + 1)) | (p & ((1 << sb) - 1));
+                cmpx(half + x, half + (x | (1 << sb)));
+            }
+        }
+    }
+    uint32_t rc[2 * G][K];
+#pragma unroll
+    for (int j = 0; j < 2 * G; ++j)
+        if (slot[j] != (uint32_t)j)
+            ld_pt<K>(pts, base + group_pos(slot[j] < (uint32_t)G ? ba : bb, slot[j] & (uint32_t)(G - 1), e0), rc[j]);
+#pragma unroll
+    for (int j = 0; j < 2 * G; ++j) {
+        if (slot[j] != (uint32_t)j) {
+            const uint32_t r = group_pos(j < G ? ba : bb, (uint32_t)(j & (G - 1)), e0);
+            st_pt<K>(pts, base + r, rc[j]);
+            perm[base + r] = (uint32_t)key[j];
+        }
     }
 }
 
@@ -716,7 +762,7 @@ struct Driver {
                 });
                 if (s) return s;
             }
-            const uint32_t nblk = tiles_level(v, BLK).tiles;
+            const uint32_t nblk = tiles_level(v, SBLK).tiles;
             const uint32_t logP = log2_exact(net_len(v));
             std::vector<Step> steps;
             plan_level_sort(logP, [&](const Step& x) { steps.push_back(x); });
@@ -728,12 +774,17 @@ struct Driver {
                         k_ip_block<K, I32, true><<<nblk, THREADS, 0, st>>>(c.pts, c.perm, n, l, dimrr, sd, hdr);
                     });
                     break;
-                case ST_MIRROR:
+                case ST_MGROUP: {
+                    const uint32_t nb = blocks_for((size_t)v.nseg << (logP - x.c - 1u));
                     s = launch_profiled(st, KIND_IP_MIRROR, pass, 0.0, [&] {
-                        k_ip_mirror<K, I32><<<blocks_for((size_t)v.nseg << (logP - 1u)), 256, 0, st>>>(
-                            c.pts, c.perm, n, l, logP, x.e, dimrr, sd);
+                        switch (x.c) {
+                        case 1: k_ip_mgroup<K, I32, 1><<<nb, 256, 0, st>>>(c.pts, c.perm, n, l, logP, x.e, dimrr, sd); break;
+                        case 2: k_ip_mgroup<K, I32, 2><<<nb, 256, 0, st>>>(c.pts, c.perm, n, l, logP, x.e, dimrr, sd); break;
+                        default: k_ip_mgroup<K, I32, 3><<<nb, 256, 0, st>>>(c.pts, c.perm, n, l, logP, x.e, dimrr, sd); break;
+                        }
                     });
                     break;
+                }
                 case ST_GROUP: {
                     const uint32_t nb = blocks_for((size_t)v.nseg << (logP - x.c));
                     s = launch_profiled(st, KIND_IP_GROUP, pass, 0.0, [&] {

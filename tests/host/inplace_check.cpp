@@ -158,11 +158,11 @@ static void cmpx(std::vector<uint64_t>& k, uint32_t lo, uint32_t hi)
 
 static void block_pass(std::vector<uint64_t>& k, uint32_t len, bool sort)
 {
-    for (uint32_t u = 0; u * BLK < len; ++u) {
-        const uint32_t base = u * BLK, cnt = std::min(BLK, len - base);
-        for (uint32_t e = sort ? 1u : BLK_LOG; e <= BLK_LOG; ++e)
+    for (uint32_t u = 0; u * SBLK < len; ++u) {
+        const uint32_t base = u * SBLK, cnt = std::min(SBLK, len - base);
+        for (uint32_t e = sort ? 1u : SBLK_LOG; e <= SBLK_LOG; ++e)
             for (int ls = (int)e - 1; ls >= 0; --ls)
-                for (uint32_t q = 0; q < BLK / 2; ++q) {
+                for (uint32_t q = 0; q < SBLK / 2; ++q) {
                     uint32_t lo, hi;
                     if (sort && ls == (int)e - 1)
                         mirror_pair(q, e, lo, hi);
@@ -182,15 +182,34 @@ static void check_sort(uint32_t len, uint32_t logP, std::mt19937_64& rng)
         switch (x.kind) {
         case ST_BLOCK_SORT: block_pass(k, len, true); break;
         case ST_BLOCK_MERGE: block_pass(k, len, false); break;
-        case ST_MIRROR:
-            for (uint32_t q = 0; q < (1u << (logP - 1)); ++q) {
-                uint32_t lo, hi;
-                mirror_pair(q, x.e, lo, hi);
-                if (hi < len) cmpx(k, lo, hi);
+        case ST_MGROUP: {
+            // the mirrored stride on two groups per thread, then half-cleaners inside each
+            CHECK(x.c >= 1 && x.c <= MGROUP_MAX && x.e0 == x.e - x.c && x.e0 >= SBLK_LOG, "mgroup step e=%u", x.e);
+            const uint32_t G = 1u << x.c;
+            for (uint32_t h = 0; h < (1u << (logP - x.c - 1)); ++h) {
+                const uint32_t ba = mgroup_base(h, x.e0, x.c), bb = ba ^ ((1u << x.e0) - 1u);
+                if (ba >= len) continue;
+                auto pos = [&](uint32_t j) { return group_pos(j < G ? ba : bb, j & (G - 1), x.e0); };
+                auto cx = [&](uint32_t a, uint32_t b) {
+                    if (pos(b) < len) cmpx(k, pos(a), pos(b));
+                };
+                for (uint32_t xx = 0; xx < G; ++xx) {
+                    const uint32_t a = xx, b = G + (G - 1 - xx);
+                    CHECK(pos(a) + pos(b) + 1 == 2 * ((pos(a) >> x.e) << x.e) + (1u << x.e), "mirror pair e=%u", x.e);
+                    if (xx >> (x.c - 1)) cx(b, a);
+                    else cx(a, b);
+                }
+                for (int sb = (int)x.c - 2; sb >= 0; --sb)
+                    for (uint32_t half = 0; half < 2 * G; half += G)
+                        for (uint32_t p = 0; p < G / 2; ++p) {
+                            const uint32_t xx = ((p >> sb) << (sb + 1)) | (p & ((1u << sb) - 1));
+                            cx(half + xx, half + (xx | (1u << sb)));
+                        }
             }
             break;
+        }
         default: {
-            CHECK(x.c >= 1 && x.c <= GROUP_MAX && x.e0 >= BLK_LOG && x.e0 + x.c <= x.e - 1, "group step e=%u", x.e);
+            CHECK(x.c >= 1 && x.c <= GROUP_MAX && x.e0 >= SBLK_LOG && x.e0 + x.c <= x.e - 1, "group step e=%u", x.e);
             for (uint32_t h = 0; h < (1u << (logP - x.c)); ++h) {
                 const uint32_t gb = group_base(h, x.e0, x.c);
                 if (gb >= len) continue;
@@ -209,6 +228,21 @@ static void check_sort(uint32_t len, uint32_t logP, std::mt19937_64& rng)
 
 static void check_groups()
 {
+    // mirrored group pairs: every position exactly once over both groups of every pair
+    for (uint32_t logP = 3; logP <= 16; ++logP)
+        for (uint32_t c = 1; c <= MGROUP_MAX; ++c)
+            for (uint32_t e0 = 1; e0 + c <= logP; ++e0) {
+                std::vector<uint8_t> seen(1u << logP, 0);
+                for (uint32_t h = 0; h < (1u << (logP - c - 1)); ++h) {
+                    const uint32_t ba = mgroup_base(h, e0, c), bb = ba ^ ((1u << e0) - 1u);
+                    for (uint32_t x = 0; x < (1u << c); ++x)
+                        for (uint32_t b : {ba, bb}) {
+                            const uint32_t r = group_pos(b, x, e0);
+                            CHECK(r < (1u << logP) && !seen[r], "mgroup positions logP=%u c=%u e0=%u", logP, c, e0);
+                            if (r < (1u << logP)) seen[r] = 1;
+                        }
+                }
+            }
     for (uint32_t logP = 2; logP <= 16; ++logP)
         for (uint32_t c = 1; c <= GROUP_MAX && c <= logP; ++c)
             for (uint32_t e0 = 0; e0 + c <= logP; ++e0) {
@@ -247,8 +281,8 @@ int main()
             const uint32_t st = 1u << ls;
             CHECK(lo == (q / st) * 2 * st + q % st && hi == lo + st, "half_pair q=%u ls=%u", q, ls);
         }
-    for (uint32_t len : {1u, 2u, 3u, 100u, 2047u, 2048u, 2049u, 3000u, 4095u, 4096u, 4097u, 8191u, 9000u, 16384u,
-                         20000u, 40000u, 65536u, 70001u})
+    for (uint32_t len : {1u, 2u, 3u, 100u, 2047u, 2048u, 2049u, 3000u, 4095u, 4096u, 4097u, 8191u, 8192u, 8193u,
+                         9000u, 16384u, 20000u, 40000u, 65536u, 70001u, 131073u})
         check_sort(len, log2_exact(ceil_pow2(len)), rng);
     for (int it = 0; it < 10; ++it) {
         const uint32_t len = 1 + (uint32_t)(rng() % 100000);
