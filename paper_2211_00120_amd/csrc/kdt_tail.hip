@@ -454,13 +454,24 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             for (int ww = 0; ww < NW; ++ww) ub.cnt[ww][q] = 0;
         }
         __syncthreads();
+        // split-widest: do all segments of this iteration split in one
+        // dimension (then the walk list is that dimension's order itself)?
+        uint32_t dall = 0;
+        bool uni = false;
+        if (WIDEST) {
+            dall = segdim[cur][0];
+            int diff = 0;
+            for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) diff |= segdim[cur][q] != dall;
+            uni = !__syncthreads_or(diff);
+        }
         // position of each point inside its segment in the order of the
         // segment's split dimension: a walk over a list in which each
         // segment's points appear in that order -- ord_d itself for round
-        // robin; for split-widest, the concatenation over d of the slots of
+        // robin and for split-widest iterations whose segments all split in
+        // one dimension; otherwise the concatenation over d of the slots of
         // the segments split in d, each part in ord_d order
         uint32_t M = m;
-        if (WIDEST) {
+        if (WIDEST && !uni) {
             // one read of every (dimension, slot), kept for the write-out
             uint32_t le[K][ITEMS];
             uint64_t lb[K][ITEMS];
@@ -499,14 +510,14 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             __syncthreads();
         }
         {
-            const uint32_t d = l % (uint32_t)K;     // round robin's split dimension
+            const uint32_t d = WIDEST ? dall : l % (uint32_t)K;     // the split dimension of every segment
             uint32_t e[ITEMS], q[ITEMS];
             bool valid[ITEMS];
             uint64_t peers[ITEMS];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                e[i] = p < M ? (uint32_t)(WIDEST ? wl[p] : ord[d][p]) : 0u;
+                e[i] = p < M ? (uint32_t)((WIDEST && !uni) ? wl[p] : ord[d][p]) : 0u;
             }
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {

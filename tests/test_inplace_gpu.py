@@ -9,6 +9,7 @@ the LDS-only path (n < 2048), the first levels that need global passes
 (2048 .. a few blocks), several global stages and the partial blocks of the
 final unshuffles, both coordinate types, all k and both split rules.
 """
+import os
 import sys
 
 import numpy as np
@@ -127,6 +128,20 @@ def test_inplace_10m(kind):
     tree, perm, dim, status = _inplace(pts, mode)
     assert status == kdt.OK
     code, node = oracle.check(pts, perm, dim, _omode(mode))
+    assert code == 0, f"checker code {code} at node {node}"
+    assert tree.tobytes() == np.ascontiguousarray(pts[perm]).tobytes()
+
+
+@pytest.mark.skipif(os.environ.get("KDT_SKIP_100M") == "1", reason="100M case disabled by KDT_SKIP_100M")
+def test_inplace_cluster_100m_widest():
+    """The benchmark's 100M split-widest workload through the in-place build:
+    the oracle's checker on every node and the overwritten points against the
+    input in perm order."""
+    pts = workloads.cfg_cluster4d()
+    _say("case inplace cluster100m (checker)")
+    tree, perm, dim, status = _inplace(pts, kdt.WIDEST)
+    assert status == kdt.OK
+    code, node = oracle.check(pts, perm, dim, oracle.WIDEST)
     assert code == 0, f"checker code {code} at node {node}"
     assert tree.tobytes() == np.ascontiguousarray(pts[perm]).tobytes()
 
