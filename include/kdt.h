@@ -78,10 +78,12 @@ size_t kdt_workspace_bytes(uint32_t n, uint32_t k, int dim_mode);
 /*
  * Build the tree of d_points into caller-provided outputs.
  *
- *   d_points   n*k float32, read only; must not overlap any output.
+ *   d_points   n*k float32, read only; must not overlap any output;
+ *              16-byte aligned for k = 4, 8-byte for k = 2, 4-byte
+ *              otherwise (rows move as whole vectors; KDT_EINVAL if not).
  *   n, k       point count (0..KDT_MAX_POINTS) and dimension (1..4).
  *   dim_mode   KDT_DIM_ROUND_ROBIN or KDT_DIM_WIDEST.
- *   d_tree     nullable; n*k float32: d_tree[s*k + d] = coordinate d of the
+ *   d_tree     nullable; n*k float32, aligned as d_points; d_tree[s*k + d] = coordinate d of the
  *              point stored at level-order node s.
  *   d_perm     nullable; n uint32: original index of the point at node s.
  *   d_dim      nullable; n uint8: split dimension of node s (round robin:
@@ -166,7 +168,8 @@ kdt_status kdt_build_inplace_i32(int32_t* d_points, uint32_t n, uint32_t k, int 
  * the tree in level order.  The library keeps one cached workspace per
  * (device, stream) pair, allocated on first use and grown when needed, so
  * this entry point may allocate.  Non-finite input is not reported (use
- * kdt_build_ws with a status word for that).
+ * kdt_build_ws with a status word for that).  d_points is aligned as for
+ * kdt_build_ws.
  */
 kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode,
                      hipStream_t stream);
@@ -175,7 +178,7 @@ kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode,
  * Batched build: C independent trees (one per cloud) in one call.
  *
  * Cloud c is the points [h_offsets[c], h_offsets[c+1]) of d_points (row-major
- * float32, k per point); its tree, permutation and dimensions go to the same
+ * float32, k per point; d_points and d_tree aligned as for kdt_build_ws); its tree, permutation and dimensions go to the same
  * entry range of d_tree / d_perm / d_dim, exactly as kdt_build_ws would write
  * them for that cloud alone (d_perm holds indices local to the cloud).  All
  * clouds share k and dim_mode.  The build is the same sequence of iterations

@@ -189,6 +189,18 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb)
     return x < y + nb && y < x + na;
 }
 
+// Points and tree rows move as whole 16-byte (k = 4) or 8-byte (k = 2)
+// vectors, so those arrays must be aligned to that.
+kdt_status validate_row_align(uint32_t k, const void* pts, const void* tree)
+{
+    const uintptr_t a = k == 4 ? 16 : k == 2 ? 8 : 4;
+    if (((uintptr_t)pts | (uintptr_t)tree) % a) {
+        set_err("points and tree must be %zu-byte aligned for k = %u", (size_t)a, k);
+        return KDT_EINVAL;
+    }
+    return KDT_OK;
+}
+
 // Checks shared by the caller-workspace entry points.
 kdt_status validate_buffers(const Plan& p, const float* pts, float* tree, uint32_t* perm, uint8_t* dim,
                             uint32_t* status, void* ws, size_t ws_bytes)
@@ -205,6 +217,7 @@ kdt_status validate_buffers(const Plan& p, const float* pts, float* tree, uint32
         set_err("workspace must be %zu-byte aligned", ALIGN);
         return KDT_EINVAL;
     }
+    if (kdt_status s = validate_row_align(p.k, pts, tree)) return s;
     const size_t n = p.ntotal;
     const size_t pb = n * p.k * 4;
     if (overlaps(pts, pb, tree, pb) || overlaps(pts, pb, perm, n * 4) || overlaps(pts, pb, dim, n) ||
@@ -809,6 +822,7 @@ kdt_status kdt_build(float* d_points, uint32_t n, uint32_t k, int dim_mode, hipS
         set_err("points is null or n exceeds KDT_MAX_POINTS");
         return KDT_EINVAL;
     }
+    if (kdt_status s = validate_row_align(k, d_points, nullptr)) return s;
     if (n == 0) return KDT_OK;
     const Plan p = make_plan(std::vector<uint32_t>{n}, k, dim_mode == KDT_DIM_WIDEST);
     const size_t pb = align_up((size_t)n * k * 4);

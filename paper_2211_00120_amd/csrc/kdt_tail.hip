@@ -56,6 +56,9 @@ __device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, c
         hi[d] = rootbox[r][4 + d];
     }
     uint32_t qq = q;
+    // the steps' LDS reads do not depend on each other: unrolled, they are
+    // issued together instead of one round trip per ancestor
+#pragma unroll 4
     for (uint32_t tt = t; tt > 0; --tt) {
         const uint32_t pq = qq >> 1;
         const uint32_t idx = gc * ((1u << (tt - 1u)) - 1u) + pq;
@@ -256,6 +259,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             uint16_t ts[C];                        // their slots
         } bsort;
         uint16_t cnt[NW][C];                       // per-(wave, segment) counters of an iteration
+        uint32_t stage[4 * C];                     // write-out: coordinates by local node
     } ub;
     __shared__ uint32_t sh[NW];
     __shared__ uint32_t red[4];
@@ -305,6 +309,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     uint4 rec[ITEMS];                              // per-dimension sort keys of each slot
     uint32_t idx[ITEMS];                           // original (local) index of each slot
     float4 pc[ITEMS];                              // coordinates of each slot's point
+    uint32_t lid[ITEMS];                           // local node of each slot, once placed (see the write-out)
     bool ok[ITEMS];
     bool bad = false;
 #pragma unroll
@@ -570,8 +575,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             const uint32_t gq = (i0 << t) + q;
             const uint32_t ls = seg_left_size(vl, gq);
             if (wr == ls) {
-                const uint32_t sn = vl.Fl + gq;
-                place_pt<K, WIDEST>(o, ti, sn, idx[i], pc[i]);
+                lid[i] = gc * ((1u << t) - 1u) + q;
                 if (WIDEST) {
                     // the node's dimension and plane; its children follow
                     // below, one thread per segment
@@ -584,7 +588,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             } else {
                 const uint32_t side = wr > ls ? 1u : 0u;
                 if (last) {
-                    place_pt<K, WIDEST>(o, ti, vl.Fl + vl.nseg + 2u * gq + side, idx[i], pc[i]);
+                    lid[i] = gc * ((2u << t) - 1u) + 2u * q + side;
                     seg[e] = (uint16_t)DONE;
                 } else {
                     seg[e] = (uint16_t)(2u * q + side);
@@ -625,6 +629,46 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             // the next iteration reads segdim after its first barrier
         }
         cur ^= 1u;
+    }
+
+    // ---- write-out (Sec. 3.2's placement, made coalesced): local node id
+    // p numbers the group's nodes level by level, gc * (2^t - 1) + j for the
+    // j-th node of local level t, whose global node is F(l0 + t) + i0 * 2^t
+    // + j; the last level holds only its existing nodes, so the ids of the m
+    // slots are exactly 0 .. m-1.  The slots' points and indices go to LDS
+    // by id, then every thread writes consecutive nodes of each level ----
+    if (l0 + 2u <= L) {
+        // ub and tmp/seg were last read before the final iteration's update
+        // barrier; the domain step after it touches neither
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (!ok[i]) continue;
+            const uint32_t q = lid[i];
+            const float cf[4] = {pc[i].x, pc[i].y, pc[i].z, pc[i].w};
+#pragma unroll
+            for (int d = 0; d < K; ++d) ub.stage[(uint32_t)d * C + q] = __float_as_uint(cf[d]);
+            tmp[q] = (uint16_t)(idx[i] & 0xFFFFu);
+            seg[q] = (uint16_t)(idx[i] >> 16);
+        }
+        __syncthreads();
+        for (uint32_t p = threadIdx.x; p < m; p += TAIL_THREADS) {
+            const uint32_t t = 31u - (uint32_t)__builtin_clz(p / gc + 1u);
+            const uint32_t node = full_nodes(l0 + t) + (i0 << t) + (p - gc * ((1u << t) - 1u));
+            if (!in_bounds(node, ti.n, o.status)) continue;
+            const size_t at = off + node;
+            if (o.tree) {
+                float* tp = o.tree + at * K;
+                if constexpr (K == 4)
+                    *reinterpret_cast<float4*>(tp) =
+                        make_float4(__uint_as_float(ub.stage[p]), __uint_as_float(ub.stage[C + p]),
+                                    __uint_as_float(ub.stage[2u * C + p]), __uint_as_float(ub.stage[3u * C + p]));
+                else
+#pragma unroll
+                    for (int d = 0; d < K; ++d) tp[d] = __uint_as_float(ub.stage[(uint32_t)d * C + p]);
+            }
+            o.nodeperm[at] = (uint32_t)tmp[p] | ((uint32_t)seg[p] << 16);
+            if (!WIDEST && o.dim) o.dim[at] = (uint8_t)((l0 + t) % (uint32_t)K);
+        }
     }
 }
 

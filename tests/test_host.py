@@ -71,6 +71,16 @@ def test_argument_errors_are_synchronous():
         == kdt.EINVAL
     assert lib.kdt_build(None, 10, 3, 0, None) == kdt.EINVAL
     assert lib.kdt_build(fake, 10, 9, 0, None) == kdt.EINVAL
+    # rows move as whole vectors: k = 4 needs 16-byte, k = 2 8-byte alignment
+    need4 = lib.kdt_workspace_bytes(10, 4, 0)
+    assert lib.kdt_build_ws(ctypes.c_void_p(0x1008), 10, 4, 0, None, None, None, None, ws, need4, None) \
+        == kdt.EINVAL
+    assert "aligned" in kdt.last_error()
+    assert lib.kdt_build_ws(fake, 10, 4, 0, ctypes.c_void_p(0x20004), None, None, None, ws, need4, None) \
+        == kdt.EINVAL
+    assert lib.kdt_build_ws(ctypes.c_void_p(0x1004), 10, 2, 0, None, None, None, None, ws, need4, None) \
+        == kdt.EINVAL
+    assert lib.kdt_build(ctypes.c_void_p(0x1008), 10, 4, 0, None) == kdt.EINVAL
 
 
 def test_status_strings():
