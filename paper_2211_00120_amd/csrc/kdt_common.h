@@ -224,13 +224,10 @@ __device__ __forceinline__ void set4(uint4& r, uint32_t d, uint32_t v)
 // `bits` bits of value (bits <= 16; one ballot per bit).
 __device__ __forceinline__ uint64_t match_bits(uint32_t value, uint32_t bits, bool valid)
 {
-    uint64_t peers = __ballot(valid);
-    for (uint32_t b = 0; b < bits; ++b) {
-        const bool bit = (value >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    return peers;
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    for (uint32_t b = 0; b < bits; ++b) match_bit(~value, b, lo, hi);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)

@@ -27,17 +27,27 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // A value every lane of the wave holds alike, moved to a scalar register.
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// One bit of a lane-set match: keeps in (lo, hi) -- the two halves of a
+// wave64 lane mask -- the lanes whose bit b of v equals this lane's; nv is
+// ~v.  With nm = (this lane's bit ? 0 : ~0) the kept set is (ballot ^ nm),
+// so a bit costs a shift, a compare and two three-input logic operations
+// (no per-lane select between the ballot and its complement).
+__device__ __forceinline__ void match_bit(uint32_t nv, uint32_t b, uint32_t& lo, uint32_t& hi)
+{
+    const uint32_t nm = (uint32_t)((int32_t)(nv << (31u - b)) >> 31);
+    const uint64_t bal = __ballot(nm == 0u);
+    lo &= (uint32_t)bal ^ nm;
+    hi &= (uint32_t)(bal >> 32) ^ nm;
+}
+
 // Lanes of this wave whose (valid, digit) equal this lane's: 8 ballots.
 __device__ __forceinline__ uint64_t match_digit(uint32_t digit, bool valid)
 {
-    uint64_t peers = __ballot(valid);
+    const uint64_t v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
-    for (int b = 0; b < (int)DIGIT_BITS; ++b) {
-        const bool bit = (digit >> b) & 1u;
-        const uint64_t bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
-    }
-    return peers;
+    for (int b = 0; b < (int)DIGIT_BITS; ++b) match_bit(~digit, (uint32_t)b, lo, hi);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Number of set bits of m in lanes below this one.

@@ -213,13 +213,11 @@ __device__ __forceinline__ void wave_multisplit16(const uint32_t (&digit)[ITEMS]
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         if (i >= active) break;
-        uint64_t peers = __ballot(valid[i]);
+        const uint64_t v = __ballot(valid[i]);
+        uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
-        for (int b = 0; b < RB; ++b) {
-            const bool bit = (digit[i] >> b) & 1u;
-            const uint64_t bal = __ballot(bit);
-            peers &= bit ? bal : ~bal;
-        }
+        for (int b = 0; b < RB; ++b) match_bit(~digit[i], (uint32_t)b, lo, hi);
+        const uint64_t peers = ((uint64_t)hi << 32) | lo;
         const uint32_t below = count_below(peers);
         uint32_t base = 0;
         if (valid[i]) base = wh[digit[i]];

@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             const uint32_t d = WIDEST ? dall : l % (uint32_t)K;     // the split dimension of every segment
             uint32_t e[ITEMS], q[ITEMS];
             bool valid[ITEMS];
-            uint64_t peers[ITEMS];
+            uint32_t plo[ITEMS], phi[ITEMS];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
@@ -532,22 +532,21 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 valid[i] = q[i] != DONE;
-                peers[i] = __ballot(valid[i]);
+                const uint64_t v = __ballot(valid[i]);
+                plo[i] = (uint32_t)v;
+                phi[i] = (uint32_t)(v >> 32);
             }
             for (uint32_t b = 0; b < gbits; ++b) {
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const bool bit = (q[i] >> b) & 1u;
-                    const uint64_t bal = __ballot(bit);
-                    peers[i] &= bit ? bal : ~bal;
-                }
+                for (int i = 0; i < ITEMS; ++i) match_bit(~q[i], b, plo[i], phi[i]);
             }
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                const uint32_t below = count_below(peers[i]);
+                const uint64_t peers = ((uint64_t)phi[i] << 32) | plo[i];
+                const uint32_t below = count_below(peers);
                 uint32_t base = 0;
                 if (valid[i]) base = ub.cnt[w][q[i]];
-                if (valid[i] && below == 0) ub.cnt[w][q[i]] = (uint16_t)(base + (uint32_t)__popcll(peers[i]));
+                if (valid[i] && below == 0) ub.cnt[w][q[i]] = (uint16_t)(base + (uint32_t)__popcll(peers));
                 if (valid[i]) tmp[e[i]] = (uint16_t)((w << 12) | (base + below));
             }
         }
