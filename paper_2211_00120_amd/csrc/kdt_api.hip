@@ -101,9 +101,9 @@ kdt_status check_launch(const char* what)
 // such work and count 0.
 const char* const kind_names[KIND_COUNT] = {"k_init", "k_prep", "k_root_dim", "k_presort_pass",
                                             "k_level0", "k_level_select", "k_level_pivot", "k_level_part",
-                                            "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_pack",
-                                            "k_rank_bucket", "k_rank_window", "k_ip_init", "k_ip_setup",
-                                            "k_ip_block", "k_ip_mgroup", "k_ip_group", "k_ip_deep", "k_ip_perm"};
+                                            "k_tail", "k_tail_whole", "share_tables", "k_word", "k_rank_bucket",
+                                            "k_rank_window", "k_ip_init", "k_ip_setup", "k_ip_block", "k_ip_mgroup",
+                                            "k_ip_group", "k_ip_deep", "k_ip_perm"};
 
 struct ProfRec {
     int kind;
@@ -358,34 +358,40 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 }))
                 return s;
 
-        // presort: per dimension, 4 stable digit passes of (key, index); the
-        // (key, index) ping-pongs live in the record region (>= 4 *
-        // presort_group * ntotal words), which is free until iteration 0.  A pass whose
-        // digit is the same in all keys of a tree is skipped for that tree;
-        // for the profile's byte counts, the key summaries are read back
-        // (profiling builds only)
+        // presort: per presort role (the root's dimension first, then the
+        // others, see PresortArgs), 4 stable digit passes of (key, payload);
+        // the (key, payload) ping-pongs live in the record region (>= 4 *
+        // presort_group * ntotal words), which is free until iteration 0.  A
+        // pass whose digit is the same in all keys of a tree is skipped for
+        // that tree; for the profile's byte counts, the key summaries (and
+        // the split-widest root dimensions) are read back (profiling builds
+        // only)
         std::vector<uint32_t> keysum;
+        std::vector<uint8_t> rootdim(nlarge_trees, 0u);
         if (g_prof.on) {
             keysum.resize((size_t)nlarge_trees * KEYSUM_WORDS);
             HIP_TRY(hipMemcpyAsync(keysum.data(), o.bbox, keysum.size() * 4, hipMemcpyDeviceToHost, st));
+            if (widest)
+                for (uint32_t i = 0; i < nlarge_trees; ++i)
+                    HIP_TRY(hipMemcpyAsync(&rootdim[i], o.dimnode + p.trees[p.large[i]].off, 1,
+                                           hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
         }
-        // the plan's launches, each over a group of dimensions, each dimension
-        // with its own ping-pong (the group's slot j: words [4j, 4j+4) *
-        // ntotal of the record region; a launch of one dimension of a group
-        // takes that dimension's slot)
+        // the plan's launches, each over a group of roles, the group's role j
+        // with its own ping-pong (slot j: words [4j, 4j+4) * ntotal of the
+        // record region)
         uint32_t q = 0;
         for (const Plan::PresortLaunch& pl : p.presort_launches) {
-            const uint32_t d0 = pl.dim0, nd = pl.ndims, ps = pl.pass;
+            const uint32_t r0 = pl.role0, nd = pl.ndims, ps = pl.pass;
             {
                 PresortArgs a{};
                 a.sh = shares(p, p.presort, p.t_presort, ws);
                 a.keys = keys;
                 a.kv_words = 2 * (size_t)ntotal;
-                a.kv = recbase + 2 * (size_t)(d0 % p.presort_group) * a.kv_words;
+                a.kv = recbase;
                 a.keysum = o.bbox;
                 a.pass = ps;
-                a.dim0 = d0;
+                a.role0 = r0;
                 a.ndims = nd;
                 a.hist = hist_rank;
                 a.hist_stride = k * 4 * RADIX_HOST;
@@ -399,10 +405,10 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     a.xq_cnt = counters + MAX_PASSES + 8 * (size_t)(&pl - p.presort_launches.data());
                 }
                 a.perms = perms;
-                // per-dimension arrays are written by the windowed scatter below
+                // per-role arrays are written by the windowed scatter below
                 a.rank_table = p.rank_dm ? nullptr : ranks;
-                a.rank_stride = p.rank_dm ? 1u : k;
-                a.rank_dstride = p.rank_dm ? (size_t)ntotal : 1u;
+                a.root_ranks = p.rank_dm ? ranks : nullptr;    // role 0's array
+                a.k = k;
                 a.dimnode = widest ? o.dimnode : nullptr;
                 a.ntotal = ntotal;
                 a.status = dstatus;
@@ -410,15 +416,18 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 a.o = o;
                 double bytes = 0;
                 if (g_prof.on) {
-                    for (uint32_t d = d0; d < d0 + nd; ++d)
+                    for (uint32_t r = r0; r < r0 + nd; ++r)
                         for (uint32_t i = 0; i < nlarge_trees; ++i) {
+                            const uint32_t d = role_dim(r, rootdim[i]);
                             const uint32_t vary =
                                 keysum[i * KEYSUM_WORDS + 8 + d] ^ keysum[i * KEYSUM_WORDS + 12 + d];
                             auto runs = [&](uint32_t qq) { return ((vary >> (8 * qq)) & 0xFFu) != 0u; };
                             if (ps < 3 && !runs(ps)) continue;
                             bool first = true;
                             for (uint32_t qq = 0; qq < ps; ++qq) first = first && !runs(qq);
-                            bytes += p.trees[p.large[i]].n * (first ? 12.0 : 16.0);
+                            // a first pass reads the key (and, but for the root's
+                            // role, the payload), a later one the pair
+                            bytes += p.trees[p.large[i]].n * (first ? (r && p.rank_dm ? 16.0 : 12.0) : 16.0);
                         }
                 }
                 // with k = 1 the last pass places the trees: it completes
@@ -430,19 +439,16 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             }
             ++q;
             if (p.rank_dm && ps == 3 && k > 1) {
-                // the dimensions' ranks into their arrays, window by window;
-                // the buckets take the ping-pong of the dimension just sorted
-                for (uint32_t d = d0; d < d0 + nd; ++d) {
-                    if (!widest && d == 0) continue;   // every tree's root dimension: no ranks needed
+                // the roles' ranks into their arrays, window by window; the
+                // buckets take the ping-pong of the role just sorted
+                for (uint32_t r = r0; r < r0 + nd; ++r) {
                     RankBucketArgs b{};
                     b.sh = shares(p, p.presort, p.t_presort, ws);
-                    b.perm = perms + (size_t)d * ntotal;
-                    b.pairs = recbase + 4 * (size_t)(d % p.presort_group) * ntotal;
-                    b.wcount = wcount + (size_t)d * RANK_MAX_WIN;
+                    b.perm = perms + (size_t)r * ntotal;
+                    b.pairs = recbase + 4 * (size_t)(r - r0) * ntotal;
+                    b.wcount = wcount + (size_t)r * RANK_MAX_WIN;
                     b.wbits = p.rank_wbits;
                     b.nwin = p.rank_nwin;
-                    b.dimnode = widest ? o.dimnode : nullptr;
-                    b.dim = d;
                     b.status = dstatus;
                     if (kdt_status s = run_kernel(st, KIND_BUCKET, nlarge * 12.0, 0.0,
                                                   [&] { launch_rank_bucket(b, p.presort_tiles, st); }))
@@ -450,7 +456,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                     RankWindowArgs wa{};
                     wa.pairs = b.pairs;
                     wa.wcount = b.wcount;
-                    wa.dm = ranks + (size_t)d * ntotal;
+                    wa.dm = ranks + (size_t)r * ntotal;
                     wa.wbits = p.rank_wbits;
                     wa.nwin = p.rank_nwin;
                     wa.chunks = std::max(1u, (1u << p.rank_wbits) / RANK_WIN_CHUNK);
@@ -470,24 +476,17 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
             return KDT_OK;
         }
 
-        // per-dimension ranks -> point-major records in rec[1], which is free
-        // until iteration 1 writes it
-        uint32_t* rank_table = ranks;
-        if (p.rank_dm) {
-            rank_table = rec[1];
-            if (kdt_status s = run_kernel(st, KIND_PACK, ntotal * 8.0 * K, 0.0,
-                                          [&] { launch_rank_pack((int)k, ranks, rank_table, ntotal, st); }))
-                return s;
-        }
-
-        // iteration 0 writes the records of iteration 1 into rec[0]
+        // iteration 0 reads the ranks (per-role arrays: by root position,
+        // streaming; point-major table: by index) and writes the records of
+        // iteration 1 into rec[0]
         int cur = 0;
         {
             const bool keys1 = !p.levels.empty() && !p.levels[0].sorted;
             Level0Args a{};
             a.sh = shares(p, p.level0, p.t_level0, ws);
             a.perms = perms;
-            a.rank_table = rank_table;
+            a.rank_table = p.rank_dm ? nullptr : ranks;
+            a.role_ranks = p.rank_dm ? ranks : nullptr;
             a.rout = rec[cur];
             a.kout = skey[0];
             a.hist = hist;
@@ -533,6 +532,7 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
                 pa.hist = hist;
                 pa.piv = piv;
                 pa.perms = perms;
+                pa.root_payload = p.rank_dm ? 1u : 0u;
                 pa.ntotal = ntotal;
                 pa.passes = p.P;
                 pa.radix_bits = p.RB;

@@ -21,7 +21,7 @@ kdt_status enqueue_plan(const Plan& p, const float* pts, float* tree, uint32_t* 
 
 // Kernels as the profiler (kdt_profile_collect) names them.
 enum Kind { KIND_INIT, KIND_PREP, KIND_ROOT, KIND_PRESORT, KIND_LEVEL0, KIND_SELECT, KIND_PIVOT, KIND_PART,
-            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_PACK, KIND_BUCKET, KIND_WINDOW,
+            KIND_TAIL, KIND_WHOLE, KIND_TABLES, KIND_STATUS, KIND_BUCKET, KIND_WINDOW,
             KIND_IP_INIT, KIND_IP_SETUP, KIND_IP_BLOCK, KIND_IP_MIRROR, KIND_IP_GROUP, KIND_IP_DEEP, KIND_IP_PERM,
             KIND_COUNT };
 

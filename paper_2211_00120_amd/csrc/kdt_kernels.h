@@ -63,7 +63,7 @@ struct PresortArgs {
     size_t kv_words;
     const uint32_t* keysum; // per tree key summaries
     uint32_t pass;
-    uint32_t dim0, ndims;   // the launch sorts dimensions dim0 .. dim0+ndims-1, tiles interleaved
+    uint32_t role0, ndims;  // the launch sorts roles role0 .. role0+ndims-1 (role_dim), tiles interleaved
     const uint32_t* hist;   // per tree digit histograms: hist + idx*hist_stride + (d*4 + pass)*RADIX
     uint32_t hist_stride;
     uint32_t* lb;           // look-back words of this pass, dimension slot j at lb + j*lb_dim_words
@@ -73,13 +73,17 @@ struct PresortArgs {
     uint32_t* counter;      // dynamic tile counter of this pass
     const uint32_t* xq;     // per-XCD tile queues (null: take tiles from `counter`)
     uint32_t* xq_cnt;       // the 8 queue counters of this launch
-    uint32_t* perms;        // last pass: per tree rank -> local index, [d*ntotal + off + rank]
-    uint32_t* rank_table;   // last pass: ranks at [(off + i)*rank_stride + d*rank_dstride], except each tree's
-                            // root dimension: point-major (k, 1) or per-dimension arrays (1, ntotal); null when
-                            // the per-dimension arrays are written by k_rank_bucket / k_rank_window instead
+    uint32_t* perms;        // last pass: per tree and role the sorted payloads, [role*ntotal + off + rank]
+    // Payloads: each point's local index; or, with root_ranks, for every
+    // role but the root's the point's root rank (its position in the root
+    // dimension's order, read in the role's first pass from root_ranks), so
+    // that the role's ranks land at root positions.
+    uint32_t* rank_table;   // point-major layout: last pass writes [(off + index)*k + dim] = rank for every
+                            // role but the root's; null in the per-role layout (k_rank_bucket / k_rank_window
+                            // write the ranks)
+    const uint32_t* root_ranks;   // per-role layout: role 0's array, root rank by local index [off + i]; else null
     const uint8_t* dimnode; // split-widest: node dims (the root's is tree's first entry); null: root dimension 0
-    uint32_t rank_stride;
-    size_t rank_dstride;
+    uint32_t k;
     uint32_t ntotal;
     uint32_t* status;
     // k = 1: the last pass places every tree (its sorted order is the tree's
@@ -91,8 +95,10 @@ struct PresortArgs {
 struct Level0Args {
     Shares sh;              // one share per tree, tiles of PREP_TILE ranks
     const uint32_t* xmap;   // null, or per workgroup its tile (0xFFFFFFFF: none), trees grouped by XCD
-    const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
-    const uint32_t* rank_table;   // point-major rank records, [(off + i)*k + d]
+    const uint32_t* perms;  // presort outputs, [role*ntotal + off + rank]; role 0: root order -> local index
+    const uint32_t* rank_table;   // point-major layout: records by local index, [(off + i)*k + d] (gathered)
+    const uint32_t* role_ranks;   // per-role layout: rank of the point at root position r in role j's dimension,
+                                  // [j*ntotal + off + r] (j >= 1, streamed); null in the point-major layout
     uint32_t* rout;         // iteration-1 records
     uint32_t* kout;         // iteration-1 split keys (share.hist_next != NO_HIST and keys_next)
     uint32_t* hist;         // base of the iteration-1 histograms (share.hist_next offsets)
@@ -128,7 +134,8 @@ struct LevelPivotArgs {
     const uint32_t* rin;    // records (the pivot record of segments split in the root's dimension)
     const uint32_t* hist;   // histogram region; share.hist word offsets
     uint32_t* piv;
-    const uint32_t* perms;  // presort outputs, [d*ntotal + off + rank]
+    const uint32_t* perms;  // presort outputs, [role*ntotal + off + rank] (see PresortArgs)
+    uint32_t root_payload;  // the roles but the root's carry root ranks (per-role layout): two lookups
     uint32_t ntotal;
     uint32_t passes, radix_bits;
     uint32_t sorted;
@@ -185,19 +192,17 @@ void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStr
 
 struct RankBucketArgs {
     Shares sh;              // presort shares: tiles of PRESORT_TILE ranks per tree
-    const uint32_t* perm;   // this dimension's rank -> local index, [off + rank]
-    uint32_t* pairs;        // bucket w: uint2 (global index, rank) at [(w << wbits) + e]
+    const uint32_t* perm;   // this role's rank -> payload (local index or root position), [off + rank]
+    uint32_t* pairs;        // bucket w: uint2 (global payload, rank) at [(w << wbits) + e]
     uint32_t* wcount;       // pairs in each bucket (zero before the launch)
     uint32_t wbits, nwin;
-    const uint8_t* dimnode; // split-widest: a tree's root dimension is dimnode[off]; null: 0
-    uint32_t dim;
     uint32_t* status;
 };
 
 struct RankWindowArgs {
     const uint32_t* pairs;
     const uint32_t* wcount;
-    uint32_t* dm;           // this dimension's rank array, [global index]
+    uint32_t* dm;           // this role's rank array, [global payload]
     uint32_t wbits, nwin, chunks;   // chunks = 2^wbits / RANK_WIN_CHUNK (at least 1)
     uint32_t ntotal;
 };
@@ -207,7 +212,6 @@ void launch_rank_window(const RankWindowArgs& a, hipStream_t st);
 
 // Per-dimension rank arrays dm[d*ntotal + i] -> point-major records
 // pm[i*k + d], i < ntotal.
-void launch_rank_pack(int k, const uint32_t* dm, uint32_t* pm, uint32_t ntotal, hipStream_t st);
 void launch_level0(int k, const Level0Args& a, uint32_t tiles, bool widest, hipStream_t st);
 void launch_level_select(const LevelSelectArgs& a, uint32_t tiles, hipStream_t st);
 void launch_level_pivot(int k, const LevelPivotArgs& a, uint32_t tiles, bool widest, hipStream_t st);

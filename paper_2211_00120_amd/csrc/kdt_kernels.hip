@@ -193,15 +193,19 @@ __device__ uint32_t xq_take(const uint32_t* xq, uint32_t* cnt, uint32_t ndims, u
     return 0xFFFFFFFFu;
 }
 
-// One stable LSD digit pass of the (key, index) sorts of a group of
-// dimensions, every tree a segment of its own.  The dimensions' tiles are
-// interleaved (tile t of the launch is tile t / ndims of dimension slot
+// One stable LSD digit pass of the (key, payload) sorts of a group of
+// presort roles, every tree a segment of its own (role r sorts dimension
+// role_dim(r, d0) of a tree whose root splits in d0).  The roles' tiles are
+// interleaved (tile t of the launch is tile t / ndims of role slot
 // t % ndims), so the look-back chains of the group advance side by side.
-// A tree's first pass that runs reads the keys of prep and takes the local
-// index as value; LAST writes the sorted indices (rank -> index) and, unless
-// the ranks go through the windowed scatter, scatters each index's rank into
-// the point-major rank table.  Pairs are stored interleaved (uint2).  Passes
-// whose digit is the same in every key of the tree are skipped (see
+// A tree's first pass that runs reads the keys of prep with the payload:
+// the local index, or, in the per-role layout, for every role but the
+// root's the point's root rank (written by the root's sort and windowed
+// scatter, which run first).  LAST writes the sorted payloads (rank ->
+// payload) and, in the point-major layout, scatters each rank into the rank
+// table row of its index.  Ties keep the input order (local index order): a
+// stable sort of keys read in index order, whatever the payload.  Pairs are stored interleaved (uint2).
+// Passes whose digit is the same in every key of the tree are skipped (see
 // PresortArgs).
 template <bool LAST>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
@@ -216,9 +220,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         // launch, no tile runs, and the workgroup leaves without taking a
         // tile (the whole launch would otherwise queue on the tile counter)
         const uint32_t* sum = a.keysum + (size_t)a.sh.tree0.idx * KEYSUM_WORDS;
+        const uint32_t r0 = a.dimnode ? (uint32_t)a.dimnode[a.sh.tree0.off] : 0u;
         uint32_t runs = 0u;
-        for (uint32_t j = 0; j < a.ndims; ++j)
-            runs |= ((sum[8 + a.dim0 + j] ^ sum[12 + a.dim0 + j]) >> (8u * a.pass)) & 0xFFu;
+        for (uint32_t j = 0; j < a.ndims; ++j) {
+            const uint32_t d = role_dim(a.role0 + j, r0);
+            runs |= ((sum[8 + d] ^ sum[12 + d]) >> (8u * a.pass)) & 0xFFu;
+        }
         if (uniform(runs) == 0u) {
             zero_range(a.lb_zero, a.lb_zero_n);
             return;
@@ -232,10 +239,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         return;
     }
     const uint32_t slot = tt % a.ndims, g = tt / a.ndims;
-    const uint32_t dim = a.dim0 + slot;
+    const uint32_t role = a.role0 + slot;
     TreeStep st;
     TreeInfo ti;
     find_share(a.sh, g, st, ti);
+    const uint32_t d0 = a.dimnode ? (uint32_t)a.dimnode[ti.off] : 0u;
+    const uint32_t dim = role_dim(role, d0);
     // digits of this dimension that are not the same in every key of the tree
     const uint32_t* sum = a.keysum + (size_t)ti.idx * KEYSUM_WORDS;
     const uint32_t vary = uniform(sum[8 + dim] ^ sum[12 + dim]);
@@ -251,7 +260,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     const uint32_t* kvin = kvs + (size_t)((ran + 1u) & 1u) * a.kv_words;
     uint32_t* kvout = kvs + (size_t)(ran & 1u) * a.kv_words;
     const uint32_t* kin = a.keys + (size_t)dim * a.ntotal;
-    uint32_t* perm_out = a.perms + (size_t)dim * a.ntotal;
+    uint32_t* perm_out = a.perms + (size_t)role * a.ntotal;
     const uint32_t start = (g - st.tile0) * T;
     const uint32_t cnt = min(T, ti.n - start);
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
@@ -269,7 +278,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         if (ok[i]) {
             if (first) {
                 rec[i].x = kin[off + start + j];
-                rec[i].y = start + j;
+                // the local index, or for the other roles their root rank
+                rec[i].y = (role == 0u || !a.root_ranks) ? start + j : a.root_ranks[off + start + j];
             } else {
                 const uint2 kv = reinterpret_cast<const uint2*>(kvin)[off + start + j];
                 rec[i].x = kv.x;
@@ -279,9 +289,6 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
         dig[i] = (rec[i].x >> shift) & 0xFFu;
     }
     const uint32_t n = ti.n;
-    // iteration 0 reads the root dimension's ranks as positions in perm_out,
-    // so only the other dimensions go into the (randomly written) rank table
-    const bool to_table = !LAST || dim != (a.dimnode ? (uint32_t)a.dimnode[off] : 0u);
     sweep_tile<RB, ITEMS, 2>(
         sm, rec, ok, dig, ITEMS, cnt, a.hist + (size_t)ti.idx * a.hist_stride + (dim * 4u + q) * RADIX, 0u,
         a.lb + (size_t)slot * a.lb_dim_words, g, st.tile0, a.status,
@@ -308,8 +315,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
             }
             if (LAST) {
                 perm_out[off + pos] = r.y;
-                if (to_table && a.rank_table)
-                    a.rank_table[(off + r.y) * a.rank_stride + dim * a.rank_dstride] = pos;
+                // iteration 0 reads the root's ranks as positions
+                if (a.rank_table && role != 0u) a.rank_table[(off + r.y) * a.k + dim] = pos;
             } else {
                 reinterpret_cast<uint2*>(kvout)[off + pos] = make_uint2(r.x, r.y);
             }
@@ -320,13 +327,15 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
 
 // ------------------------------------------------------ windowed rank scatter
 
-// The per-dimension rank arrays of a large tree are written in two steps
-// instead of one random scatter: k_rank_bucket reads a dimension's rank ->
-// index list and appends each (global index, rank) pair to the bucket of its
-// index window (2^wbits indices; a tile counts its pairs per window in LDS
-// and reserves room with one atomic per window), then k_rank_window writes
-// the ranks one window at a time, so that the lines it writes stay in cache
+// The per-role rank arrays of a large tree are written in two steps instead
+// of one random scatter: k_rank_bucket reads a role's rank -> payload list
+// and appends each (global payload, rank) pair to the bucket of its payload
+// window (2^wbits payloads; a tile counts its pairs per window in LDS and
+// reserves room with one atomic per window), then k_rank_window writes the
+// ranks one window at a time, so that the lines it writes stay in cache
 // until they are full.  The order of pairs inside a bucket is immaterial.
+// The root's role gives each local index its root rank; the other roles
+// give each root position the rank of its point in their dimension.
 __global__ void __launch_bounds__(SWEEP_THREADS) k_rank_bucket(RankBucketArgs a)
 {
     constexpr int ITEMS = PRESORT_ITEMS;
@@ -336,8 +345,6 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_rank_bucket(RankBucketArgs a)
     TreeInfo ti;
     find_share(a.sh, blockIdx.x, st, ti);
     const size_t off = ti.off;
-    // a tree's root dimension has no rank array (iteration 0 uses positions)
-    if (a.dim == (a.dimnode ? (uint32_t)a.dimnode[off] : 0u)) return;
     for (uint32_t x = threadIdx.x; x < a.nwin; x += SWEEP_THREADS) cnt[x] = 0u;
     __syncthreads();
     const uint32_t start = (blockIdx.x - st.tile0) * PRESORT_TILE;
@@ -408,52 +415,6 @@ void launch_rank_window(const RankWindowArgs& a, hipStream_t st)
     if (grid) k_rank_window<<<grid, BLOCK, 0, st>>>(a);
 }
 
-// ------------------------------------------------------------- rank packing
-
-// Per-dimension rank arrays to point-major records, PACK_PER points per
-// thread (loads first, then stores).  Each tree's root-dimension slot is
-// copied as it is (never written by the presort); iteration 0 replaces it.
-constexpr uint32_t PACK_PER = 4;
-
-template <int K>
-__global__ void __launch_bounds__(BLOCK) k_rank_pack(const uint32_t* __restrict__ dm, uint32_t* __restrict__ pm,
-                                                     uint32_t ntotal)
-{
-    const size_t base = (size_t)blockIdx.x * BLOCK * PACK_PER + threadIdx.x;
-    uint32_t v[PACK_PER][K];
-#pragma unroll
-    for (uint32_t j = 0; j < PACK_PER; ++j) {
-        const size_t i = base + (size_t)j * BLOCK;
-#pragma unroll
-        for (int d = 0; d < K; ++d) v[j][d] = i < ntotal ? dm[(size_t)d * ntotal + i] : 0u;
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < PACK_PER; ++j) {
-        const size_t i = base + (size_t)j * BLOCK;
-        if (i >= ntotal) continue;
-        if constexpr (K == 4) {
-            reinterpret_cast<uint4*>(pm)[i] = make_uint4(v[j][0], v[j][1], v[j][2], v[j][3]);
-        } else if constexpr (K == 2) {
-            reinterpret_cast<uint2*>(pm)[i] = make_uint2(v[j][0], v[j][1]);
-        } else {
-#pragma unroll
-            for (int d = 0; d < K; ++d) pm[i * K + d] = v[j][d];
-        }
-    }
-}
-
-void launch_rank_pack(int k, const uint32_t* dm, uint32_t* pm, uint32_t ntotal, hipStream_t st)
-{
-    const uint32_t grid = (uint32_t)(((size_t)ntotal + BLOCK * PACK_PER - 1) / (BLOCK * PACK_PER));
-    if (!grid) return;
-    switch (k) {
-    case 2: k_rank_pack<2><<<grid, BLOCK, 0, st>>>(dm, pm, ntotal); break;
-    case 3: k_rank_pack<3><<<grid, BLOCK, 0, st>>>(dm, pm, ntotal); break;
-    case 4: k_rank_pack<4><<<grid, BLOCK, 0, st>>>(dm, pm, ntotal); break;
-    default: break;
-    }
-}
-
 // ------------------------------------------------------------------ level 0
 
 // Iteration 0 of one tile of one tree: every tag is 0 and the presort of the
@@ -470,8 +431,8 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
     __shared__ uint32_t nh[2 * MAX_BINS];
     __shared__ uint32_t cdim[2];
     // with an XCD map, workgroup b (on XCD b mod 8) takes the tile the map
-    // gives it: a tree's tiles all on one XCD, whose L2 then holds its rank
-    // records for the gathers below; padding entries take none
+    // gives it: a tree's tiles all on one XCD, as the tail's groups later;
+    // padding entries take none
     const uint32_t tile = a.xmap ? a.xmap[blockIdx.x] : blockIdx.x;
     if (tile == 0xFFFFFFFFu) return;
     TreeStep st;
@@ -488,7 +449,7 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
     const size_t off = ti.off;
     const uint32_t L = num_levels(n);
     const uint32_t d0 = WIDEST ? (uint32_t)a.o.dimnode[off] : 0u;
-    const uint32_t* perm_d0 = a.perms + (size_t)d0 * a.ntotal + off;
+    const uint32_t* perm_d0 = a.perms + off;                 // the root's role: root order -> local index
     const uint32_t piv = (L >= 2) ? seg_pivot(make_level(n, 0), 0) : 0u;
     if (threadIdx.x == 0) {
         // split dimensions of the root's children
@@ -522,7 +483,17 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
             place<K, WIDEST>(a.o, ti, r < piv ? 1u : 2u, idx);
             continue;
         }
-        uint4 rec = load_rec4<K>(a.rank_table, off + idx);
+        // per-role arrays hold the ranks by root position (r's streams in);
+        // the point-major table holds them by index (gathered)
+        uint4 rec = make_uint4(0u, 0u, 0u, 0u);
+        if (a.role_ranks) {
+#pragma unroll
+            for (int d = 0; d < K; ++d)
+                if ((uint32_t)d != d0)
+                    set4(rec, (uint32_t)d, a.role_ranks[(size_t)dim_role((uint32_t)d, d0) * a.ntotal + off + r]);
+        } else {
+            rec = load_rec4<K>(a.rank_table, off + idx);
+        }
         // the root dimension's rank is the position (every later segment
         // keeps the root dimension's order), so its slot carries the index
         set4(rec, d0, idx);

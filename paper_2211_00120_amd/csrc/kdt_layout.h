@@ -134,6 +134,11 @@ KDT_HD uint32_t inorder_to_level(uint32_t p, uint32_t n)
     return full_nodes(lev) + ((u + 1u) >> (z + 1u));
 }
 
+// Presort roles of a tree whose root splits in dimension d0 (k dimensions):
+// role 0 is d0, roles 1 .. k-1 are the other dimensions in increasing order.
+KDT_HD uint32_t role_dim(uint32_t role, uint32_t d0) { return role == 0u ? d0 : (role <= d0 ? role - 1u : role); }
+KDT_HD uint32_t dim_role(uint32_t d, uint32_t d0) { return d == d0 ? 0u : (d < d0 ? d + 1u : d); }
+
 // Subtrees of a level come in three sizes (see the header comment); a
 // segment-aligned tiling cuts each one into tiles of at most `tile` points.
 struct SegTiles {

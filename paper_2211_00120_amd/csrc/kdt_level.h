@@ -61,7 +61,12 @@ __global__ void __launch_bounds__(64 * PIVOT_SEGS) k_level_pivot(LevelPivotArgs 
             p = (p << RBv) | wave_find_bucket(h + (size_t)jj * NB, NB, kk, a.o.status);
     }
     if (lane_id() != 0) return;
-    if (d != d0 && in_bounds(p, ti.n, a.o.status)) idx = a.perms[(size_t)d * a.ntotal + off + p];
+    // rank p in dimension d -> that role's payload: the local index, or
+    // the point's root position, whose root-role payload is the index
+    if (d != d0 && in_bounds(p, ti.n, a.o.status)) {
+        idx = a.perms[(size_t)dim_role(d, d0) * a.ntotal + off + p];
+        if (a.root_payload && in_bounds(idx, ti.n, a.o.status)) idx = a.perms[off + idx];
+    }
     if (!in_bounds(idx, ti.n, a.o.status)) idx = 0;
     place<K, WIDEST>(a.o, ti, s, idx);
     uint32_t c0 = (st.level + 1u) % a.k, c1 = c0;

@@ -312,15 +312,19 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     }
 
     // look-back words per pass, in the order the passes run
-    // presort launches: the 4 passes of a group of dimensions share a launch
-    // each (per-dimension rank arrays are written after the last one, by the
-    // windowed scatter)
+    // presort launches: roles in groups whose 4 passes share a launch each;
+    // with per-role rank arrays the root's role runs alone first (the other
+    // roles read its ranks as payloads), and each group's last pass is
+    // followed by the windowed scatter of its ranks
     p.presort_group = std::min(k, opt.presort_dims ? std::min(opt.presort_dims, PRESORT_GROUP) : PRESORT_GROUP);
-    if (!p.large.empty())
-        for (uint32_t d0 = 0; d0 < k; d0 += p.presort_group) {
-            const uint32_t nd = std::min(p.presort_group, k - d0);
-            for (uint32_t q = 0; q < 4u; ++q) p.presort_launches.push_back({d0, nd, q});
+    if (!p.large.empty()) {
+        if (p.rank_dm)
+            for (uint32_t q = 0; q < 4u; ++q) p.presort_launches.push_back({0u, 1u, q});
+        for (uint32_t r0 = p.rank_dm ? 1u : 0u; r0 < k; r0 += p.presort_group) {
+            const uint32_t nd = std::min(p.presort_group, k - r0);
+            for (uint32_t q = 0; q < 4u; ++q) p.presort_launches.push_back({r0, nd, q});
         }
+    }
     for (const Plan::PresortLaunch& pl : p.presort_launches)
         p.pass_words.push_back(pl.ndims * p.presort_tiles * RADIX_HOST);
 
@@ -417,6 +421,7 @@ Plan make_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, const Pl
     p.o_ranks = take(N * k * 4);
     // the record buffers also hold the presort's (key, index) ping-pongs
     p.rec_words = std::max(N * k, 2 * N);
+    // (a launch of g roles takes slots 0 .. g-1 of 4N words each)
     p.o_rec = take(std::max(p.rec_words * 2, (size_t)4 * p.presort_group * N) * 4);
     p.o_nodeperm = take(N * 4);
     p.o_dimnode = take(N);

@@ -25,12 +25,12 @@ constexpr uint32_t NO_HIST = 0xFFFFFFFFu;
 struct PlanOptions {
     uint32_t radix_bits = 0;   // digit width of the pivot selects: 8, 9 or 10
     uint32_t max_items = 0;    // records per thread of the split tiles: 4 (512 x 4 only) or PART_ITEMS (also 512 x PART_ITEMS)
-    uint32_t rank_layout = 0;  // 1: point-major rank table, 2: per-dimension rank arrays + packing pass
-    uint32_t presort_dims = 0; // dimensions whose presort digit passes share a launch: 1..4 (clamped to k)
+    uint32_t rank_layout = 0;  // 1: point-major rank table, 2: per-role rank arrays (windowed scatter)
+    uint32_t presort_dims = 0; // non-root presort roles whose digit passes share a launch: 1..4 (clamped)
 };
 
 // A tree whose rank table is larger than this has its ranks scattered into
-// per-dimension arrays and then packed (random 4-byte writes that leave a
+// per-role arrays through payload windows (random 4-byte writes that leave a
 // line partly written cost about twice as much as ones that, over the pass,
 // fill it); smaller tables stay in the last-level cache while their tree's
 // tiles run and are written point-major.
@@ -64,11 +64,11 @@ struct Plan {
     std::vector<uint32_t> large;     // trees built by digit passes
     std::vector<TreeStep> small;     // whole-tree shares (one workgroup each)
     uint32_t B = 0, RB = 8, P = 0;   // rank bits / digit bits / digits of the pivot selects
-    bool rank_dm = false;            // per-dimension rank arrays (windowed scatter), a pass packs them
-    uint32_t rank_wbits = 0, rank_nwin = 0;  // index windows of the windowed scatter
-    uint32_t presort_group = 1;      // dimensions sharing the presort launches of passes 0-2
+    bool rank_dm = false;            // per-role rank arrays (windowed scatter) instead of a point-major table
+    uint32_t rank_wbits = 0, rank_nwin = 0;  // payload windows of the windowed scatter
+    uint32_t presort_group = 1;      // presort roles sharing a launch (the root's role runs alone, first)
     struct PresortLaunch {
-        uint32_t dim0, ndims, pass;  // digit pass `pass` of dimensions dim0 .. dim0+ndims-1
+        uint32_t role0, ndims, pass;  // digit pass `pass` of presort roles role0 .. role0+ndims-1
     };
     std::vector<PresortLaunch> presort_launches;  // in order
     bool xq = false;                 // presort tiles from per-XCD queues (many trees)

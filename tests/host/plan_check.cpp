@@ -232,27 +232,41 @@ static void check_plan(const std::vector<uint32_t>& n, uint32_t k, bool widest, 
     }
     CHECK(groups == p.tail_groups, "tail groups");
     // look-back words
-    // presort: dimensions in groups of presort_group, each of the 4 passes of
-    // a group one launch; every launch's look-back words cover its dimensions
+    // presort: roles in groups of presort_group, each of the 4 passes of a
+    // group one launch; with per-role rank arrays the root's role runs alone
+    // first and every other role's passes come after all of the root's
     const uint32_t G = p.presort_group;
     CHECK(G == std::min(k, opt.presort_dims ? std::min(opt.presort_dims, PRESORT_GROUP) : PRESORT_GROUP),
           "presort group %u (option %u)", G, opt.presort_dims);
     std::vector<Plan::PresortLaunch> want;
-    if (!p.large.empty())
-        for (uint32_t d0 = 0; d0 < k; d0 += G) {
-            const uint32_t nd = std::min(G, k - d0);
-            for (uint32_t q = 0; q < 4u; ++q) want.push_back({d0, nd, q});
+    if (!p.large.empty()) {
+        if (p.rank_dm)
+            for (uint32_t q = 0; q < 4u; ++q) want.push_back({0u, 1u, q});
+        for (uint32_t r0 = p.rank_dm ? 1u : 0u; r0 < k; r0 += G) {
+            const uint32_t nd = std::min(G, k - r0);
+            for (uint32_t q = 0; q < 4u; ++q) want.push_back({r0, nd, q});
         }
+    }
     CHECK(want.size() == p.presort_launches.size(), "presort launch count");
     uint32_t sorted_passes[4] = {0, 0, 0, 0};
     for (size_t i = 0; i < want.size() && i < p.presort_launches.size(); ++i) {
         const Plan::PresortLaunch& a = p.presort_launches[i];
-        CHECK(a.dim0 == want[i].dim0 && a.ndims == want[i].ndims && a.pass == want[i].pass, "presort launch %zu", i);
-        // a one-dimension launch inside a group uses its dimension's slot
-        CHECK(a.ndims == G || a.ndims == 1 || a.dim0 + a.ndims == k, "presort launch shape");
-        for (uint32_t d = a.dim0; d < a.dim0 + a.ndims && d < 4; ++d) sorted_passes[d] |= 1u << a.pass;
+        CHECK(a.role0 == want[i].role0 && a.ndims == want[i].ndims && a.pass == want[i].pass, "presort launch %zu", i);
+        CHECK(a.ndims >= 1 && a.ndims <= G && a.role0 + a.ndims <= k, "presort launch shape");
+        if (a.role0 > 0 && p.rank_dm) CHECK(sorted_passes[0] == 0xFu, "role %u before the root's passes", a.role0);
+        for (uint32_t r = a.role0; r < a.role0 + a.ndims && r < 4; ++r) sorted_passes[r] |= 1u << a.pass;
     }
-    for (uint32_t d = 0; d < k && !p.large.empty(); ++d) CHECK(sorted_passes[d] == 0xFu, "dimension %u passes", d);
+    for (uint32_t r = 0; r < k && !p.large.empty(); ++r) CHECK(sorted_passes[r] == 0xFu, "role %u passes", r);
+    // roles <-> dimensions: a bijection for every root dimension
+    for (uint32_t d0 = 0; d0 < k; ++d0) {
+        uint32_t seen = 0;
+        for (uint32_t r = 0; r < k; ++r) {
+            const uint32_t d = role_dim(r, d0);
+            CHECK(d < k && dim_role(d, d0) == r, "role %u of root dimension %u", r, d0);
+            seen |= 1u << d;
+        }
+        CHECK(seen == (1u << k) - 1u && role_dim(0, d0) == d0, "roles of root dimension %u", d0);
+    }
     // per-XCD presort queues (many trees): every presort tile in exactly one
     // queue, a tree's tiles all in one queue and in order
     CHECK(p.xq == (p.large.size() >= XQ_MIN_TREES && p.presort_launches.size() <= XQ_LAUNCHES), "xq choice");
