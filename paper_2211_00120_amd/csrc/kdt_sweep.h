@@ -285,19 +285,25 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const u
     constexpr uint32_t NB = 1u << RB;
     constexpr uint32_t BPT = NB > SWEEP_THREADS ? NB / SWEEP_THREADS : 1u;   // bins per thread (contiguous)
     const uint32_t w = threadIdx.x >> 6;
+    const uint32_t t0 = threadIdx.x * BPT;
+    const bool has = t0 < NB;
+    // the segment's digit counts: from global memory (the staged passes),
+    // loaded before the multisplit so that their latency hides behind it;
+    // from LDS (the split passes, whose caller writes them just before the
+    // call) after its barrier
+    uint32_t h[BPT];
+#pragma unroll
+    for (uint32_t b = 0; b < BPT; ++b) h[b] = (STAGE && has) ? seg_hist[t0 + b] : 0u;
     uint32_t rnk[ITEMS];
     wave_multisplit16<RB, ITEMS>(dig, ok, rnk, sm.wh + w * NB, active);
     __syncthreads();
 
     // per-digit tile counts and per-wave exclusive offsets
-    const uint32_t t0 = threadIdx.x * BPT;
-    const bool has = t0 < NB;
-    uint32_t c[BPT], h[BPT];
+    uint32_t c[BPT];
     uint32_t csum = 0, hsum = 0;
 #pragma unroll
     for (uint32_t b = 0; b < BPT; ++b) {
         c[b] = 0;
-        h[b] = 0;
         if (!has) continue;
         uint32_t run = 0;
 #pragma unroll
@@ -308,7 +314,7 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const u
         }
         c[b] = run;
         csum += run;
-        h[b] = seg_hist[t0 + b];
+        if (!STAGE) h[b] = seg_hist[t0 + b];
         hsum += h[b];
     }
     // publish this tile's counts first, so successors can go on

@@ -310,6 +310,7 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     uint32_t idx[ITEMS];                           // original (local) index of each slot
     float4 pc[ITEMS];                              // coordinates of each slot's point
     uint32_t lid[ITEMS];                           // local node of each slot, once placed (see the write-out)
+    uint32_t sq[ITEMS];                            // each slot's segment (its owner's copy of seg)
     bool ok[ITEMS];
     bool bad = false;
 #pragma unroll
@@ -333,7 +334,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
                 kk[d] = coord_key<I32>(bits);
             }
             rec[i] = ok[i] ? make_uint4(kk[0], kk[1], kk[2], kk[3]) : make_uint4(0u, 0u, 0u, 0u);
-            seg[e] = ok[i] ? (uint16_t)0 : (uint16_t)DONE;
+            sq[i] = ok[i] ? 0u : DONE;
+            seg[e] = (uint16_t)sq[i];
         }
     } else {
         // the records (the root dimension's slot holds the point's index:
@@ -347,7 +349,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-            seg[e] = ok[i] ? (uint16_t)(seg_of_pos(v0, off0 + e) - i0) : (uint16_t)DONE;
+            sq[i] = ok[i] ? seg_of_pos(v0, off0 + e) - i0 : DONE;
+            seg[e] = (uint16_t)sq[i];
         }
         const uint32_t d0 = WIDEST ? (uint32_t)o.dimnode[off] : 0u;
 #pragma unroll
@@ -561,16 +564,23 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             }
         }
         __syncthreads();
-        // tag update (Sec. 3.2); each slot's owner places its point as soon
-        // as its node is known
+        // tag update (Sec. 3.2): each slot's owner learns its node or child
+        // segment.  All loads first: a store to seg may alias a later
+        // slot's load, which would otherwise wait for it
+        uint32_t tv[ITEMS], cw[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-            if (!ok[i]) continue;
-            const uint32_t q = seg[e];
+            tv[i] = sq[i] != DONE ? (uint32_t)tmp[e] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) cw[i] = sq[i] != DONE ? (uint32_t)ub.cnt[tv[i] >> 12][sq[i]] : 0u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            const uint32_t q = sq[i];
             if (q == DONE) continue;
-            const uint32_t tv = tmp[e];
-            const uint32_t wr = (tv & 0xFFFu) + ub.cnt[tv >> 12][q];
+            const uint32_t wr = (tv[i] & 0xFFFu) + cw[i];
             const uint32_t gq = (i0 << t) + q;
             const uint32_t ls = seg_left_size(vl, gq);
             if (wr == ls) {
@@ -583,16 +593,17 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
                     ndim[nidx] = (uint8_t)ds;
                     nplane[nidx] = coord_key<I32>(__float_as_uint(pickf(pc[i], ds)));
                 }
-                seg[e] = (uint16_t)DONE;
+                sq[i] = DONE;
             } else {
                 const uint32_t side = wr > ls ? 1u : 0u;
                 if (last) {
                     lid[i] = gc * ((2u << t) - 1u) + 2u * q + side;
-                    seg[e] = (uint16_t)DONE;
+                    sq[i] = DONE;
                 } else {
-                    seg[e] = (uint16_t)(2u * q + side);
+                    sq[i] = 2u * q + side;
                 }
             }
+            seg[e] = (uint16_t)sq[i];
         }
         __syncthreads();
         if (WIDEST) {
