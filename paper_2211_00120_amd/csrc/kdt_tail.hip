@@ -234,8 +234,152 @@ __device__ __forceinline__ bool tail_bucket_sort(const uint32_t (&key)[ITEMS], c
     return true;
 }
 
+// The group's rank keys of ND dimensions bucket-sorted together.  As
+// tail_bucket_sort, but for ranks: they are unique, so a bucket's keys need
+// no tie-break and only their low 16 bits (the bucket fixes the rest when the
+// bucket shift is at most 16); bucket counters and starts are 16-bit.  The ND
+// sorts then fit the LDS of one and share its barriers.  rec holds the keys
+// (dimension dims[j] of record i), bcp ND * TB_BUCKETS / 2 words, tk ND *
+// TAIL_CAP halves, red 3 * ND words, sh ND * (TAIL_THREADS / 64) words.
+// Returns the dimensions it sorted (bit d for dimension d): one whose shift
+// exceeds 16 or whose fullest bucket holds more than TB_FILL keys is left to
+// the caller.  All threads call it; it starts and ends with a barrier.
+template <int ITEMS, int ND>
+__device__ __forceinline__ uint32_t tail_bucket_sort_ranks(const uint4 (&rec)[ITEMS], const bool (&ok)[ITEMS],
+                                                           uint16_t (*ord)[TAIL_CAP], const uint32_t (&dims)[ND],
+                                                           uint32_t m, uint32_t* bcp, uint16_t* tk, uint32_t* red,
+                                                           uint32_t* sh)
+{
+    constexpr int NW = TAIL_THREADS / 64;
+    constexpr uint32_t CW = 64u * ITEMS;
+    constexpr uint32_t HB = TB_BUCKETS / 2u;                 // counter words of one dimension
+    static_assert(TB_BUCKETS == 4u * TAIL_THREADS, "four buckets per thread");
+    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+    uint32_t lo[ND], hi[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        lo[j] = 0xFFFFFFFFu;
+        hi[j] = 0u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (!ok[i]) continue;
+            const uint32_t k = pick4(rec[i], dims[j]);
+            lo[j] = min(lo[j], k);
+            hi[j] = max(hi[j], k);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            lo[j] = min(lo[j], (uint32_t)__shfl_xor((int)lo[j], o, 64));
+            hi[j] = max(hi[j], (uint32_t)__shfl_xor((int)hi[j], o, 64));
+        }
+    __syncthreads();
+    if (threadIdx.x < (uint32_t)ND) {
+        red[3 * threadIdx.x] = 0xFFFFFFFFu;
+        red[3 * threadIdx.x + 1] = 0u;
+        red[3 * threadIdx.x + 2] = 0u;
+    }
+    for (uint32_t x = threadIdx.x; x < ND * HB; x += TAIL_THREADS) bcp[x] = 0u;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < ND; ++j) {
+            atomicMin(&red[3 * j], lo[j]);
+            atomicMax(&red[3 * j + 1], hi[j]);
+        }
+    __syncthreads();
+    uint32_t kmin[ND], shift[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        kmin[j] = red[3 * j];
+        const uint32_t range = red[3 * j + 1] - kmin[j];
+        const uint32_t rbits = range ? 32u - (uint32_t)__builtin_clz(range) : 0u;
+        shift[j] = rbits > TB_BITS ? rbits - TB_BITS : 0u;
+    }
+    // each key's place in its bucket's arrival order (two 16-bit places a
+    // word: items 2h and 2h+1); the bucket is recomputed from the key
+    auto bucket = [&](int j, int i) { return (pick4(rec[i], dims[j]) - kmin[j]) >> shift[j]; };
+    uint32_t pl[ND][(ITEMS + 1) / 2];
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if ((i & 1) == 0) pl[j][i / 2] = 0u;
+            if (!ok[i]) continue;
+            const uint32_t b = bucket(j, i);
+            const uint32_t half = 16u * (b & 1u);
+            const uint32_t old = atomicAdd(&bcp[j * HB + (b >> 1)], 1u << half);
+            pl[j][i / 2] |= ((old >> half) & 0xFFFFu) << (16 * (i & 1));
+        }
+    __syncthreads();
+    // bucket starts: four consecutive buckets per thread and dimension (the
+    // counts are read again after the barrier rather than kept live)
+    uint32_t ex[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        const uint32_t w0 = bcp[j * HB + 2u * threadIdx.x], w1 = bcp[j * HB + 2u * threadIdx.x + 1u];
+        const uint32_t sum = (w0 & 0xFFFFu) + (w0 >> 16) + (w1 & 0xFFFFu) + (w1 >> 16);
+        uint32_t mx = max(max(w0 & 0xFFFFu, w0 >> 16), max(w1 & 0xFFFFu, w1 >> 16));
+        const uint32_t inc = wave_incl_scan(sum);
+        ex[j] = inc - sum;
+        if (lane == 63) sh[j * NW + w] = inc;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        if (lane == 0) atomicMax(&red[3 * j + 2], mx);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        uint32_t s0 = ex[j];
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww)
+            if (ww < (int)w) s0 += sh[j * NW + ww];
+        const uint32_t w0 = bcp[j * HB + 2u * threadIdx.x], w1 = bcp[j * HB + 2u * threadIdx.x + 1u];
+        const uint32_t s1 = s0 + (w0 & 0xFFFFu), s2 = s1 + (w0 >> 16), s3 = s2 + (w1 & 0xFFFFu);
+        bcp[j * HB + 2u * threadIdx.x] = s0 | (s1 << 16);
+        bcp[j * HB + 2u * threadIdx.x + 1u] = s2 | (s3 << 16);
+    }
+    __syncthreads();
+    uint32_t done = 0;
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+        if (shift[j] <= 16u && red[3 * j + 2] <= TB_FILL) done |= 1u << dims[j];
+    auto start_of = [&](int j, uint32_t b) { return (bcp[j * HB + (b >> 1)] >> (16u * (b & 1u))) & 0xFFFFu; };
+    // the keys' low 16 bits (relative to the minimum) by bucket
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        if (!((done >> dims[j]) & 1u)) continue;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (!ok[i]) continue;
+            const uint32_t place = (pl[j][i / 2] >> (16 * (i & 1))) & 0xFFFFu;
+            tk[j * TAIL_CAP + start_of(j, bucket(j, i)) + place] = (uint16_t)(pick4(rec[i], dims[j]) - kmin[j]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        if (!((done >> dims[j]) & 1u)) continue;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (!ok[i]) continue;
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            const uint32_t b = bucket(j, i);
+            const uint32_t st = start_of(j, b), en = b + 1u < TB_BUCKETS ? start_of(j, b + 1u) : m;
+            const uint32_t mine = (pick4(rec[i], dims[j]) - kmin[j]) & 0xFFFFu;
+            uint32_t r = 0;
+            for (uint32_t x = st; x < en; ++x) r += (uint32_t)tk[j * TAIL_CAP + x] < mine ? 1u : 0u;
+            ord[dims[j]][st + r] = (uint16_t)e;
+        }
+    }
+    __syncthreads();
+    return done;
+}
+
 template <int K, bool WIDEST, bool I32>
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
+__global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
 {
     constexpr int ITEMS = TAIL_ITEMS;
     constexpr int NW = TAIL_THREADS / 64;
@@ -258,11 +402,15 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
             uint32_t tk[C];                        // keys in bucket order
             uint16_t ts[C];                        // their slots
         } bsort;
+        struct {
+            uint32_t bcp[(K > 1 ? K - 1 : 1) * TB_BUCKETS / 2];   // packed 16-bit bucket counts, then starts
+            uint16_t tk[(K > 1 ? K - 1 : 1) * C];                  // low key bits in bucket order
+        } rsort;
         uint16_t cnt[NW][C];                       // per-(wave, segment) counters of an iteration
         uint32_t stage[4 * C];                     // write-out: coordinates by local node
     } ub;
-    __shared__ uint32_t sh[NW];
-    __shared__ uint32_t red[4];
+    __shared__ uint32_t sh[(K > 1 ? K - 1 : 1) * NW];
+    __shared__ uint32_t red[3 * (K > 1 ? K - 1 : 1)];
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
     __shared__ uint16_t wl[WIDEST ? C : 1];        // split-widest: the iteration's walk list
     __shared__ uint32_t lcnt[WIDEST ? K : 1][NW];  // split-widest: walk-list slots per (dimension, wave)
@@ -410,11 +558,22 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail(TailArgs a)
     // bunch, stable LSD radix in LDS with the fewest passes over the B key
     // bits (digits of at most 9 bits) ----
     const uint32_t nsb = ((B + 7u) / 8u == (B + 8u) / 9u) ? 8u : 9u;
+    // ranks (unique keys): the dimensions but the free one in one bucket sort
+    uint32_t sorted = 0;
+    if constexpr (K > 1) {
+        if (!FP) {
+            uint32_t dims[K - 1];
+#pragma unroll
+            for (int j = 0; j < K - 1; ++j) dims[j] = (uint32_t)j + ((uint32_t)j >= free_dim ? 1u : 0u);
+            sorted = tail_bucket_sort_ranks<ITEMS, K - 1>(rec, ok, ord, dims, m, ub.rsort.bcp, ub.rsort.tk, red, sh);
+        }
+    }
     for (uint32_t d = 0; d < (uint32_t)K; ++d) {
         if (d == free_dim) {
             for (uint32_t p = threadIdx.x; p < m; p += TAIL_THREADS) ord[d][p] = (uint16_t)p;
             continue;
         }
+        if ((sorted >> d) & 1u) continue;
         uint32_t key[ITEMS];
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) key[i] = pick4(rec[i], d);
