@@ -352,11 +352,11 @@ kdt_status enqueue(const Plan& p, const float* pts, float* tree, uint32_t* perm,
         if (kdt_status s = run_kernel(st, KIND_PREP, nlarge * 8.0 * K, 0.0,
                                       [&] { launch_prep((int)k, pa, p.prep_tiles, widest, st); }))
             return s;
-        if (widest)
-            if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, 0.0, [&] {
-                    launch_root_dim((int)k, shares(p, p.roots, p.t_roots, ws), o, nlarge_trees, st);
-                }))
-                return s;
+        // key summaries combined; split-widest: scene boxes and root dims
+        if (kdt_status s = run_kernel(st, KIND_ROOT, 0.0, 0.0, [&] {
+                launch_root_dim((int)k, shares(p, p.roots, p.t_roots, ws), o, nlarge_trees, widest, st);
+            }))
+            return s;
 
         // presort: per presort role (the root's dimension first, then the
         // others, see PresortArgs), 4 stable digit passes of (key, payload);

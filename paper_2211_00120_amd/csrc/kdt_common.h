@@ -230,6 +230,19 @@ __device__ __forceinline__ uint64_t match_bits(uint32_t value, uint32_t bits, bo
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Key summaries of a tree (its KEYSUM_WORDS words), combined over the
+// copies: the least and greatest key of dimension d.
+__device__ __forceinline__ void keysum_box(const uint32_t* sum, uint32_t d, uint32_t& lo, uint32_t& hi)
+{
+    lo = 0xFFFFFFFFu;
+    hi = 0u;
+#pragma unroll
+    for (uint32_t c = 0; c < KEYSUM_COPIES; ++c) {
+        lo = min(lo, sum[c * KEYSUM_COPY_WORDS + d]);
+        hi = max(hi, sum[c * KEYSUM_COPY_WORDS + 4u + d]);
+    }
+}
+
 __device__ __forceinline__ void zero_range(uint32_t* p, uint32_t n)
 {
     if (!p) return;

@@ -184,7 +184,7 @@ void launch_init(uint32_t* status, uint32_t* counters, uint32_t* z1, uint32_t n1
                  uint32_t* z3, uint32_t n3, uint32_t* z4, uint32_t n4, uint32_t* z5, uint32_t n5, uint32_t* bbox,
                  uint32_t nbox, hipStream_t st);
 void launch_prep(int k, const PrepArgs& a, uint32_t tiles, bool widest, hipStream_t st);
-void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, hipStream_t st);
+void launch_root_dim(int k, const Shares& sh, const Outs& o, uint32_t ntrees, bool widest, hipStream_t st);
 void launch_presort_pass(const PresortArgs& a, bool last, uint32_t tiles, hipStream_t st);
 // Windowed scatter of one dimension's ranks into its per-dimension array
 // (see k_rank_bucket).  Windows of 2^wbits global indices, at most

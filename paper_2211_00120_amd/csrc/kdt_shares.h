@@ -18,9 +18,14 @@ constexpr uint32_t MAX_LEVEL_PASSES = 3;   // digits of a rank of at most 30 bit
 constexpr uint32_t MAX_BINS = 1024;        // 2^10 digit values
 constexpr uint32_t PART_BINS = 4;          // digit values of the split passes (smaller, pivot, larger)
 constexpr uint32_t PREP_TILE = 4096;       // points per workgroup of prep / iteration 0
-// Per-tree key summary words, as orderable keys: [0..3] per-dimension minimum,
-// [4..7] maximum, [8..11] bitwise AND, [12..15] bitwise OR.
-constexpr uint32_t KEYSUM_WORDS = 16;
+// Per-tree key summary, as orderable keys: [0..3] per-dimension minimum,
+// [4..7] maximum, [8..11] bitwise AND, [12..15] bitwise OR, kept in
+// KEYSUM_COPIES copies on lines of their own (prep workgroup b updates copy
+// b mod KEYSUM_COPIES: one line taking every tile's atomics serialises them)
+// that k_root_dim combines into the first copy.
+constexpr uint32_t KEYSUM_COPIES = 8;
+constexpr uint32_t KEYSUM_COPY_WORDS = 32;                          // 128 bytes
+constexpr uint32_t KEYSUM_WORDS = KEYSUM_COPIES * KEYSUM_COPY_WORDS; // per tree
 
 // Threads of the onesweep workgroups (presort and level passes).
 #ifndef KDT_SWEEP_THREADS
