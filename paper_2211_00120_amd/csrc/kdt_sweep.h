@@ -325,6 +325,45 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const u
     }
     uint32_t cex, hex;
     sweep_excl_scan2(csum, hsum, sm.sh, cex, hex);
+    if (STAGE && cnt <= SWEEP_STAGE) {
+        // one staging round: the tile-local digit starts first, then the
+        // look-back of the waves that own digits while every wave stages its
+        // items (those without digits at once, instead of idling through
+        // the look-back), then the write-out
+        if (has) {
+            uint32_t x = cex;
+#pragma unroll
+            for (uint32_t b = 0; b < BPT; ++b) {
+                sm.dstart[t0 + b] = x;
+                x += c[b];
+            }
+        }
+        __syncthreads();
+        if (has) {
+#pragma unroll
+            for (uint32_t b = 0; b < BPT; ++b) {
+                const uint32_t bin = t0 + b;
+                const uint32_t excl = first ? 0u : lookback_bin(lb, NB, g, g0, bin, status);
+                if (!first) lb_store(&lb[(size_t)g * NB + bin], LB_INC | (excl + c[b]));
+                sm.gbase[bin] = seg_off + hex + excl - cex;
+                cex += c[b];
+                hex += h[b];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            if (i >= active) break;
+            if (ok[i]) stage_put(sm.stage[sm.dstart[dig[i]] + sm.wh[w * NB + dig[i]] + rnk[i]], rec[i]);
+        }
+        __syncthreads();
+        for (uint32_t j = threadIdx.x; j < cnt; j += SWEEP_THREADS) {
+            const uint4 r = stage_get(sm.stage[j]);
+            const uint32_t d = digit_of(r);
+            store(j, sm.gbase[d] + j, r);
+        }
+        __syncthreads();
+        return;
+    }
     if (has) {
 #pragma unroll
         for (uint32_t b = 0; b < BPT; ++b) {
