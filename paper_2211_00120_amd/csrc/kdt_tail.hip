@@ -767,8 +767,10 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
         __syncthreads();
         if (WIDEST) {
             // each segment's children: domain = the segment's domain (root
-            // box clipped by its ancestors' planes) clipped by its own plane
-            for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) {
+            // box clipped by its ancestors' planes) clipped by its own plane;
+            // while the segments are at most half the threads, one thread per
+            // child (both walk the segment's ancestors), else one per segment
+            auto children = [&](uint32_t q, uint32_t c0, uint32_t c1) {
                 const uint32_t gq = (i0 << t) + q;
                 const uint32_t sn = vl.Fl + gq;
                 const uint32_t nidx = gc * ((1u << t) - 1u) + q;
@@ -776,8 +778,7 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                 const uint32_t plane = nplane[nidx];
                 uint32_t lo[K], hi[K];
                 local_box<K>(t, q, gc, rootbox, ndim, nplane, lo, hi);
-#pragma unroll
-                for (uint32_t c = 0; c < 2u; ++c) {
+                for (uint32_t c = c0; c < c1; ++c) {
                     const uint32_t child = 2u * sn + 1u + c;
                     if (child >= ti.n) continue;
                     uint32_t l2[K], h2[K];
@@ -794,6 +795,11 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                     o.dimnode[off + child] = (uint8_t)cd;
                     if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
                 }
+            };
+            if (2u * S <= TAIL_THREADS) {
+                if (threadIdx.x < 2u * S) children(threadIdx.x >> 1, threadIdx.x & 1u, (threadIdx.x & 1u) + 1u);
+            } else {
+                for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) children(q, 0u, 2u);
             }
             // the next iteration reads segdim after its first barrier
         }
