@@ -262,13 +262,15 @@ typedef struct kdt_tuning {
     uint32_t level_items;  /* records per thread of the split tiles: 0 (planner's choice), 4 (tiles of
                               512 x 4 records only) or 10 (also tiles of 512 x 10 records, where an
                               iteration's subtrees fill them) */
-    uint32_t rank_layout;  /* 0 (planner's choice: 2 when the largest tree's rank table exceeds 128 MiB), 1 (each dimension's
-                              last presort pass writes a point-major rank table) or 2 (it writes one rank array
-                              per dimension, which a packing pass turns into the point-major table); never
-                              swept by kdt_tune_batched */
-    uint32_t presort_dims; /* 0 (planner's choice: all k) or 1..4 (clamped to k): dimensions whose presort
-                              digit passes share a launch, each with its own look-back chain (a last pass
-                              that scatters into per-dimension arrays always runs one dimension per launch) */
+    uint32_t rank_layout;  /* 0 (planner's choice: 2 when the largest tree's rank table exceeds 128 MiB), 1 (each
+                              dimension's last presort pass writes a point-major rank table, which iteration 0
+                              gathers by index) or 2 (the root dimension is sorted first; every other dimension's
+                              sort carries each point's root rank, and its ranks go to an array of its own by root
+                              position through a windowed scatter, which iteration 0 streams); never swept by
+                              kdt_tune_batched */
+    uint32_t presort_dims; /* 0 (planner's choice: all k) or 1..4 (clamped to k): presort dimensions whose digit
+                              passes share a launch, each with its own look-back chain (with rank_layout 2 the
+                              root dimension's passes run alone, before the others) */
     double ms;             /* kdt_tune_batched: time of one build with this choice */
 } kdt_tuning;
 
