@@ -229,7 +229,7 @@ def test_batched_full_4096_clouds():
 
 @pytest.mark.parametrize("mode", [kdt.ROUND_ROBIN, kdt.WIDEST])
 def test_batched_rank_layouts(mode):
-    """A batch built with per-dimension rank arrays plus packing equals the
+    """A batch built with per-role rank arrays (by root position) equals the
     same batch built with the point-major scatter, and every cloud is the
     oracle's tree."""
     sizes = [70000, 3000, 0, 130000, 9000, 1500, 40000, 2049]
@@ -248,6 +248,36 @@ def test_batched_rank_layouts(mode):
         assert np.array_equal(got[1][1], got[2][1]) and np.array_equal(got[1][2], got[2][2])
         for c in range(len(sizes)):
             _assert_cloud(pts, offsets, c, *got[2][:3], mode, "rank-layout-2")
+    finally:
+        kdt.tuning_clear()
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_batched_widest_root_dims_differ(k, layout):
+    """Split-widest clouds whose roots split in different dimensions (cloud i
+    stretched along dimension i mod k) in one batch: the presort roles map
+    to other dimensions in every cloud, and with per-role rank arrays the
+    root's role runs first and the others carry root ranks.  Every cloud is
+    the oracle's tree, with either rank layout."""
+    sizes = [60000, 9000, 2500, 33333, 70001, 4100, 12000, 2049]
+    clouds = []
+    for i, n in enumerate(sizes):
+        c = workloads.uniform(n, k, 900 + 10 * k + i)
+        c[:, i % k] *= np.float32(3.0)
+        clouds.append(c)
+    pts, offsets = _concat(clouds)
+    bits = int(max(sizes) - 1).bit_length()
+    kdt.tuning_clear()
+    try:
+        kdt.tuning_set(k, kdt.WIDEST, bits, 0, 0, layout)
+        _say(f"case batched widest root dims k={k} layout {layout}")
+        tree, perm, dim, status = _run_batched(pts, offsets, kdt.WIDEST)
+        assert status == kdt.OK
+        for c in range(len(sizes)):
+            a = int(offsets[c])
+            assert dim[a] == c % k, f"cloud {c}: root dimension {dim[a]}"
+            _assert_cloud(pts, offsets, c, tree, perm, dim, kdt.WIDEST, f"widest-roots-layout-{layout}")
     finally:
         kdt.tuning_clear()
 

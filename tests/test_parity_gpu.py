@@ -125,11 +125,11 @@ def test_constant_digit_passes(mode):
 @pytest.mark.parametrize("k", [2, 3, 4])
 def test_rank_layouts(pdims, layout, mode, k):
     """Both rank-table layouts (the last presort passes scatter point-major
-    records; or per-dimension arrays that a packing pass turns into records)
-    build the oracle's tree, whatever number of dimensions share a presort
-    launch (0: the planner's, all of them).  The planner picks the layout by
-    the table's size, so each is forced through the tuning table of this
-    size class."""
+    records; or per-role arrays by root position, the root's role sorted
+    first) build the oracle's tree, whatever number of dimensions share a
+    presort launch (0: the planner's, all of them).  The planner picks the
+    layout by the table's size, so each is forced through the tuning table
+    of this size class."""
     n = 150_001
     bits = (n - 1).bit_length()
     pts = workloads.grid(n, k, 300 + k, levels=9)
@@ -138,6 +138,25 @@ def test_rank_layouts(pdims, layout, mode, k):
         kdt.tuning_set(k, mode, bits, 0, 0, layout, pdims)
         assert kdt.tuning_get(k, mode, bits) == (0, 0, layout, pdims)
         _assert_same(pts, mode, f"rank-layout-{layout}-presort-dims-{pdims}")
+    finally:
+        kdt.tuning_clear()
+
+
+@pytest.mark.parametrize("pdims", [0, 1])
+@pytest.mark.parametrize("layout", [1, 2])
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_rank_layouts_widest_root_not_first(pdims, layout, k):
+    """Split-widest with the root splitting in the last dimension (stretched
+    points): presort role 0 is that dimension and the other roles map past
+    it; both layouts build the oracle's tree."""
+    n = 150_001
+    bits = (n - 1).bit_length()
+    pts = workloads.uniform(n, k, 700 + k)
+    pts[:, k - 1] *= np.float32(2.5)
+    kdt.tuning_clear()
+    try:
+        kdt.tuning_set(k, kdt.WIDEST, bits, 0, 0, layout, pdims)
+        _assert_same(pts, kdt.WIDEST, f"rank-layout-{layout}-root-dim-{k - 1}")
     finally:
         kdt.tuning_clear()
 
