@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
     __shared__ uint16_t ord[K][C];
     __shared__ uint16_t seg[C];
     __shared__ uint16_t tmp[C];
-    __shared__ union {
+    __shared__ union __attribute__((aligned(16))) {
         struct {
             uint64_t x[C];                         // sort exchange
             uint16_t wh[NW * TAIL_SORT_BINS];      // per-wave digit counters
@@ -414,6 +414,7 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
     __shared__ uint16_t wl[WIDEST ? C : 1];        // split-widest: the iteration's walk list
     __shared__ uint32_t lcnt[WIDEST ? K : 1][NW];  // split-widest: walk-list slots per (dimension, wave)
+    __shared__ uint32_t dmask[2];                  // split-widest: bit d set if some segment splits in d
     __shared__ uint8_t ndim[NODES];
     __shared__ uint32_t nplane[NODES];             // keys of the fixed local nodes' planes
     __shared__ uint32_t rootbox[2][8];             // keys of the group roots' domains
@@ -534,6 +535,8 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                 }
                 const uint32_t d0 = widest_dim<K, I32>(lo, hi);
                 segdim[0][0] = (uint8_t)d0;
+                dmask[0] = 1u << d0;
+                dmask[1] = 0u;
                 o.dimnode[off] = (uint8_t)d0;
             }
         }
@@ -547,6 +550,12 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
 #pragma unroll
         for (int d = 0; d < 8; ++d) rootbox[q][d] = bx[d];
         segdim[0][q] = o.dimnode[off + v0.Fl + i0 + q];
+        if (q == 0) {
+            uint32_t dm = 0;
+            for (uint32_t r = 0; r < gc; ++r) dm |= 1u << o.dimnode[off + v0.Fl + i0 + r];
+            dmask[0] = dm;
+            dmask[1] = 0u;
+        }
     }
     // dimension whose order the input already has (within every segment):
     // the root's
@@ -616,20 +625,27 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
         const uint32_t S = gc << t;                       // group segments on this level
         const uint32_t gbits = rank_bits(S);
         const bool last = (l + 2u == L);
-        for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) {
-#pragma unroll
-            for (int ww = 0; ww < NW; ++ww) ub.cnt[ww][q] = 0;
+        {
+            // the counters of the S segments, eight to a 16-byte store (C
+            // is a multiple of 8, so rounding S up stays inside each row)
+            const uint32_t per = (S + 7u) >> 3;
+            uint4* z = reinterpret_cast<uint4*>(&ub.cnt[0][0]);
+            for (uint32_t x = threadIdx.x; x < NW * per; x += TAIL_THREADS) {
+                const uint32_t ww = x / per;
+                z[ww * (C / 8u) + (x - ww * per)] = make_uint4(0u, 0u, 0u, 0u);
+            }
         }
         __syncthreads();
         // split-widest: do all segments of this iteration split in one
         // dimension (then the walk list is that dimension's order itself)?
+        // The previous domain step (or the set-up) collected their dimensions
         uint32_t dall = 0;
         bool uni = false;
         if (WIDEST) {
-            dall = segdim[cur][0];
-            int diff = 0;
-            for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) diff |= segdim[cur][q] != dall;
-            uni = !__syncthreads_or(diff);
+            const uint32_t dm = dmask[cur];
+            dall = dm ? (uint32_t)__builtin_ctz(dm) : 0u;
+            uni = (dm & (dm - 1u)) == 0u;
+            if (threadIdx.x == 0) dmask[cur ^ 1u] = 0u;   // filled by this iteration's domain step
         }
         // position of each point inside its segment in the order of the
         // segment's split dimension: a walk over a list in which each
@@ -770,6 +786,7 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             // box clipped by its ancestors' planes) clipped by its own plane;
             // while the segments are at most half the threads, one thread per
             // child (both walk the segment's ancestors), else one per segment
+            uint32_t used = 0;                     // dimensions of the children this thread set
             auto children = [&](uint32_t q, uint32_t c0, uint32_t c1) {
                 const uint32_t gq = (i0 << t) + q;
                 const uint32_t sn = vl.Fl + gq;
@@ -793,7 +810,10 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                     }
                     const uint32_t cd = widest_dim<K, I32>(l2, h2);
                     o.dimnode[off + child] = (uint8_t)cd;
-                    if (!last) segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
+                    if (!last) {
+                        segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
+                        used |= 1u << cd;
+                    }
                 }
             };
             if (2u * S <= TAIL_THREADS) {
@@ -801,7 +821,14 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             } else {
                 for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) children(q, 0u, 2u);
             }
-            // the next iteration reads segdim after its first barrier
+            if (!last) {
+                uint32_t wm = 0;
+#pragma unroll
+                for (int d = 0; d < K; ++d)
+                    if (__any((used >> d) & 1u)) wm |= 1u << d;
+                if (lane == 0 && wm) atomicOr(&dmask[cur ^ 1u], wm);
+            }
+            // the next iteration reads segdim and dmask after its first barrier
         }
         cur ^= 1u;
     }
