@@ -41,25 +41,27 @@ namespace kdt {
 
 constexpr uint32_t DONE = 0xFFFFu;
 
-// Domain of local node (t, q) for split-widest: the subtree root's box
-// clipped by the planes of its local ancestors (stored per local node); all
-// bounds and planes are coordinate keys (see widest_dim).
+// Domain of local node (t, q) for split-widest: the box of its ancestor on
+// local level t0 <= t (box0, indexed by that ancestor's position: the group
+// roots' boxes for t0 = 0) clipped by the planes of its ancestors below
+// (stored per local node); all bounds and planes are coordinate keys (see
+// widest_dim).
 template <int K>
-__device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, const uint32_t (*rootbox)[8],
+__device__ __forceinline__ void local_box(uint32_t t, uint32_t q, uint32_t gc, uint32_t t0, const uint32_t (*box0)[8],
                                           const uint8_t* ndim, const uint32_t* nplane, uint32_t (&lo)[K],
                                           uint32_t (&hi)[K])
 {
-    const uint32_t r = q >> t;
+    const uint32_t r = q >> (t - t0);
 #pragma unroll
     for (int d = 0; d < K; ++d) {
-        lo[d] = rootbox[r][d];
-        hi[d] = rootbox[r][4 + d];
+        lo[d] = box0[r][d];
+        hi[d] = box0[r][4 + d];
     }
     uint32_t qq = q;
     // the steps' LDS reads do not depend on each other: unrolled, they are
     // issued together instead of one round trip per ancestor
 #pragma unroll 4
-    for (uint32_t tt = t; tt > 0; --tt) {
+    for (uint32_t tt = t; tt > t0; --tt) {
         const uint32_t pq = qq >> 1;
         const uint32_t idx = gc * ((1u << (tt - 1u)) - 1u) + pq;
         const uint32_t da = ndim[idx];
@@ -418,6 +420,10 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
     __shared__ uint8_t ndim[NODES];
     __shared__ uint32_t nplane[NODES];             // keys of the fixed local nodes' planes
     __shared__ uint32_t rootbox[2][8];             // keys of the group roots' domains
+    // split-widest: the domains of the TBOX nodes of local level log2(TBOX /
+    // gc), so that deeper domains clip from there, not from the roots
+    constexpr uint32_t TBOX = 128;
+    __shared__ uint32_t tbox[WIDEST ? TBOX : 1][8];
     __shared__ uint32_t bxk[8];                    // from_points split-widest: scene box keys
 
     const Outs& o = a.o;
@@ -501,9 +507,6 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             sq[i] = ok[i] ? seg_of_pos(v0, off0 + e) - i0 : DONE;
             seg[e] = (uint16_t)sq[i];
         }
-        const uint32_t d0 = WIDEST ? (uint32_t)o.dimnode[off] : 0u;
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) idx[i] = ok[i] ? pick4(rec[i], d0) : 0xFFFFFFFFu;
     }
     if (FP) {
         if (__any(bad) && lane == 0) {
@@ -604,11 +607,14 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
     __syncthreads();
 
     if (!FP) {
-        // the points of the slots (an index out of range -- a corrupt input
-        // record -- is flagged and its slot reads point 0)
+        // the points of the slots, by the index in the root dimension's slot
+        // of each record (taken only now: not live across the sorts); an
+        // index out of range -- a corrupt input record -- is flagged and its
+        // slot reads point 0
         bool oob = false;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
+            idx[i] = ok[i] ? pick4(rec[i], free_dim) : 0xFFFFFFFFu;
             const bool in = idx[i] < ti.n;
             oob |= ok[i] && !in;
             if (!in) idx[i] = 0u;
@@ -787,6 +793,7 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             // while the segments are at most half the threads, one thread per
             // child (both walk the segment's ancestors), else one per segment
             uint32_t used = 0;                     // dimensions of the children this thread set
+            const uint32_t ts = 31u - (uint32_t)__builtin_clz(TBOX / gc);   // local level of the tbox nodes
             auto children = [&](uint32_t q, uint32_t c0, uint32_t c1) {
                 const uint32_t gq = (i0 << t) + q;
                 const uint32_t sn = vl.Fl + gq;
@@ -794,7 +801,8 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                 const uint32_t ds = ndim[nidx];
                 const uint32_t plane = nplane[nidx];
                 uint32_t lo[K], hi[K];
-                local_box<K>(t, q, gc, rootbox, ndim, nplane, lo, hi);
+                const bool deep = t >= ts;
+                local_box<K>(t, q, gc, deep ? ts : 0u, deep ? tbox : rootbox, ndim, nplane, lo, hi);
                 for (uint32_t c = c0; c < c1; ++c) {
                     const uint32_t child = 2u * sn + 1u + c;
                     if (child >= ti.n) continue;
@@ -813,6 +821,13 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                     if (!last) {
                         segdim[cur ^ 1u][2u * q + c] = (uint8_t)cd;
                         used |= 1u << cd;
+                        if (t + 1u == ts) {
+#pragma unroll
+                            for (int dd = 0; dd < K; ++dd) {
+                                tbox[2u * q + c][dd] = l2[dd];
+                                tbox[2u * q + c][4 + dd] = h2[dd];
+                            }
+                        }
                     }
                 }
             };
