@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
     __shared__ uint32_t red[3 * (K > 1 ? K - 1 : 1)];
     __shared__ uint8_t segdim[2][WIDEST ? C : 1];
     __shared__ uint16_t wl[WIDEST ? C : 1];        // split-widest: the iteration's walk list
-    __shared__ uint32_t lcnt[WIDEST ? K : 1][NW];  // split-widest: walk-list slots per (dimension, wave)
+    __shared__ __attribute__((aligned(16))) uint32_t lcnt[WIDEST ? K : 1][NW];   // split-widest: walk-list slots per (dimension, wave)
     __shared__ uint32_t dmask[2];                  // split-widest: bit d set if some segment splits in d
     __shared__ uint8_t ndim[NODES];
     __shared__ uint32_t nplane[NODES];             // keys of the fixed local nodes' planes
@@ -622,6 +622,20 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
         }
         if (__any(oob) && lane == 0) atomicOr(o.status, KDT_STATUS_INTERNAL);
     }
+    // split-widest, while the segments split in several dimensions: seg[e]
+    // of a live slot holds, beside its segment (below 2048), the segment's
+    // split dimension in bits 12-13, which the walk list reads
+    auto pack_dims = [&](uint32_t cs) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
+            if (sq[i] != DONE) seg[e] = (uint16_t)(sq[i] | ((uint32_t)segdim[cs][sq[i]] << 12));
+        }
+    };
+    if (WIDEST) {
+        const uint32_t dm = dmask[0];
+        if (dm & (dm - 1u)) pack_dims(0u);
+    }
 
     // ---- iterations l0 .. L-2 ----
     uint32_t cur = 0;
@@ -671,23 +685,28 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                 for (int i = 0; i < ITEMS; ++i) {
                     const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
                     const uint32_t e = p < m ? (uint32_t)ord[d][p] : 0u;
-                    const uint32_t q = p < m ? (uint32_t)seg[e] : DONE;
+                    const uint32_t v = p < m ? (uint32_t)seg[e] : DONE;
                     le[d][i] = e;
-                    lb[d][i] = __ballot(q != DONE && segdim[cur][q] == (uint32_t)d);
+                    lb[d][i] = __ballot(v != DONE && (v >> 12) == (uint32_t)d);
                     c += (uint32_t)__popcll(lb[d][i]);
                 }
                 if (lane == 0) lcnt[d][w] = c;
             }
             __syncthreads();
             uint32_t base = 0;
+            static_assert(NW % 4 == 0, "walk-list counts are read four at a time");
 #pragma unroll
             for (int d = 0; d < K; ++d) {
                 uint32_t b = base;
 #pragma unroll
-                for (int ww = 0; ww < NW; ++ww) {
-                    const uint32_t c = lcnt[d][ww];
-                    b += (uint32_t)ww < w ? c : 0u;
-                    base += c;
+                for (int w4 = 0; w4 < NW / 4; ++w4) {
+                    const uint4 c4 = reinterpret_cast<const uint4*>(&lcnt[d][0])[w4];
+                    const uint32_t cc[4] = {c4.x, c4.y, c4.z, c4.w};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        b += (uint32_t)(4 * w4 + j) < w ? cc[j] : 0u;
+                        base += cc[j];
+                    }
                 }
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
@@ -711,7 +730,8 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const uint32_t p = w * CW + (uint32_t)i * 64u + lane;
-                q[i] = p < M ? (uint32_t)seg[e[i]] : DONE;
+                const uint32_t v = p < M ? (uint32_t)seg[e[i]] : DONE;
+                q[i] = v == DONE ? DONE : (v & 0xFFFu);
             }
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
@@ -735,13 +755,17 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             }
         }
         __syncthreads();
-        for (uint32_t q = threadIdx.x; q < S; q += TAIL_THREADS) {
-            uint32_t run = 0;
+        // two segments' counters to a 32-bit word (an odd S scans one
+        // zeroed counter past the end, which nothing reads)
+        for (uint32_t q2 = threadIdx.x; 2u * q2 < S; q2 += TAIL_THREADS) {
+            uint32_t run0 = 0, run1 = 0;
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
-                const uint32_t c = ub.cnt[ww][q];
-                ub.cnt[ww][q] = (uint16_t)run;
-                run += c;
+                uint32_t* c2 = reinterpret_cast<uint32_t*>(&ub.cnt[ww][2u * q2]);
+                const uint32_t c = *c2;
+                *c2 = run0 | (run1 << 16);
+                run0 += c & 0xFFFFu;
+                run1 += c >> 16;
             }
         }
         __syncthreads();
@@ -844,6 +868,11 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
                 if (lane == 0 && wm) atomicOr(&dmask[cur ^ 1u], wm);
             }
             // the next iteration reads segdim and dmask after its first barrier
+            if (!last) {
+                __syncthreads();
+                const uint32_t dm = dmask[cur ^ 1u];
+                if (dm & (dm - 1u)) pack_dims(cur ^ 1u);
+            }
         }
         cur ^= 1u;
     }
