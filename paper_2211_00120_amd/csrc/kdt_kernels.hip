@@ -301,22 +301,39 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_presort_pass(PresortArgs a)
     bool ok[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
-        ok[i] = j < cnt;
+        ok[i] = w * 64u * ITEMS + (uint32_t)i * 64u + lane < cnt;
         rec[i] = make_uint4(0u, 0u, 0u, 0u);
-        if (ok[i]) {
-            if (first) {
-                rec[i].x = kin[off + start + j];
-                // the local index, or for the other roles their root rank
-                rec[i].y = (role == 0u || !a.root_ranks) ? start + j : a.root_ranks[off + start + j];
-            } else {
+    }
+    // the two load forms as separate loops under the tile-uniform branch:
+    // chosen per item inside a per-lane branch, both forms' loads shared
+    // registers, and the waits between them kept one item's loads in
+    // flight at a time
+    if (first) {
+        // the key, and the local index or, for the other roles, the root rank
+        const bool by_index = role == 0u || !a.root_ranks;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+            if (ok[i]) rec[i].x = kin[off + start + j];
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+            if (ok[i]) rec[i].y = by_index ? start + j : a.root_ranks[off + start + j];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t j = w * 64u * ITEMS + (uint32_t)i * 64u + lane;
+            if (ok[i]) {
                 const uint2 kv = reinterpret_cast<const uint2*>(kvin)[off + start + j];
                 rec[i].x = kv.x;
                 rec[i].y = kv.y;
             }
         }
-        dig[i] = (rec[i].x >> shift) & 0xFFu;
     }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) dig[i] = (rec[i].x >> shift) & 0xFFu;
     const uint32_t n = ti.n;
     sweep_tile<RB, ITEMS, 2>(
         sm, rec, ok, dig, ITEMS, cnt, a.hist + (size_t)ti.idx * a.hist_stride + (dim * 4u + q) * RADIX, 0u,
