@@ -350,10 +350,18 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const u
                 hex += h[b];
             }
         }
+        // every item's staging position first (the counter reads need no
+        // guard: digits are in range), so the reads are in flight together
+        uint32_t spos[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t d = dig[i] & (NB - 1u);
+            spos[i] = sm.dstart[d] + sm.wh[w * NB + d] + (i < active ? rnk[i] : 0u);
+        }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if (i >= active) break;
-            if (ok[i]) stage_put(sm.stage[sm.dstart[dig[i]] + sm.wh[w * NB + dig[i]] + rnk[i]], rec[i]);
+            if (ok[i]) stage_put(sm.stage[spos[i]], rec[i]);
         }
         __syncthreads();
         for (uint32_t j = threadIdx.x; j < cnt; j += SWEEP_THREADS) {
@@ -380,8 +388,9 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const u
     uint32_t dst[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        dst[i] = 0xFFFFFFFFu;
-        if (i < active && ok[i]) dst[i] = sm.dstart[dig[i]] + sm.wh[w * NB + dig[i]] + rnk[i];
+        const uint32_t d = dig[i] & (NB - 1u);
+        const uint32_t at = sm.dstart[d] + sm.wh[w * NB + d] + (i < active ? rnk[i] : 0u);
+        dst[i] = (i < active && ok[i]) ? at : 0xFFFFFFFFu;
     }
     if (!STAGE) {
         // few digit values: each wave's stores of one item already form a
