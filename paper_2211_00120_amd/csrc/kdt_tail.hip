@@ -349,31 +349,41 @@ __device__ __forceinline__ uint32_t tail_bucket_sort_ranks(const uint4 (&rec)[IT
     for (int j = 0; j < ND; ++j)
         if (shift[j] <= 16u && red[3 * j + 2] <= TB_FILL) done |= 1u << dims[j];
     auto start_of = [&](int j, uint32_t b) { return (bcp[j * HB + (b >> 1)] >> (16u * (b & 1u))) & 0xFFFFu; };
-    // the keys' low 16 bits (relative to the minimum) by bucket
+    // the keys' low 16 bits (relative to the minimum) by bucket; each
+    // dimension's bucket starts are read for all items before any store
+    // (the stores might otherwise alias the next item's read and wait)
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
         if (!((done >> dims[j]) & 1u)) continue;
+        uint32_t at[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) at[i] = start_of(j, bucket(j, i) & (TB_BUCKETS - 1u));
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if (!ok[i]) continue;
             const uint32_t place = (pl[j][i / 2] >> (16 * (i & 1))) & 0xFFFFu;
-            tk[j * TAIL_CAP + start_of(j, bucket(j, i)) + place] = (uint16_t)(pick4(rec[i], dims[j]) - kmin[j]);
+            tk[j * TAIL_CAP + at[i] + place] = (uint16_t)(pick4(rec[i], dims[j]) - kmin[j]);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
         if (!((done >> dims[j]) & 1u)) continue;
+        uint32_t st[ITEMS], en[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t b = bucket(j, i) & (TB_BUCKETS - 1u);
+            st[i] = start_of(j, b);
+            en[i] = b + 1u < TB_BUCKETS ? start_of(j, b + 1u) : m;
+        }
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             if (!ok[i]) continue;
             const uint32_t e = w * CW + (uint32_t)i * 64u + lane;
-            const uint32_t b = bucket(j, i);
-            const uint32_t st = start_of(j, b), en = b + 1u < TB_BUCKETS ? start_of(j, b + 1u) : m;
             const uint32_t mine = (pick4(rec[i], dims[j]) - kmin[j]) & 0xFFFFu;
             uint32_t r = 0;
-            for (uint32_t x = st; x < en; ++x) r += (uint32_t)tk[j * TAIL_CAP + x] < mine ? 1u : 0u;
-            ord[dims[j]][st + r] = (uint16_t)e;
+            for (uint32_t x = st[i]; x < en[i]; ++x) r += (uint32_t)tk[j * TAIL_CAP + x] < mine ? 1u : 0u;
+            ord[dims[j]][st[i] + r] = (uint16_t)e;
         }
     }
     __syncthreads();
