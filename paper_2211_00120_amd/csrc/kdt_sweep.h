@@ -364,10 +364,24 @@ __device__ __forceinline__ void sweep_tile(SweepSmem<RB, RW, STAGE>& sm, const u
             if (ok[i]) stage_put(sm.stage[spos[i]], rec[i]);
         }
         __syncthreads();
-        for (uint32_t j = threadIdx.x; j < cnt; j += SWEEP_THREADS) {
-            const uint4 r = stage_get(sm.stage[j]);
-            const uint32_t d = digit_of(r);
-            store(j, sm.gbase[d] + j, r);
+        // four sorted positions per thread and round: their staged records
+        // and run bases are read before any of them is stored
+        constexpr uint32_t U = 4;
+        for (uint32_t j0 = threadIdx.x; j0 < cnt; j0 += U * SWEEP_THREADS) {
+            uint4 r[U];
+            uint32_t gbv[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t j = j0 + u * SWEEP_THREADS;
+                r[u] = j < cnt ? stage_get(sm.stage[j]) : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) gbv[u] = sm.gbase[digit_of(r[u]) & (NB - 1u)];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t j = j0 + u * SWEEP_THREADS;
+                if (j < cnt) store(j, gbv[u] + j, r[u]);
+            }
         }
         __syncthreads();
         return;
