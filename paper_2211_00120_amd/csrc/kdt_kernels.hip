@@ -530,44 +530,67 @@ __global__ void __launch_bounds__(BLOCK) k_level0(Level0Args a)
     const uint32_t cd0 = uniform(cdim[0]), cd1 = uniform(cdim[1]);
     const uint32_t start = (tile - st.tile0) * PREP_TILE;
     const uint32_t end = min(start + PREP_TILE, n);
-    for (uint32_t r = start + threadIdx.x; r < end; r += BLOCK) {
-        const uint32_t idx = perm_d0[r];
-        if (!in_bounds(idx, n, a.o.status)) continue;
-        if (r == piv) {
-            place<K, WIDEST>(a.o, ti, 0u, idx);
-            if (WIDEST && L >= 2)
-                widest_children<K, I32>(a.o, ti, 0u, 0u, plane_key<I32>(a.o, ti, idx, d0, K), d0, a.o.box[0],
-                                        L > 2 ? a.o.box[1] : nullptr);
-            continue;
-        }
-        if (L == 2) {                       // N = 2 or 3: children are leaves
-            place<K, WIDEST>(a.o, ti, r < piv ? 1u : 2u, idx);
-            continue;
+    // four points per thread and round, all their loads issued before the
+    // first point is processed
+    constexpr uint32_t U = 4;
+    for (uint32_t r0 = start + threadIdx.x; r0 < end; r0 += U * BLOCK) {
+        uint32_t idxv[U];
+        uint4 recv[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t r = r0 + u * BLOCK;
+            idxv[u] = r < end ? perm_d0[r] : 0xFFFFFFFFu;
+            recv[u] = make_uint4(0u, 0u, 0u, 0u);
         }
         // per-role arrays hold the ranks by root position (r's streams in);
         // the point-major table holds them by index (gathered)
-        uint4 rec = make_uint4(0u, 0u, 0u, 0u);
         if (a.role_ranks) {
 #pragma unroll
-            for (int d = 0; d < K; ++d)
-                if ((uint32_t)d != d0)
-                    set4(rec, (uint32_t)d, a.role_ranks[(size_t)dim_role((uint32_t)d, d0) * a.ntotal + off + r]);
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t r = r0 + u * BLOCK;
+                if (r >= end) continue;
+#pragma unroll
+                for (int d = 0; d < K; ++d)
+                    if ((uint32_t)d != d0)
+                        set4(recv[u], (uint32_t)d, a.role_ranks[(size_t)dim_role((uint32_t)d, d0) * a.ntotal + off + r]);
+            }
         } else {
-            rec = load_rec4<K>(a.rank_table, off + idx);
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (idxv[u] < n) recv[u] = load_rec4<K>(a.rank_table, off + idxv[u]);
         }
-        // the root dimension's rank is the position (every later segment
-        // keeps the root dimension's order), so its slot carries the index
-        set4(rec, d0, idx);
-        const uint32_t side = r > piv ? 1u : 0u;
-        store_rec4<K>(a.rout, off + r - side, rec);
-        if (acc) {
-            // no split key for a child split in the root's dimension: its
-            // pivot is found by position
-            const uint32_t cd = side ? cd1 : cd0;
-            if (cd != d0) {
-                const uint32_t kv = pick4(rec, cd);
-                a.kout[off + r - side] = kv;
-                atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t r = r0 + u * BLOCK;
+            if (r >= end) continue;
+            const uint32_t idx = idxv[u];
+            if (!in_bounds(idx, n, a.o.status)) continue;
+            if (r == piv) {
+                place<K, WIDEST>(a.o, ti, 0u, idx);
+                if (WIDEST && L >= 2)
+                    widest_children<K, I32>(a.o, ti, 0u, 0u, plane_key<I32>(a.o, ti, idx, d0, K), d0, a.o.box[0],
+                                            L > 2 ? a.o.box[1] : nullptr);
+                continue;
+            }
+            if (L == 2) {                       // N = 2 or 3: children are leaves
+                place<K, WIDEST>(a.o, ti, r < piv ? 1u : 2u, idx);
+                continue;
+            }
+            uint4 rec = recv[u];
+            // the root dimension's rank is the position (every later segment
+            // keeps the root dimension's order), so its slot carries the index
+            set4(rec, d0, idx);
+            const uint32_t side = r > piv ? 1u : 0u;
+            store_rec4<K>(a.rout, off + r - side, rec);
+            if (acc) {
+                // no split key for a child split in the root's dimension: its
+                // pivot is found by position
+                const uint32_t cd = side ? cd1 : cd0;
+                if (cd != d0) {
+                    const uint32_t kv = pick4(rec, cd);
+                    a.kout[off + r - side] = kv;
+                    atomicAdd(&nh[side * NB + ((kv >> top) & (NB - 1u))], 1u);
+                }
             }
         }
     }

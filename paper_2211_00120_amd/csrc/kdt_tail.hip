@@ -907,7 +907,22 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             seg[q] = (uint16_t)(idx[i] >> 16);
         }
         __syncthreads();
-        for (uint32_t p = threadIdx.x; p < m; p += TAIL_THREADS) {
+        // every thread's (at most C / TAIL_THREADS) nodes read from LDS
+        // before the first store
+        constexpr int R = (int)(C / TAIL_THREADS);
+        uint32_t cv[R][K], ix[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const uint32_t p = threadIdx.x + (uint32_t)u * TAIL_THREADS;
+            const uint32_t pp = p < m ? p : 0u;
+#pragma unroll
+            for (int d = 0; d < K; ++d) cv[u][d] = ub.stage[(uint32_t)d * C + pp];
+            ix[u] = (uint32_t)tmp[pp] | ((uint32_t)seg[pp] << 16);
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const uint32_t p = threadIdx.x + (uint32_t)u * TAIL_THREADS;
+            if (p >= m) continue;
             const uint32_t t = 31u - (uint32_t)__builtin_clz(p / gc + 1u);
             const uint32_t node = full_nodes(l0 + t) + (i0 << t) + (p - gc * ((1u << t) - 1u));
             if (!in_bounds(node, ti.n, o.status)) continue;
@@ -915,14 +930,13 @@ __global__ void __launch_bounds__(TAIL_THREADS, 4) k_tail(TailArgs a)
             if (o.tree) {
                 float* tp = o.tree + at * K;
                 if constexpr (K == 4)
-                    *reinterpret_cast<float4*>(tp) =
-                        make_float4(__uint_as_float(ub.stage[p]), __uint_as_float(ub.stage[C + p]),
-                                    __uint_as_float(ub.stage[2u * C + p]), __uint_as_float(ub.stage[3u * C + p]));
+                    *reinterpret_cast<float4*>(tp) = make_float4(__uint_as_float(cv[u][0]), __uint_as_float(cv[u][1]),
+                                                                 __uint_as_float(cv[u][2]), __uint_as_float(cv[u][3]));
                 else
 #pragma unroll
-                    for (int d = 0; d < K; ++d) tp[d] = __uint_as_float(ub.stage[(uint32_t)d * C + p]);
+                    for (int d = 0; d < K; ++d) tp[d] = __uint_as_float(cv[u][d]);
             }
-            o.nodeperm[at] = (uint32_t)tmp[p] | ((uint32_t)seg[p] << 16);
+            o.nodeperm[at] = ix[u];
             if (!WIDEST && o.dim) o.dim[at] = (uint8_t)((l0 + t) % (uint32_t)K);
         }
     }
