@@ -17,7 +17,7 @@
  *    by the O(1) closed form of Sec. 4 (the GPU path uses the closed form; the
  *    oracle must not).
  *
- *  - Build is the "usual" recursive list build the introduction describes:
+ *  - Build is the conventional recursive list build the introduction describes:
  *    sort the subtree's points along its split dimension, split at the
  *    balance position, recurse.  The balance position is the size of the left
  *    child's subtree (Observation 2.1): the point at that position of the
